@@ -1,0 +1,188 @@
+"""CPU oracle of the m-Cubes integrator -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product path (the HIP library and
+its Python binding) never imports or calls it.
+
+The arithmetic lives in ``mcubes_oracle.c`` (plain single-threaded FP64 C,
+built by ``oracle/build.py``); this module only marshals numpy arrays.
+Integrand family ids follow the order of eqs. 1-6 of the paper plus the
+addition integrand of §5.3.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+OSCILLATORY, PRODUCT_PEAK, CORNER_PEAK, GAUSSIAN, C0, DISCONTINUOUS, ADDITION = range(7)
+FAMILY_NAMES = ["oscillatory", "product_peak", "corner_peak", "gaussian", "c0",
+                "discontinuous", "addition"]
+
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def lib():
+    """Load liboracle.so (building it first if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        from . import build as _build
+        _build.build()
+    L = ctypes.CDLL(LIB_PATH)
+    L.mco_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+    L.mco_philox4x32_10.restype = None
+    L.mco_uniform.argtypes = [ctypes.c_uint32]
+    L.mco_uniform.restype = ctypes.c_double
+    L.mco_plan.argtypes = [ctypes.c_int, ctypes.c_int64, _i64p]
+    L.mco_plan.restype = ctypes.c_int
+    L.mco_integrand.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp]
+    L.mco_integrand.restype = ctypes.c_double
+    L.mco_map.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _ip]
+    L.mco_map.restype = ctypes.c_double
+    L.mco_sample_range.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int,
+                                   ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                   ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, _dp,
+                                   ctypes.c_int64, ctypes.c_int64, _dp, _dp]
+    L.mco_sample_range.restype = ctypes.c_int
+    L.mco_estimates.argtypes = [ctypes.c_int64, ctypes.c_int64, _dp, _dp]
+    L.mco_estimates.restype = None
+    L.mco_refine.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp]
+    L.mco_refine.restype = ctypes.c_int
+    L.mco_combine.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int, _dp]
+    L.mco_combine.restype = ctypes.c_int
+    L.mco_integrate.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int64, ctypes.c_int,
+                                ctypes.c_double, ctypes.c_uint64, ctypes.c_int, ctypes.c_double,
+                                ctypes.c_int, ctypes.c_int, _dp, _i64p, _dp, _dp, _dp]
+    L.mco_integrate.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+def philox4x32_10(counter, key):
+    """Philox4x32-10 of one 4-word counter under a 2-word key -> 4 uint32."""
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xffffffff for v in counter])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xffffffff for v in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().mco_philox4x32_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def uniform(r):
+    return lib().mco_uniform(int(r) & 0xffffffff)
+
+
+def plan(dim, ncall):
+    """(g, m, p, N) of the stratification rule; raises on invalid input."""
+    out = (ctypes.c_int64 * 4)()
+    if lib().mco_plan(int(dim), int(ncall), out) != 0:
+        raise ValueError(f"invalid plan arguments dim={dim} ncall={ncall}")
+    return tuple(int(v) for v in out)
+
+
+def integrand(family, params, x):
+    x, xp = _d(x)
+    params, pp = _d(params)
+    return lib().mco_integrand(int(family), len(x), pp, xp)
+
+
+def uniform_grid(dim, nb):
+    e = np.arange(nb + 1, dtype=np.float64) / float(nb)
+    return np.tile(e, (dim, 1))
+
+
+def map_point(grid, y):
+    """Map y through the grid -> (x, J, bins)."""
+    grid, gp = _d(grid)
+    dim, nbp1 = grid.shape
+    y, yp = _d(y)
+    x = np.zeros(dim)
+    bins = (ctypes.c_int * dim)()
+    J = lib().mco_map(dim, nbp1 - 1, gp, yp, x.ctypes.data_as(_dp), bins)
+    return x, J, np.array(list(bins), dtype=np.int64)
+
+
+def sample_range(family, params, dim, nb, g, m, p, seed, iteration, grid, c_begin, c_end,
+                 stream=0):
+    """Sums over cubes [c_begin, c_end): (sum S_c, sum var_c, bins[dim, nb])."""
+    grid, gp = _d(grid)
+    params, pp = _d(params if params is not None else np.zeros(2 * dim))
+    sums = np.zeros(2)
+    bins = np.zeros((dim, nb))
+    rc = lib().mco_sample_range(int(family), int(dim), pp, int(nb), int(g), int(m), int(p),
+                                int(seed), int(stream), int(iteration), gp, int(c_begin),
+                                int(c_end), sums.ctypes.data_as(_dp), bins.ctypes.data_as(_dp))
+    if rc != 0:
+        raise ValueError(f"mco_sample_range failed rc={rc}")
+    return float(sums[0]), float(sums[1]), bins
+
+
+def estimates(m, p, sum_s, sum_v):
+    s = np.array([sum_s, sum_v])
+    e = np.zeros(2)
+    lib().mco_estimates(int(m), int(p), s.ctypes.data_as(_dp), e.ctypes.data_as(_dp))
+    return float(e[0]), float(e[1])
+
+
+def iteration(family, params, dim, nb, ncall, seed, it, grid, stream=0):
+    """One full iteration -> (I_t, var_t, bins[dim, nb])."""
+    g, m, p, _ = plan(dim, ncall)
+    s, v, bins = sample_range(family, params, dim, nb, g, m, p, seed, it, grid, 0, m, stream)
+    I, var = estimates(m, p, s, v)
+    return I, var, bins
+
+
+def refine(grid, bins, alpha=1.5):
+    grid, gp = _d(grid)
+    bins, bp = _d(bins)
+    dim, nbp1 = grid.shape
+    out = np.zeros_like(grid)
+    rc = lib().mco_refine(dim, nbp1 - 1, float(alpha), gp, bp, out.ctypes.data_as(_dp))
+    if rc != 0:
+        raise ValueError("mco_refine failed")
+    return out
+
+
+def combine(I, var, skip=0):
+    """-> (Ibar, sigma, chi2_dof, dof)."""
+    I, ip = _d(I)
+    var, vp = _d(var)
+    out = np.zeros(3)
+    dof = lib().mco_combine(len(I), ip, vp, int(skip), out.ctypes.data_as(_dp))
+    return float(out[0]), float(out[1]), float(out[2]), int(dof)
+
+
+def integrate(family, params, dim, ncall, itmax, rel_tol, seed, nb=500, alpha=1.5,
+              adapt_iters=None, skip=0):
+    """Whole integrator -> dict with estimate, error, chi2_dof, trace and final grid."""
+    if adapt_iters is None:
+        adapt_iters = itmax
+    params, pp = _d(params if params is not None else np.zeros(2 * dim))
+    res = np.zeros(3)
+    info = np.zeros(7, dtype=np.int64)
+    grid = np.zeros((dim, nb + 1))
+    tI = np.zeros(itmax)
+    tV = np.zeros(itmax)
+    rc = lib().mco_integrate(int(family), int(dim), pp, int(ncall), int(itmax), float(rel_tol),
+                             int(seed), int(nb), float(alpha), int(adapt_iters), int(skip),
+                             res.ctypes.data_as(_dp), info.ctypes.data_as(_i64p),
+                             grid.ctypes.data_as(_dp), tI.ctypes.data_as(_dp),
+                             tV.ctypes.data_as(_dp))
+    n = int(info[0])
+    return {"rc": rc, "estimate": float(res[0]), "error": float(res[1]),
+            "chi2_dof": float(res[2]), "iterations": n, "dof": int(info[1]),
+            "g": int(info[2]), "m": int(info[3]), "p": int(info[4]), "n": int(info[5]),
+            "converged": bool(info[6]), "grid": grid, "trace_I": tI[:n], "trace_var": tV[:n]}

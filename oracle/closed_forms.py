@@ -1,0 +1,137 @@
+"""Exact integrals over the unit cube of the integrand families -- TEST INFRASTRUCTURE.
+
+The paper's benchmark integrands (eqs. 1-6, §5) and the addition integrand
+(§5.3) are special cases of the parameterised Genz families evaluated by the
+oracle.  Each integral factorises (or, for the corner peak, telescopes) and is
+derived here by calculus; every function is evaluated with mpmath at 50
+significant digits, or exactly with rational arithmetic where the closed form
+cancels badly in floating point.
+
+Families take params = [a_0..a_{d-1}, u_0..u_{d-1}] as in the oracle.
+"""
+from fractions import Fraction
+from itertools import combinations
+from math import factorial
+
+import mpmath as mp
+
+mp.mp.dps = 50
+
+
+def _split(params, dim):
+    a = [mp.mpf(float(v)) for v in params[:dim]]
+    u = [mp.mpf(float(v)) for v in params[dim:2 * dim]]
+    return a, u
+
+
+def oscillatory(params, dim):
+    """int cos(2 pi u_0 + sum a_i x_i) dx = Re[e^{2 pi i u_0} prod (e^{i a_j} - 1)/(i a_j)]."""
+    a, u = _split(params, dim)
+    z = mp.exp(mp.mpc(0, 1) * 2 * mp.pi * u[0])
+    for aj in a:
+        if aj == 0:
+            continue
+        z *= (mp.exp(mp.mpc(0, 1) * aj) - 1) / (mp.mpc(0, 1) * aj)
+    return mp.re(z)
+
+
+def product_peak(params, dim):
+    """int prod (a^-2 + (x-u)^2)^-1 dx = prod a [atan(a (1-u)) + atan(a u)]."""
+    a, u = _split(params, dim)
+    r = mp.mpf(1)
+    for aj, uj in zip(a, u):
+        r *= aj * (mp.atan(aj * (1 - uj)) + mp.atan(aj * uj))
+    return r
+
+
+def corner_peak_exact(params, dim):
+    """int (1 + sum a x)^-(d+1) dx = (1/(d! prod a)) sum_{S} (-1)^|S| / (1 + sum_{i in S} a_i).
+
+    Integrating one axis at a time lowers the exponent by one and turns every
+    term into a difference; the result is exact as a Fraction of the FP64
+    parameters.
+    """
+    a = [Fraction(float(v)) for v in params[:dim]]
+    total = Fraction(0)
+    for k in range(dim + 1):
+        for sub in combinations(range(dim), k):
+            total += Fraction((-1) ** k) / (1 + sum((a[i] for i in sub), Fraction(0)))
+    pa = Fraction(1)
+    for v in a:
+        pa *= v
+    return total / (factorial(dim) * pa)
+
+
+def corner_peak(params, dim):
+    f = corner_peak_exact(params, dim)
+    return mp.mpf(f.numerator) / mp.mpf(f.denominator)
+
+
+def gaussian(params, dim):
+    """int exp(-sum a^2 (x-u)^2) dx = prod sqrt(pi)/(2a) [erf(a(1-u)) + erf(a u)]."""
+    a, u = _split(params, dim)
+    r = mp.mpf(1)
+    for aj, uj in zip(a, u):
+        if aj == 0:
+            continue
+        r *= mp.sqrt(mp.pi) / (2 * aj) * (mp.erf(aj * (1 - uj)) + mp.erf(aj * uj))
+    return r
+
+
+def c0(params, dim):
+    """int exp(-sum a |x-u|) dx = prod (2 - e^{-a u} - e^{-a (1-u)}) / a."""
+    a, u = _split(params, dim)
+    r = mp.mpf(1)
+    for aj, uj in zip(a, u):
+        r *= (2 - mp.exp(-aj * uj) - mp.exp(-aj * (1 - uj))) / aj
+    return r
+
+
+def discontinuous(params, dim):
+    """int exp(sum a x) [x_i < u_i for all i] dx = prod (e^{a min(u,1)} - 1) / a."""
+    a, u = _split(params, dim)
+    r = mp.mpf(1)
+    for aj, uj in zip(a, u):
+        c = min(max(uj, mp.mpf(0)), mp.mpf(1))
+        r *= (mp.exp(aj * c) - 1) / aj if aj != 0 else c
+    return r
+
+
+def addition(params, dim):
+    """int sum x_i dx = d/2."""
+    return mp.mpf(dim) / 2
+
+
+BY_FAMILY = [oscillatory, product_peak, corner_peak, gaussian, c0, discontinuous, addition]
+
+
+def integral(family, params, dim):
+    """Exact integral (mpmath mpf) of family `family` with the given parameters."""
+    return BY_FAMILY[family](params, dim)
+
+
+def paper_params(k, dim):
+    """Parameters that turn the families into the paper's f_k (eqs. 1-6).
+
+    f1 = cos(sum i x_i)                       oscillatory, a_i = i, u_0 = 0
+    f2 = prod (1/50^2 + (x_i - 1/2)^2)^-1     product peak, a_i = 50, u_i = 1/2
+    f3 = (1 + sum i x_i)^-(d+1)               corner peak, a_i = i
+    f4 = exp(-625 sum (x_i - 1/2)^2)          Gaussian, a_i = 25, u_i = 1/2
+    f5 = exp(-10 sum |x_i - 1/2|)             C0, a_i = 10, u_i = 1/2
+    f6 = exp(sum (i+4) x_i) if x_i < (3+i)/10 discontinuous, a_i = i+4, u_i = (3+i)/10
+    (i counts axes from 1).  Returns (family id, params).
+    """
+    idx = range(1, dim + 1)
+    if k == 1:
+        return 0, [float(i) for i in idx] + [0.0] * dim
+    if k == 2:
+        return 1, [50.0] * dim + [0.5] * dim
+    if k == 3:
+        return 2, [float(i) for i in idx] + [0.0] * dim
+    if k == 4:
+        return 3, [25.0] * dim + [0.5] * dim
+    if k == 5:
+        return 4, [10.0] * dim + [0.5] * dim
+    if k == 6:
+        return 5, [float(i + 4) for i in idx] + [(3.0 + i) / 10.0 for i in idx]
+    raise ValueError(k)

@@ -1,0 +1,44 @@
+/*
+ * mcubes_oracle.h -- TEST INFRASTRUCTURE, not part of the product.
+ * Declarations of the plain CPU reference of the m-Cubes integrator
+ * (Alg. 2, §3.2 of the paper).  See mcubes_oracle.c for the definitions.
+ */
+#ifndef MCUBES_ORACLE_H
+#define MCUBES_ORACLE_H
+
+#include <stdint.h>
+
+#define MCO_MAX_DIM 10
+#define MCO_MAX_BINS 500
+
+enum {
+    MCO_OSCILLATORY = 0,
+    MCO_PRODUCT_PEAK = 1,
+    MCO_CORNER_PEAK = 2,
+    MCO_GAUSSIAN = 3,
+    MCO_C0 = 4,
+    MCO_DISCONTINUOUS = 5,
+    MCO_ADDITION = 6
+};
+
+void mco_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double mco_uniform(uint32_t r);
+int mco_plan(int dim, int64_t ncall, int64_t out[4]);
+double mco_integrand(int family, int dim, const double *params, const double *x);
+double mco_map(int dim, int nb, const double *grid, const double *y, double *x, int *bin);
+int mco_sample_range(int family, int dim, const double *params, int nb,
+                     int64_t g, int64_t m, int64_t p, uint64_t seed, uint32_t stream,
+                     uint32_t iteration, const double *grid,
+                     int64_t c_begin, int64_t c_end, double sums[2], double *bins);
+void mco_estimates(int64_t m, int64_t p, const double sums[2], double est[2]);
+int mco_iteration(int family, int dim, const double *params, int nb, int64_t ncall,
+                  uint64_t seed, uint32_t stream, uint32_t iteration, const double *grid,
+                  double est[2], double *bins);
+int mco_refine(int dim, int nb, double alpha, const double *grid, const double *bins, double *out);
+int mco_combine(int T, const double *I, const double *var, int skip, double out[3]);
+int mco_integrate(int family, int dim, const double *params, int64_t ncall, int itmax,
+                  double rel_tol, uint64_t seed, int nb, double alpha, int adapt_iters,
+                  int skip, double res[3], int64_t info[7], double *grid_out,
+                  double *trace_I, double *trace_var);
+
+#endif

@@ -1,0 +1,81 @@
+"""Seeded synthetic workloads shared by the tests, the smoke check and the benchmark.
+
+This module only draws integrand parameters and names problem sizes; it holds
+none of the integrator's arithmetic.  Parameters come from numpy's PCG64
+``default_rng(seed)``, so they are identical on every machine.
+
+Families (ids shared with the C interface): 0 oscillatory, 1 product peak,
+2 corner peak, 3 Gaussian, 4 C0, 5 discontinuous, 6 addition.  The paper's
+benchmark integrands (eqs. 1-6, §5) are members of the first six families.
+"""
+from dataclasses import dataclass, field
+from typing import List
+
+import numpy as np
+
+OSCILLATORY, PRODUCT_PEAK, CORNER_PEAK, GAUSSIAN, C0, DISCONTINUOUS, ADDITION = range(7)
+FAMILY_NAMES = ["oscillatory", "product_peak", "corner_peak", "gaussian", "c0",
+                "discontinuous", "addition"]
+
+
+@dataclass
+class Problem:
+    name: str
+    family: int
+    dim: int
+    params: List[float]
+    ncall: int
+    nbins: int = 500
+    itmax: int = 10
+    rel_tol: float = 0.0
+    seed: int = 0
+    extra: dict = field(default_factory=dict)
+
+
+def genz_params(rng, dim, a_lo, a_hi, u_lo, u_hi):
+    a = rng.uniform(a_lo, a_hi, size=dim)
+    u = rng.uniform(u_lo, u_hi, size=dim)
+    return [float(v) for v in a] + [float(v) for v in u]
+
+
+def small_product_peak():
+    """3-D product peak, a_i = 5, u_i ~ U(0.2, 0.8) (parameter seed 0), 100 bins,
+    1e5 samples per iteration, 10 iterations, Philox seed 0."""
+    rng = np.random.default_rng(0)
+    u = rng.uniform(0.2, 0.8, size=3)
+    params = [5.0] * 3 + [float(v) for v in u]
+    return Problem("product_peak_3d", PRODUCT_PEAK, 3, params, ncall=100_000, nbins=100,
+                   itmax=10, rel_tol=0.0, seed=0)
+
+
+# Parameter seeds of the three 8-D integrands of the large workload.
+LARGE_SEEDS = {GAUSSIAN: 1, OSCILLATORY: 2, CORNER_PEAK: 3}
+
+
+def large_8d(family, ncall=1 << 30, itmax=50, rel_tol=1e-4):
+    """8-D Genz integrand with a_i ~ U(5, 15), u_i ~ U(0, 1), 500 bins, 2^30
+    samples per iteration, up to 50 iterations, rel_tol 1e-4."""
+    rng = np.random.default_rng(LARGE_SEEDS[family])
+    params = genz_params(rng, 8, 5.0, 15.0, 0.0, 1.0)
+    return Problem(f"{FAMILY_NAMES[family]}_8d", family, 8, params, ncall=ncall, nbins=500,
+                   itmax=itmax, rel_tol=rel_tol, seed=0)
+
+
+def large_8d_set(ncall=1 << 30, itmax=50, rel_tol=1e-4):
+    return [large_8d(f, ncall, itmax, rel_tol) for f in (GAUSSIAN, OSCILLATORY, CORNER_PEAK)]
+
+
+def random_problem(rng, family, dim, ncall, nbins):
+    """A random member of a family with parameters in the ranges the paper's
+    integrands span (a in [5, 15] scaled down for the peaked families at high
+    dimension so that the integral stays representable)."""
+    if family == ADDITION:
+        params = [0.0] * (2 * dim)
+    elif family == DISCONTINUOUS:
+        params = genz_params(rng, dim, 1.0, 8.0, 0.3, 1.2)
+    elif family == CORNER_PEAK:
+        params = genz_params(rng, dim, 0.5, 5.0, 0.0, 1.0)
+    else:
+        params = genz_params(rng, dim, 2.0, 12.0, 0.0, 1.0)
+    return Problem(f"{FAMILY_NAMES[family]}_{dim}d", family, dim, params, ncall=ncall,
+                   nbins=nbins)
