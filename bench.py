@@ -1,0 +1,183 @@
+"""Benchmark of the MI355X m-Cubes path on the 8-D Genz workload.
+
+Workload: the 8-D Gaussian, oscillatory and corner-peak integrands with
+a_i ~ U(5, 15), u_i ~ U(0, 1) (parameter seeds 1, 2, 3), 500 bins per axis,
+2^30 samples requested per iteration (12^8 cubes x 2 samples = 859,963,392
+evaluations), FP64 throughout.  One step = one whole iteration (V-Sample,
+reduction, combination, refinement) of each of the three integrands, so a step
+evaluates 3 x 859,963,392 samples.  Inputs (grids, parameters) are resident on
+the GPU before the timed region starts.
+
+Prints one JSON line.  Besides throughput it reports, for the V-Sample kernel,
+the achieved FP64 rate against the vector peak (HIP events around every
+launch), a CPU baseline (the single-threaded oracle on a bounded sample) and
+the wall time to a 1e-3 relative error.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+
+
+def flops_per_sample(family, d, p):
+    """Algorithmic FP64 operations of one sample (FMA = 2, exp/cos/div = 1 each).
+
+    Per axis: uniform from the random word (fma: 2), stratum (add, mul: 2),
+    map (z mul, phi sub, width sub, x fma, Jacobian mul: 6), bin update (add: 1)
+    -> 11 d.  Per sample: Jacobian scale, weight, cube sum, shift, two shifted
+    sums (add; mul+add), w^2 -> 8.  Per cube, amortised over p: variance (4) and
+    the two thread sums (2) -> 6/p.  Plus the integrand.
+    """
+    f = {0: 2 * d + 1,          # fma per axis, cos
+         1: 4 * d + 1,          # sub, fma, mul per axis, one division
+         2: 3 * d + 1,          # fma per axis, d multiplications of the power, one division
+         3: 4 * d + 2,          # sub, mul, fma per axis, negation, exp
+         4: 3 * d + 2,          # sub, fma per axis (|.| free), negation, exp
+         5: 2 * d + 1,          # fma per axis, exp
+         6: d}[family]
+    return 11 * d + 8 + 6.0 / p + f
+
+
+def cpu_baseline(problems, ncall):
+    """The oracle, single-threaded, one iteration of each integrand at `ncall`."""
+    import oracle
+    total = 0
+    t0 = time.perf_counter()
+    for pr in problems:
+        grid = oracle.uniform_grid(pr.dim, pr.nbins)
+        oracle.iteration(pr.family, pr.params, pr.dim, pr.nbins, ncall, pr.seed, 0, grid)
+        total += oracle.plan(pr.dim, ncall)[3]
+    dt = time.perf_counter() - t0
+    return {"value": total / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": (f"one iteration of each of the three 8-D integrands at {ncall} samples "
+                       f"requested ({total} evaluated), 500 bins, uniform grid, "
+                       f"{dt:.1f} s single-threaded")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--ncall", type=int, default=1 << 30)
+    ap.add_argument("--cpu-ncall", type=int, default=1 << 25)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-ttt", action="store_true")
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--blocks", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout "
+              "(cube ranges per GPU, one all-reduce of sums and bins per iteration) is "
+              "described in the design notes but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2302_05730_amd as mc
+
+    torch.cuda.set_device(0)
+    problems = workloads.large_8d_set(ncall=args.ncall)
+    opts = mc.mcubes_default_options(nbins=500, block_size=args.block, blocks=args.blocks)
+    plans = [mc.mcubes_plan_create(pr.family, pr.params, pr.dim, pr.ncall, pr.seed, opts)
+             for pr in problems]
+    bufs = [mc.Buffers(pl) for pl in plans]
+    for pl, b in zip(plans, bufs):
+        mc.mcubes_init_grid(pl, b.grid[0])
+    n_eval = plans[0].info["samples_per_iter"]
+    p = plans[0].info["samples_per_cube"]
+    stream = torch.cuda.current_stream()
+    it = [0] * len(plans)
+
+    def step(events=None):
+        for k, (pl, b) in enumerate(zip(plans, bufs)):
+            t = it[k]
+            g_in, g_out = b.grid[t & 1], b.grid[(t + 1) & 1]
+            mc.mcubes_fill(b.bins, 0.0)
+            if events is not None:
+                events[k][0].record(stream)
+            mc.mcubes_vsample(pl, t, g_in, b.bins, b.partials)
+            if events is not None:
+                events[k][1].record(stream)
+            mc.mcubes_reduce(pl, b.partials, b.est)
+            mc.mcubes_combine(pl, t, b.est, b.state, 0.0)
+            mc.mcubes_refine(pl, g_in, b.bins, g_out)
+            it[k] = t + 1
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in plans]
+           for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(evs[s])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    vs_ms = [[evs[s][k][0].elapsed_time(evs[s][k][1]) for s in range(args.steps)]
+             for k in range(len(plans))]
+    for b in bufs:
+        st = b.state[:8].cpu().tolist()
+        if st[6] != 0.0:
+            raise RuntimeError("non-finite iteration estimate in the benchmark run")
+    value = len(plans) * n_eval * args.steps / elapsed
+
+    # dominant kernel: V-Sample; algorithmic FP64 flops per launch / mean launch time
+    per_family = {}
+    tot_flops, tot_ms = 0.0, 0.0
+    for pr, ms in zip(problems, vs_ms):
+        mean_ms = sum(ms) / len(ms)
+        fl = flops_per_sample(pr.family, pr.dim, p) * n_eval
+        per_family[workloads.FAMILY_NAMES[pr.family]] = {
+            "vsample_ms": round(mean_ms, 4), "evals_per_s": n_eval / (mean_ms * 1e-3),
+            "tflops": fl / (mean_ms * 1e-3) / 1e12}
+        tot_flops += fl
+        tot_ms += mean_ms
+    achieved = tot_flops / (tot_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
+                "traffic": None, "kernel": "vsample_kernel<family, 8>",
+                "per_family": per_family}
+
+    ttt = None
+    if not args.no_ttt:
+        ttt = {}
+        for pr in problems:
+            t_a = time.perf_counter()
+            r = mc.mcubes_integrate(pr.family, pr.params, pr.dim, pr.ncall, 50, 1e-3, pr.seed,
+                                    mc.mcubes_default_options(nbins=500))
+            t_b = time.perf_counter()
+            ttt[workloads.FAMILY_NAMES[pr.family]] = {
+                "seconds": round(t_b - t_a, 4), "iterations": r["iterations"],
+                "converged": r["converged"], "estimate": r["estimate"], "error": r["error"],
+                "rel_error": (r["error"] / abs(r["estimate"]) if r["estimate"] else None)}
+
+    cpu = None if args.no_cpu else cpu_baseline(problems, args.cpu_ncall)
+    out = {
+        "metric": "integrand evals/s + time to 1e-3 rel err, plain FP64 vs FP32/flow form",
+        "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": ("8-D Genz Gaussian + oscillatory + corner peak, a~U(5,15), "
+                                "u~U(0,1), 500 bins/axis, 2^30 samples/iter, one iteration "
+                                "of each per step"),
+                   "samples_per_iter": n_eval, "cubes": plans[0].info["ncubes"],
+                   "samples_per_cube": p, "block": plans[0].info["block_size"],
+                   "blocks": plans[0].info["blocks"], "parallelism": "single GPU"},
+        "roofline": roofline, "cpu_baseline": cpu, "time_to_1e-3": ttt,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

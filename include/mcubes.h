@@ -1,0 +1,195 @@
+/*
+ * mcubes.h -- C interface of the MI355X (gfx950) m-Cubes integrator.
+ *
+ * m-Cubes (§3.2 of "Porting numerical integration codes from CUDA to oneAPI:
+ * a case study", Sakiotis et al. 2023) is a VEGAS-style Monte Carlo
+ * integrator over (0,1)^d.  Each iteration runs the sampling kernel of Alg. 2
+ * ("V-Sample" here): the unit cube of y-space is split into m = g^d equal
+ * sub-cubes, p samples are drawn in every sub-cube, each sample is mapped to
+ * x through a separable step-function importance grid with nb bins per axis,
+ * the integrand is evaluated, per-cube means and variances are reduced into
+ * the iteration estimate (I_t, var_t), and every sample adds w^2 (w = f(x)
+ * times the map's Jacobian) to the bin it used on each axis.  The bin sums
+ * drive the refinement of the grid for the next iteration; the iteration
+ * estimates are combined by inverse-variance weighting.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: an mcubes_status.  Negative values are errors; the
+ *     outputs are then left untouched (for asynchronous entry points: no work
+ *     was enqueued).  mcubes_last_error() gives a message for the calling
+ *     thread's last error.
+ *   - Integrand parameters: params = [a_0..a_{d-1}, u_0..u_{d-1}] (host
+ *     memory, 2*dim doubles, copied at plan creation; may be NULL for
+ *     MCUBES_ADDITION).  All must be finite; MCUBES_PRODUCT_PEAK needs a_i != 0.
+ *   - Grid layout: dim rows of nbins+1 edges, row-major FP64;
+ *     E_j[0] = 0 < ... < E_j[nbins] = 1.  Bin layout: dim rows of nbins FP64.
+ *   - "d_" arguments are device pointers (HBM, e.g. torch tensors) owned by
+ *     the caller; "stream" is a hipStream_t passed as void* (NULL = the null
+ *     stream).  Device entry points only enqueue work and return.
+ *   - Random numbers: Philox4x32-10 keyed by the 64-bit seed, with counter
+ *     (cube id, stream id, sample * ceil(d/4) + block, iteration), so the
+ *     samples, and therefore the results, do not depend on launch geometry.
+ *   - Limits: 1 <= dim <= MCUBES_MAX_DIM, 2 <= nbins <= MCUBES_MAX_BINS,
+ *     ncall >= 2, number of cubes m < 2^32.
+ *   - Threading: a plan may be used from one host thread / one stream at a
+ *     time.  Calls on different plans are independent.
+ */
+#ifndef MCUBES_H
+#define MCUBES_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MCUBES_MAX_DIM 10
+#define MCUBES_MAX_BINS 500
+/* Combined-state buffer: 8 scalars followed by (I_t, var_t) per iteration. */
+#define MCUBES_STATE_HEADER 8
+#define MCUBES_MAX_ITERATIONS 1024
+#define MCUBES_STATE_LEN (MCUBES_STATE_HEADER + 2 * MCUBES_MAX_ITERATIONS)
+
+typedef enum {
+    MCUBES_OK = 0,
+    MCUBES_NOT_CONVERGED = 1, /* valid result; error > rel_tol * |estimate| after itmax */
+    MCUBES_E_ARG = -1,        /* invalid argument (message via mcubes_last_error) */
+    MCUBES_E_INTEGRAND = -2,  /* unknown integrand family or invalid parameters */
+    MCUBES_E_NONFINITE = -3,  /* an iteration estimate was NaN or infinite */
+    MCUBES_E_DEVICE = -4,     /* no usable gfx950 device or a HIP runtime error */
+    MCUBES_E_ALLOC = -5       /* host or device allocation failed */
+} mcubes_status;
+
+/* Integrand families (the paper's benchmark integrands of eqs. 1-6, §5, in
+ * the parameterised form, plus the addition integrand of §5.3):
+ *   OSCILLATORY    cos(2 pi u_0 + sum a_i x_i)                      eq. 1
+ *   PRODUCT_PEAK   prod (a_i^-2 + (x_i - u_i)^2)^-1                 eq. 2
+ *   CORNER_PEAK    (1 + sum a_i x_i)^-(d+1)                         eq. 3
+ *   GAUSSIAN       exp(-sum a_i^2 (x_i - u_i)^2)                    eq. 4
+ *   C0             exp(-sum a_i |x_i - u_i|)                        eq. 5
+ *   DISCONTINUOUS  exp(sum a_i x_i) if x_i < u_i for all i, else 0  eq. 6
+ *   ADDITION       sum x_i                                          §5.3   */
+typedef enum {
+    MCUBES_OSCILLATORY = 0,
+    MCUBES_PRODUCT_PEAK = 1,
+    MCUBES_CORNER_PEAK = 2,
+    MCUBES_GAUSSIAN = 3,
+    MCUBES_C0 = 4,
+    MCUBES_DISCONTINUOUS = 5,
+    MCUBES_ADDITION = 6
+} mcubes_family;
+
+typedef struct {
+    int32_t nbins;       /* bins per axis, 2..500; default 500 (Alg. 2 uses 500) */
+    int32_t adapt_iters; /* refine the grid after iterations t < adapt_iters; <0 = always (default) */
+    int32_t skip;        /* leading iterations left out of the combination; default 0 */
+    int32_t block_size;  /* V-Sample threads per block (64..1024, multiple of 64); 0 = library choice */
+    int32_t blocks;      /* V-Sample blocks; 0 = enough to fill every compute unit */
+    uint32_t stream_id;  /* second Philox counter word; default 0 */
+    double alpha;        /* refinement damping exponent; default 1.5 */
+    void *stream;        /* hipStream_t for mcubes_integrate; NULL = null stream */
+} mcubes_options;
+
+typedef struct {
+    double estimate;   /* combined integral estimate */
+    double error;      /* its standard deviation */
+    double chi2_dof;   /* chi^2 per degree of freedom of the combined iterations */
+    int32_t iterations; /* iterations run */
+    int32_t dof;       /* degrees of freedom (combined iterations - 1) */
+    int32_t converged; /* 1 if error <= rel_tol * |estimate| */
+    int32_t status;    /* same as the return value */
+    int64_t cube_side; /* g: cubes per axis */
+    int64_t ncubes;    /* m = g^dim */
+    int64_t samples_per_cube; /* p */
+    int64_t samples_per_iter; /* N = m p */
+    double kernel_ms;  /* total V-Sample kernel time (HIP events) */
+} mcubes_result;
+
+typedef struct mcubes_plan mcubes_plan;
+
+typedef struct {
+    int32_t family, dim, nbins, block_size, blocks;
+    int32_t lds_bytes;     /* dynamic LDS per V-Sample block */
+    int64_t cube_side, ncubes, samples_per_cube, samples_per_iter;
+    int64_t grid_len;      /* dim * (nbins + 1) */
+    int64_t bins_len;      /* dim * nbins */
+    int64_t partials_len;  /* 2 * blocks: per-block (sum S_c, sum var_c) */
+    int64_t state_len;     /* MCUBES_STATE_LEN */
+} mcubes_plan_info;
+
+/* Fill *opt with the defaults listed above. */
+void mcubes_default_options(mcubes_options *opt);
+
+/* Message describing the calling thread's last error ("" if none). */
+const char *mcubes_last_error(void);
+
+/* Stratification of §3.2 (a 2-point MC per sub-cube, about ncall samples):
+ * g = largest integer with g^dim <= floor(ncall/2), m = g^dim,
+ * p = max(2, floor(ncall/m)), N = m p.  out = [g, m, p, N].  Host only. */
+int mcubes_plan_sizes(int dim, int64_t ncall, int64_t out[4]);
+
+/* Whole integrator: uniform start grid, then per iteration t = 0..itmax-1
+ * V-Sample -> estimate -> combine -> refine (while t < adapt_iters), stopping
+ * after the first iteration whose combined error <= rel_tol * |estimate|.
+ * out (host) receives the result.  grid_out (host, dim*(nbins+1), may be
+ * NULL) receives the grid after the last refinement.  trace (host, 2*itmax
+ * doubles, may be NULL) receives (I_t, var_t) per iteration run.
+ * Allocates its device buffers itself and synchronises once per iteration.
+ * Returns MCUBES_OK, MCUBES_NOT_CONVERGED or an error. */
+int mcubes_integrate(int family, const double *params, int dim, int64_t ncall, int itmax,
+                     double rel_tol, uint64_t seed, const mcubes_options *opt,
+                     mcubes_result *out, double *grid_out, double *trace);
+
+/* Plan: validated problem, stratification and launch geometry for the device
+ * entry points below.  opt may be NULL (defaults).  Host memory only; the
+ * plan holds no device memory.  Free with mcubes_plan_destroy. */
+int mcubes_plan_create(int family, const double *params, int dim, int64_t ncall, uint64_t seed,
+                       const mcubes_options *opt, mcubes_plan **plan);
+int mcubes_plan_get_info(const mcubes_plan *plan, mcubes_plan_info *info);
+void mcubes_plan_destroy(mcubes_plan *plan);
+
+/* d_grid (grid_len) <- the uniform grid E_j[i] = i/nbins. */
+int mcubes_init_grid(const mcubes_plan *plan, double *d_grid, void *stream);
+
+/* d[0..n) <- value (a fill kernel, safe under graph capture). */
+int mcubes_fill(double *d, int64_t n, double value, void *stream);
+
+/* V-Sample (Alg. 2) for iteration `iteration` with grid d_grid:
+ *   d_bins[j*nbins + i] += sum of w^2 over the samples that used bin i on axis j;
+ *   d_partials[2b], d_partials[2b+1] <- block b's sum of cube sums S_c = sum_k w_ck
+ *   and of unbiased in-cube variances var_c.  Sizes from mcubes_plan_get_info. */
+int mcubes_vsample(const mcubes_plan *plan, uint32_t iteration, const double *d_grid,
+                   double *d_bins, double *d_partials, void *stream);
+
+/* Fixed-order reduction of the block partials: d_est[0] = I_t = sum S_c / N,
+ * d_est[1] = var_t = sum var_c / (p m^2). */
+int mcubes_reduce(const mcubes_plan *plan, const double *d_partials, double *d_est, void *stream);
+
+/* Records (I_t, var_t) = d_est as iteration `iteration` in d_state and
+ * recombines iterations skip..iteration (inverse-variance weighting):
+ *   d_state[0] = estimate, [1] = error, [2] = chi2/dof, [3] = dof,
+ *   [4] = iterations recorded, [5] = converged (error <= rel_tol |estimate|),
+ *   [6] = 1 if any recorded estimate was not finite,
+ *   [8 + 2t], [9 + 2t] = (I_t, var_t).
+ * iteration must be < MCUBES_MAX_ITERATIONS; d_state must hold MCUBES_STATE_LEN
+ * doubles and be zeroed before iteration 0. */
+int mcubes_combine(const mcubes_plan *plan, uint32_t iteration, const double *d_est,
+                   double *d_state, double rel_tol, void *stream);
+
+/* VEGAS rebinning of every axis from the bin sums: smooth, damp with alpha,
+ * re-divide into bins of equal damped weight.  d_grid_out may not alias
+ * d_grid. */
+int mcubes_refine(const mcubes_plan *plan, const double *d_grid, const double *d_bins,
+                  double *d_grid_out, void *stream);
+
+/* One whole iteration: zero d_bins, V-Sample, reduce, combine, then refine
+ * d_grid into d_grid_out (or copy it when iteration >= adapt_iters). */
+int mcubes_iteration(const mcubes_plan *plan, uint32_t iteration, const double *d_grid,
+                     double *d_grid_out, double *d_bins, double *d_partials, double *d_est,
+                     double *d_state, double rel_tol, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCUBES_H */

@@ -1,0 +1,282 @@
+"""Python binding of libmcubes, the MI355X (gfx950) m-Cubes integrator.
+
+Argument marshalling only: every entry point forwards to the C function of the
+same name declared in include/mcubes.h, and all arithmetic runs in the HIP
+kernels of the library.  Device buffers are PyTorch tensors (float64, on the
+GPU, contiguous) or raw device addresses; streams default to PyTorch's current
+stream.  There is no CPU fallback: if libmcubes.so is missing, importing
+anything that needs it raises.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmcubes.so")
+
+MCUBES_MAX_DIM = 10
+MCUBES_MAX_BINS = 500
+MCUBES_STATE_HEADER = 8
+MCUBES_MAX_ITERATIONS = 1024
+MCUBES_STATE_LEN = MCUBES_STATE_HEADER + 2 * MCUBES_MAX_ITERATIONS
+
+MCUBES_OK, MCUBES_NOT_CONVERGED = 0, 1
+MCUBES_E_ARG, MCUBES_E_INTEGRAND, MCUBES_E_NONFINITE, MCUBES_E_DEVICE, MCUBES_E_ALLOC = (
+    -1, -2, -3, -4, -5)
+(MCUBES_OSCILLATORY, MCUBES_PRODUCT_PEAK, MCUBES_CORNER_PEAK, MCUBES_GAUSSIAN, MCUBES_C0,
+ MCUBES_DISCONTINUOUS, MCUBES_ADDITION) = range(7)
+
+
+class MCubesError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__(f"mcubes error {code}: {message}")
+        self.code = code
+
+
+class mcubes_options(ctypes.Structure):
+    _fields_ = [("nbins", ctypes.c_int32), ("adapt_iters", ctypes.c_int32),
+                ("skip", ctypes.c_int32), ("block_size", ctypes.c_int32),
+                ("blocks", ctypes.c_int32), ("stream_id", ctypes.c_uint32),
+                ("alpha", ctypes.c_double), ("stream", ctypes.c_void_p)]
+
+
+class mcubes_result(ctypes.Structure):
+    _fields_ = [("estimate", ctypes.c_double), ("error", ctypes.c_double),
+                ("chi2_dof", ctypes.c_double), ("iterations", ctypes.c_int32),
+                ("dof", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("cube_side", ctypes.c_int64),
+                ("ncubes", ctypes.c_int64), ("samples_per_cube", ctypes.c_int64),
+                ("samples_per_iter", ctypes.c_int64), ("kernel_ms", ctypes.c_double)]
+
+
+class mcubes_plan_info(ctypes.Structure):
+    _fields_ = [("family", ctypes.c_int32), ("dim", ctypes.c_int32), ("nbins", ctypes.c_int32),
+                ("block_size", ctypes.c_int32), ("blocks", ctypes.c_int32),
+                ("lds_bytes", ctypes.c_int32), ("cube_side", ctypes.c_int64),
+                ("ncubes", ctypes.c_int64), ("samples_per_cube", ctypes.c_int64),
+                ("samples_per_iter", ctypes.c_int64), ("grid_len", ctypes.c_int64),
+                ("bins_len", ctypes.c_int64), ("partials_len", ctypes.c_int64),
+                ("state_len", ctypes.c_int64)]
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+_lib = None
+
+# name -> (restype, argtypes), mirroring include/mcubes.h
+_SIGNATURES = {
+    "mcubes_default_options": (None, [ctypes.POINTER(mcubes_options)]),
+    "mcubes_last_error": (ctypes.c_char_p, []),
+    "mcubes_plan_sizes": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64,
+                                         ctypes.POINTER(ctypes.c_int64)]),
+    "mcubes_integrate": (ctypes.c_int, [ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int64,
+                                        ctypes.c_int, ctypes.c_double, ctypes.c_uint64,
+                                        ctypes.POINTER(mcubes_options),
+                                        ctypes.POINTER(mcubes_result), _dp, _dp]),
+    "mcubes_plan_create": (ctypes.c_int, [ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int64,
+                                          ctypes.c_uint64, ctypes.POINTER(mcubes_options),
+                                          ctypes.POINTER(_vp)]),
+    "mcubes_plan_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(mcubes_plan_info)]),
+    "mcubes_plan_destroy": (None, [_vp]),
+    "mcubes_init_grid": (ctypes.c_int, [_vp, _vp, _vp]),
+    "mcubes_fill": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_double, _vp]),
+    "mcubes_vsample": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, _vp, _vp, _vp]),
+    "mcubes_reduce": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "mcubes_combine": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, _vp, ctypes.c_double, _vp]),
+    "mcubes_refine": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "mcubes_iteration": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp, _vp,
+                                        ctypes.c_double, _vp]),
+}
+
+
+def lib():
+    """The loaded libmcubes.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python paper_2302_05730_amd/build.py` (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def mcubes_last_error():
+    return lib().mcubes_last_error().decode()
+
+
+def _check(rc, allow=(MCUBES_OK,)):
+    if rc not in allow:
+        raise MCubesError(rc, mcubes_last_error())
+    return rc
+
+
+def _dev(t, n=None, name="buffer"):
+    """Device address of a float64 tensor (or a raw int address)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    import torch
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 GPU tensor")
+    if n is not None and t.numel() < n:
+        raise ValueError(f"{name} needs {n} elements, has {t.numel()}")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _params(params, dim):
+    if params is None:
+        return None, None
+    arr = (ctypes.c_double * (2 * dim))(*[float(v) for v in list(params)[:2 * dim]])
+    return arr, ctypes.cast(arr, _dp)
+
+
+def mcubes_default_options(**overrides):
+    opt = mcubes_options()
+    lib().mcubes_default_options(ctypes.byref(opt))
+    for k, v in overrides.items():
+        setattr(opt, k, v)
+    return opt
+
+
+def mcubes_plan_sizes(dim, ncall):
+    out = (ctypes.c_int64 * 4)()
+    _check(lib().mcubes_plan_sizes(int(dim), int(ncall), out))
+    return tuple(int(v) for v in out)
+
+
+def mcubes_integrate(family, params, dim, ncall, itmax, rel_tol, seed, options=None,
+                     grid=True, trace=True):
+    """Whole integrator.  Returns a dict with the mcubes_result fields plus the
+    final grid (list of dim rows) and the per-iteration (I_t, var_t) trace."""
+    keep, pp = _params(params, dim)
+    opt = options if options is not None else mcubes_default_options()
+    res = mcubes_result()
+    nb = opt.nbins
+    g_buf = (ctypes.c_double * (dim * (nb + 1)))() if grid else None
+    t_buf = (ctypes.c_double * (2 * itmax))() if trace else None
+    rc = lib().mcubes_integrate(int(family), pp, int(dim), int(ncall), int(itmax),
+                                float(rel_tol), int(seed) & (2**64 - 1), ctypes.byref(opt),
+                                ctypes.byref(res),
+                                ctypes.cast(g_buf, _dp) if grid else None,
+                                ctypes.cast(t_buf, _dp) if trace else None)
+    _check(rc, allow=(MCUBES_OK, MCUBES_NOT_CONVERGED))
+    out = {f: getattr(res, f) for f, _ in mcubes_result._fields_}
+    out["converged"] = bool(out["converged"])
+    n = res.iterations
+    if grid:
+        out["grid"] = [list(g_buf[j * (nb + 1):(j + 1) * (nb + 1)]) for j in range(dim)]
+    if trace:
+        out["trace_I"] = [t_buf[2 * t] for t in range(n)]
+        out["trace_var"] = [t_buf[2 * t + 1] for t in range(n)]
+    return out
+
+
+class Plan:
+    """Owns an mcubes_plan*; destroyed with the object."""
+
+    def __init__(self, handle):
+        self.handle = handle
+        self.info = mcubes_plan_get_info(self)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.mcubes_plan_destroy(self.handle)
+            self.handle = None
+
+
+def mcubes_plan_create(family, params, dim, ncall, seed, options=None):
+    keep, pp = _params(params, dim)
+    opt = options if options is not None else mcubes_default_options()
+    h = _vp()
+    _check(lib().mcubes_plan_create(int(family), pp, int(dim), int(ncall),
+                                    int(seed) & (2**64 - 1), ctypes.byref(opt), ctypes.byref(h)))
+    return Plan(h)
+
+
+def mcubes_plan_get_info(plan):
+    info = mcubes_plan_info()
+    _check(lib().mcubes_plan_get_info(plan.handle, ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in mcubes_plan_info._fields_}
+
+
+def mcubes_plan_destroy(plan):
+    if plan.handle:
+        lib().mcubes_plan_destroy(plan.handle)
+        plan.handle = None
+
+
+def mcubes_init_grid(plan, d_grid, stream=None):
+    _check(lib().mcubes_init_grid(plan.handle, _dev(d_grid, plan.info["grid_len"], "grid"),
+                                  _stream(stream)))
+
+
+def mcubes_fill(d, value, n=None, stream=None):
+    n = d.numel() if n is None else n
+    _check(lib().mcubes_fill(_dev(d, n), int(n), float(value), _stream(stream)))
+
+
+def mcubes_vsample(plan, iteration, d_grid, d_bins, d_partials, stream=None):
+    i = plan.info
+    _check(lib().mcubes_vsample(plan.handle, int(iteration), _dev(d_grid, i["grid_len"], "grid"),
+                                _dev(d_bins, i["bins_len"], "bins"),
+                                _dev(d_partials, i["partials_len"], "partials"),
+                                _stream(stream)))
+
+
+def mcubes_reduce(plan, d_partials, d_est, stream=None):
+    i = plan.info
+    _check(lib().mcubes_reduce(plan.handle, _dev(d_partials, i["partials_len"], "partials"),
+                               _dev(d_est, 2, "est"), _stream(stream)))
+
+
+def mcubes_combine(plan, iteration, d_est, d_state, rel_tol, stream=None):
+    _check(lib().mcubes_combine(plan.handle, int(iteration), _dev(d_est, 2, "est"),
+                                _dev(d_state, MCUBES_STATE_LEN, "state"), float(rel_tol),
+                                _stream(stream)))
+
+
+def mcubes_refine(plan, d_grid, d_bins, d_grid_out, stream=None):
+    i = plan.info
+    _check(lib().mcubes_refine(plan.handle, _dev(d_grid, i["grid_len"], "grid"),
+                               _dev(d_bins, i["bins_len"], "bins"),
+                               _dev(d_grid_out, i["grid_len"], "grid_out"), _stream(stream)))
+
+
+def mcubes_iteration(plan, iteration, d_grid, d_grid_out, d_bins, d_partials, d_est, d_state,
+                     rel_tol, stream=None):
+    i = plan.info
+    _check(lib().mcubes_iteration(plan.handle, int(iteration),
+                                  _dev(d_grid, i["grid_len"], "grid"),
+                                  _dev(d_grid_out, i["grid_len"], "grid_out"),
+                                  _dev(d_bins, i["bins_len"], "bins"),
+                                  _dev(d_partials, i["partials_len"], "partials"),
+                                  _dev(d_est, 2, "est"), _dev(d_state, MCUBES_STATE_LEN, "state"),
+                                  float(rel_tol), _stream(stream)))
+
+
+class Buffers:
+    """Device buffers (torch float64 tensors) sized for a plan's step API."""
+
+    def __init__(self, plan, device="cuda"):
+        import torch
+        i = plan.info
+        z = lambda n: torch.zeros(int(n), dtype=torch.float64, device=device)  # noqa: E731
+        self.grid = [z(i["grid_len"]), z(i["grid_len"])]
+        self.bins = z(i["bins_len"])
+        self.partials = z(i["partials_len"])
+        self.est = z(2)
+        self.state = z(MCUBES_STATE_LEN)

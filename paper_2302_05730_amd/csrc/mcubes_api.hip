@@ -1,0 +1,471 @@
+// Host runtime and C interface of libmcubes (declared in include/mcubes.h).
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "mcubes_internal.h"
+
+using namespace mcubes;
+
+struct mcubes_plan {
+    int family, dim, nb;
+    int block, blocks;
+    size_t lds;
+    int adapt_iters, skip;
+    double alpha;
+    int64_t g, m, p, n;
+    VsArgs args;
+    VsKernel kernel;
+};
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(MCUBES_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+const VsKernel *family_table(int family) {
+    switch (family) {
+    case MCUBES_OSCILLATORY: return kVsOscillatory();
+    case MCUBES_PRODUCT_PEAK: return kVsProductPeak();
+    case MCUBES_CORNER_PEAK: return kVsCornerPeak();
+    case MCUBES_GAUSSIAN: return kVsGaussian();
+    case MCUBES_C0: return kVsC0();
+    case MCUBES_DISCONTINUOUS: return kVsDiscontinuous();
+    case MCUBES_ADDITION: return kVsAddition();
+    default: return nullptr;
+    }
+}
+
+int64_t pow_capped(int64_t b, int e, int64_t cap) {
+    int64_t r = 1;
+    for (int i = 0; i < e; ++i) {
+        if (r > cap / b) return cap + 1;
+        r *= b;
+    }
+    return r;
+}
+
+int plan_sizes(int dim, int64_t ncall, int64_t out[4]) {
+    if (dim < 1 || dim > MCUBES_MAX_DIM)
+        return fail(MCUBES_E_ARG, "dim must be in [1, %d], got %d", MCUBES_MAX_DIM, dim);
+    if (ncall < 2) return fail(MCUBES_E_ARG, "ncall must be >= 2, got %lld", (long long)ncall);
+    const int64_t half = ncall / 2;
+    int64_t g = (int64_t)floor(pow((double)half, 1.0 / dim));
+    if (g < 1) g = 1;
+    while (g > 1 && pow_capped(g, dim, half) > half) --g;
+    while (pow_capped(g + 1, dim, half) <= half) ++g;
+    const int64_t m = pow_capped(g, dim, half);
+    int64_t p = ncall / m;
+    if (p < 2) p = 2;
+    out[0] = g;
+    out[1] = m;
+    out[2] = p;
+    out[3] = m * p;
+    return MCUBES_OK;
+}
+
+int64_t gcd64(int64_t a, int64_t b) {
+    while (b) {
+        const int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+int validate_params(int family, const double *params, int dim) {
+    if (family < 0 || family >= kFamilies)
+        return fail(MCUBES_E_INTEGRAND, "unknown integrand family %d", family);
+    if (family == MCUBES_ADDITION) return MCUBES_OK;
+    if (!params) return fail(MCUBES_E_INTEGRAND, "family %d needs 2*dim parameters", family);
+    for (int i = 0; i < 2 * dim; ++i)
+        if (!isfinite(params[i])) return fail(MCUBES_E_INTEGRAND, "parameter %d is not finite", i);
+    if (family == MCUBES_PRODUCT_PEAK)
+        for (int i = 0; i < dim; ++i)
+            if (params[i] == 0.0) return fail(MCUBES_E_INTEGRAND, "product peak needs a_%d != 0", i);
+    return MCUBES_OK;
+}
+
+// Fold the integrand parameters into the kernel's coefficients.
+void fold_params(int family, const double *params, int dim, VsArgs &A) {
+    for (int i = 0; i < kMaxDim; ++i) A.ca[i] = A.cu[i] = 0.0;
+    A.phase = 0.0;
+    if (family == MCUBES_ADDITION) return;
+    const double *a = params, *u = params + dim;
+    for (int i = 0; i < dim; ++i) {
+        switch (family) {
+        case MCUBES_PRODUCT_PEAK: A.ca[i] = 1.0 / (a[i] * a[i]); break;
+        case MCUBES_GAUSSIAN: A.ca[i] = a[i] * a[i]; break;
+        default: A.ca[i] = a[i]; break;
+        }
+        A.cu[i] = u[i];
+    }
+    if (family == MCUBES_OSCILLATORY) A.phase = (2.0 * M_PI) * u[0];
+}
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+void mcubes_default_options(mcubes_options *opt) {
+    if (!opt) return;
+    opt->nbins = 500;
+    opt->adapt_iters = -1;
+    opt->skip = 0;
+    opt->block_size = 0;
+    opt->blocks = 0;
+    opt->stream_id = 0;
+    opt->alpha = 1.5;
+    opt->stream = nullptr;
+}
+
+const char *mcubes_last_error(void) { return g_error.c_str(); }
+
+int mcubes_plan_sizes(int dim, int64_t ncall, int64_t out[4]) {
+    if (!out) return fail(MCUBES_E_ARG, "out is NULL");
+    int64_t tmp[4];
+    const int rc = plan_sizes(dim, ncall, tmp);
+    if (rc != MCUBES_OK) return rc;
+    memcpy(out, tmp, sizeof tmp);
+    return MCUBES_OK;
+}
+
+int mcubes_plan_create(int family, const double *params, int dim, int64_t ncall, uint64_t seed,
+                       const mcubes_options *opt_in, mcubes_plan **plan_out) {
+    if (!plan_out) return fail(MCUBES_E_ARG, "plan is NULL");
+    mcubes_options opt;
+    mcubes_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    int64_t sz[4];
+    int rc = plan_sizes(dim, ncall, sz);
+    if (rc != MCUBES_OK) return rc;
+    rc = validate_params(family, params, dim);
+    if (rc != MCUBES_OK) return rc;
+    if (opt.nbins < 2 || opt.nbins > MCUBES_MAX_BINS)
+        return fail(MCUBES_E_ARG, "nbins must be in [2, %d], got %d", MCUBES_MAX_BINS, opt.nbins);
+    if (!(opt.alpha >= 0.0) || !isfinite(opt.alpha))
+        return fail(MCUBES_E_ARG, "alpha must be finite and >= 0");
+    if (opt.skip < 0) return fail(MCUBES_E_ARG, "skip must be >= 0");
+    if (opt.block_size != 0 &&
+        (opt.block_size < 64 || opt.block_size > kMaxBlock || opt.block_size % 64 != 0))
+        return fail(MCUBES_E_ARG, "block_size must be 0 or a multiple of 64 in [64, %d]", kMaxBlock);
+    if (opt.blocks < 0) return fail(MCUBES_E_ARG, "blocks must be >= 0");
+    const int64_t g = sz[0], m = sz[1], p = sz[2];
+    const int nblk = (dim + 3) / 4;
+    if (m > 0xFFFFFFFFll) return fail(MCUBES_E_ARG, "too many cubes (%lld >= 2^32)", (long long)m);
+    if (p * nblk > 0xFFFFFFFFll) return fail(MCUBES_E_ARG, "too many samples per cube");
+
+    // device and launch geometry
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    int cus = 0, max_lds = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute(CUs)");
+    e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute(LDS)");
+
+    const VsKernel kern = family_table(family)[dim];
+    const int nb = opt.nbins;
+    const size_t lds = (size_t)(dim * (nb + 1) + dim * nb) * sizeof(double);
+    if (lds + 2 * (kMaxBlock / 64) * sizeof(double) > (size_t)max_lds)
+        return fail(MCUBES_E_ARG, "dim %d with %d bins needs %zu bytes of LDS, device has %d", dim,
+                    nb, lds, max_lds);
+    if (lds > 65536) {
+        e = hipFuncSetAttribute(kern.func, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
+    }
+    const int block = opt.block_size ? opt.block_size : 512;
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern.func, block, lds);
+    if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+    if (per_cu < 1) return fail(MCUBES_E_ARG, "V-Sample does not fit: block %d, LDS %zu", block, lds);
+    int64_t blocks = opt.blocks ? opt.blocks : (int64_t)per_cu * cus;
+    const int64_t needed = (m + block - 1) / block;
+    if (!opt.blocks && blocks > needed) blocks = needed;
+    if (blocks < 1) blocks = 1;
+    if (blocks * block > 0x7FFFFFFFll) return fail(MCUBES_E_ARG, "too many threads");
+
+    mcubes_plan *P = new (std::nothrow) mcubes_plan();
+    if (!P) return fail(MCUBES_E_ALLOC, "out of host memory");
+    P->family = family;
+    P->dim = dim;
+    P->nb = nb;
+    P->block = block;
+    P->blocks = (int)blocks;
+    P->lds = lds;
+    P->adapt_iters = opt.adapt_iters;
+    P->skip = opt.skip;
+    P->alpha = opt.alpha;
+    P->g = g;
+    P->m = m;
+    P->p = p;
+    P->n = sz[3];
+    P->kernel = kern;
+
+    VsArgs &A = P->args;
+    memset(&A, 0, sizeof A);
+    fold_params(family, params, dim, A);
+    A.inv_g = 1.0 / (double)g;
+    A.nb_d = (double)nb;
+    double nbd = (double)nb;
+    for (int j = 1; j < dim; ++j) nbd = nbd * (double)nb;
+    A.nbd = nbd;
+    A.inv_p = 1.0 / (double)p;
+    A.inv_pm1 = 1.0 / (double)(p - 1);
+    uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+    for (int r = 0; r < 10; ++r) {
+        A.round_key[2 * r] = k0;
+        A.round_key[2 * r + 1] = k1;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    A.stream_id = opt.stream_id;
+    A.iteration = 0;
+    A.g = (uint32_t)g;
+    A.m = (uint32_t)m;
+    A.p = (uint32_t)p;
+    A.nb = (uint32_t)nb;
+    // cube permutation multiplier: near m (sqrt(5)-1)/2, coprime to g (hence to m = g^d)
+    int64_t mult = (int64_t)floor((double)m * 0.6180339887498949);
+    if (mult < 1) mult = 1;
+    while (gcd64(mult, g) != 1) ++mult;
+    mult %= m;
+    if (m == 1) mult = 0;
+    A.mult = (uint32_t)mult;
+    const int64_t threads = blocks * block;
+    const int64_t step = (int64_t)(((unsigned __int128)threads * (uint64_t)mult) % (uint64_t)m);
+    A.step = (uint32_t)step;
+    int64_t rest = step;
+    for (int j = 0; j < kMaxDim; ++j) {
+        A.step_digit[j] = j < dim ? (uint32_t)(rest % g) : 0u;
+        if (j < dim) rest /= g;
+    }
+    *plan_out = P;
+    return MCUBES_OK;
+}
+
+int mcubes_plan_get_info(const mcubes_plan *P, mcubes_plan_info *info) {
+    if (!P || !info) return fail(MCUBES_E_ARG, "NULL argument");
+    info->family = P->family;
+    info->dim = P->dim;
+    info->nbins = P->nb;
+    info->block_size = P->block;
+    info->blocks = P->blocks;
+    info->lds_bytes = (int32_t)P->lds;
+    info->cube_side = P->g;
+    info->ncubes = P->m;
+    info->samples_per_cube = P->p;
+    info->samples_per_iter = P->n;
+    info->grid_len = (int64_t)P->dim * (P->nb + 1);
+    info->bins_len = (int64_t)P->dim * P->nb;
+    info->partials_len = 2 * (int64_t)P->blocks;
+    info->state_len = MCUBES_STATE_LEN;
+    return MCUBES_OK;
+}
+
+void mcubes_plan_destroy(mcubes_plan *P) { delete P; }
+
+int mcubes_init_grid(const mcubes_plan *P, double *d_grid, void *stream) {
+    if (!P || !d_grid) return fail(MCUBES_E_ARG, "NULL argument");
+    const hipError_t e = launch_init_grid(d_grid, P->dim, P->nb, as_stream(stream));
+    return e == hipSuccess ? MCUBES_OK : hip_fail(e, "init_grid launch");
+}
+
+int mcubes_fill(double *d, int64_t n, double value, void *stream) {
+    if (n < 0 || (n > 0 && !d)) return fail(MCUBES_E_ARG, "bad buffer");
+    const hipError_t e = launch_fill(d, n, value, as_stream(stream));
+    return e == hipSuccess ? MCUBES_OK : hip_fail(e, "fill launch");
+}
+
+int mcubes_vsample(const mcubes_plan *P, uint32_t iteration, const double *d_grid, double *d_bins,
+                   double *d_partials, void *stream) {
+    if (!P || !d_grid || !d_bins || !d_partials) return fail(MCUBES_E_ARG, "NULL argument");
+    VsArgs A = P->args;
+    A.iteration = iteration;
+    const hipError_t e = P->kernel.launch(A, d_grid, d_bins, d_partials, P->blocks, P->block, P->lds,
+                                          as_stream(stream));
+    return e == hipSuccess ? MCUBES_OK : hip_fail(e, "V-Sample launch");
+}
+
+int mcubes_reduce(const mcubes_plan *P, const double *d_partials, double *d_est, void *stream) {
+    if (!P || !d_partials || !d_est) return fail(MCUBES_E_ARG, "NULL argument");
+    const double n = (double)P->m * (double)P->p;
+    const double denom = (double)P->p * (double)P->m * (double)P->m;
+    const hipError_t e = launch_reduce(d_partials, P->blocks, n, denom, d_est, as_stream(stream));
+    return e == hipSuccess ? MCUBES_OK : hip_fail(e, "reduce launch");
+}
+
+int mcubes_combine(const mcubes_plan *P, uint32_t iteration, const double *d_est, double *d_state,
+                   double rel_tol, void *stream) {
+    if (!P || !d_est || !d_state) return fail(MCUBES_E_ARG, "NULL argument");
+    if (iteration >= MCUBES_MAX_ITERATIONS)
+        return fail(MCUBES_E_ARG, "iteration %u >= %d", iteration, MCUBES_MAX_ITERATIONS);
+    if (!(rel_tol >= 0.0) || !isfinite(rel_tol)) return fail(MCUBES_E_ARG, "rel_tol must be finite and >= 0");
+    const hipError_t e = launch_combine(d_est, d_state, iteration, P->skip, rel_tol, as_stream(stream));
+    return e == hipSuccess ? MCUBES_OK : hip_fail(e, "combine launch");
+}
+
+int mcubes_refine(const mcubes_plan *P, const double *d_grid, const double *d_bins,
+                  double *d_grid_out, void *stream) {
+    if (!P || !d_grid || !d_bins || !d_grid_out) return fail(MCUBES_E_ARG, "NULL argument");
+    if (d_grid == d_grid_out) return fail(MCUBES_E_ARG, "d_grid_out must not alias d_grid");
+    const hipError_t e =
+        launch_refine(d_grid, d_bins, d_grid_out, P->dim, P->nb, P->alpha, as_stream(stream));
+    return e == hipSuccess ? MCUBES_OK : hip_fail(e, "refine launch");
+}
+
+int mcubes_iteration(const mcubes_plan *P, uint32_t iteration, const double *d_grid,
+                     double *d_grid_out, double *d_bins, double *d_partials, double *d_est,
+                     double *d_state, double rel_tol, void *stream) {
+    if (!P || !d_grid || !d_grid_out || !d_bins || !d_partials || !d_est || !d_state)
+        return fail(MCUBES_E_ARG, "NULL argument");
+    if (d_grid == d_grid_out) return fail(MCUBES_E_ARG, "d_grid_out must not alias d_grid");
+    if (iteration >= MCUBES_MAX_ITERATIONS)
+        return fail(MCUBES_E_ARG, "iteration %u >= %d", iteration, MCUBES_MAX_ITERATIONS);
+    if (!(rel_tol >= 0.0) || !isfinite(rel_tol)) return fail(MCUBES_E_ARG, "rel_tol must be finite and >= 0");
+    hipStream_t s = as_stream(stream);
+    hipError_t e = launch_fill(d_bins, (int64_t)P->dim * P->nb, 0.0, s);
+    if (e != hipSuccess) return hip_fail(e, "fill launch");
+    int rc = mcubes_vsample(P, iteration, d_grid, d_bins, d_partials, stream);
+    if (rc != MCUBES_OK) return rc;
+    rc = mcubes_reduce(P, d_partials, d_est, stream);
+    if (rc != MCUBES_OK) return rc;
+    rc = mcubes_combine(P, iteration, d_est, d_state, rel_tol, stream);
+    if (rc != MCUBES_OK) return rc;
+    if (P->adapt_iters < 0 || (int64_t)iteration < P->adapt_iters)
+        return mcubes_refine(P, d_grid, d_bins, d_grid_out, stream);
+    e = launch_copy(d_grid, d_grid_out, (int64_t)P->dim * (P->nb + 1), s);
+    return e == hipSuccess ? MCUBES_OK : hip_fail(e, "copy launch");
+}
+
+int mcubes_integrate(int family, const double *params, int dim, int64_t ncall, int itmax,
+                     double rel_tol, uint64_t seed, const mcubes_options *opt_in,
+                     mcubes_result *out, double *grid_out, double *trace) {
+    if (!out) return fail(MCUBES_E_ARG, "out is NULL");
+    if (itmax < 1 || itmax > MCUBES_MAX_ITERATIONS)
+        return fail(MCUBES_E_ARG, "itmax must be in [1, %d]", MCUBES_MAX_ITERATIONS);
+    if (!(rel_tol >= 0.0) || !isfinite(rel_tol)) return fail(MCUBES_E_ARG, "rel_tol must be finite and >= 0");
+    mcubes_options opt;
+    mcubes_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    mcubes_plan *P = nullptr;
+    int rc = mcubes_plan_create(family, params, dim, ncall, seed, &opt, &P);
+    if (rc != MCUBES_OK) return rc;
+    hipStream_t s = as_stream(opt.stream);
+
+    const int64_t ng = (int64_t)P->dim * (P->nb + 1), nbn = (int64_t)P->dim * P->nb;
+    const int64_t total = 2 * ng + nbn + 2 * (int64_t)P->blocks + 2 + MCUBES_STATE_LEN;
+    double *buf = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double head[MCUBES_STATE_HEADER];
+    double kernel_ms = 0.0;
+    int done = 0;
+    hipError_t e = hipMalloc(&buf, (size_t)total * sizeof(double));
+    if (e != hipSuccess) {
+        mcubes_plan_destroy(P);
+        return fail(MCUBES_E_ALLOC, "hipMalloc: %s", hipGetErrorString(e));
+    }
+    double *grid[2] = {buf, buf + ng};
+    double *bins = buf + 2 * ng;
+    double *partials = bins + nbn;
+    double *est = partials + 2 * (int64_t)P->blocks;
+    double *state = est + 2;
+    memset(head, 0, sizeof head);
+
+#define MC_CHECK(expr, what)                 \
+    do {                                     \
+        e = (expr);                          \
+        if (e != hipSuccess) {               \
+            rc = hip_fail(e, what);          \
+            goto cleanup;                    \
+        }                                    \
+    } while (0)
+#define MC_CALL(expr)                        \
+    do {                                     \
+        rc = (expr);                         \
+        if (rc != MCUBES_OK) goto cleanup;   \
+    } while (0)
+
+    MC_CHECK(hipEventCreate(&ev0), "hipEventCreate");
+    MC_CHECK(hipEventCreate(&ev1), "hipEventCreate");
+    MC_CHECK(launch_init_grid(grid[0], P->dim, P->nb, s), "init_grid launch");
+    MC_CHECK(launch_fill(state, MCUBES_STATE_LEN, 0.0, s), "fill launch");
+    for (int t = 0; t < itmax; ++t) {
+        double *g_in = grid[t & 1], *g_out = grid[(t + 1) & 1];
+        MC_CHECK(launch_fill(bins, nbn, 0.0, s), "fill launch");
+        MC_CHECK(hipEventRecord(ev0, s), "hipEventRecord");
+        MC_CALL(mcubes_vsample(P, (uint32_t)t, g_in, bins, partials, opt.stream));
+        MC_CHECK(hipEventRecord(ev1, s), "hipEventRecord");
+        MC_CALL(mcubes_reduce(P, partials, est, opt.stream));
+        MC_CALL(mcubes_combine(P, (uint32_t)t, est, state, rel_tol, opt.stream));
+        if (P->adapt_iters < 0 || t < P->adapt_iters)
+            MC_CALL(mcubes_refine(P, g_in, bins, g_out, opt.stream));
+        else
+            MC_CHECK(launch_copy(g_in, g_out, ng, s), "copy launch");
+        MC_CHECK(hipMemcpyAsync(head, state, sizeof head, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+        MC_CHECK(hipStreamSynchronize(s), "hipStreamSynchronize");
+        float ms = 0.0f;
+        MC_CHECK(hipEventElapsedTime(&ms, ev0, ev1), "hipEventElapsedTime");
+        kernel_ms += ms;
+        done = t + 1;
+        if (head[6] != 0.0) {
+            rc = fail(MCUBES_E_NONFINITE, "iteration %d produced a non-finite estimate", t);
+            goto cleanup;
+        }
+        if (head[5] != 0.0) break;
+    }
+    if (trace) {
+        MC_CHECK(hipMemcpy(trace, state + MCUBES_STATE_HEADER, (size_t)(2 * done) * sizeof(double),
+                           hipMemcpyDeviceToHost),
+                 "hipMemcpy trace");
+    }
+    if (grid_out) {
+        MC_CHECK(hipMemcpy(grid_out, grid[done & 1], (size_t)ng * sizeof(double),
+                           hipMemcpyDeviceToHost),
+                 "hipMemcpy grid");
+    }
+    out->estimate = head[0];
+    out->error = head[1];
+    out->chi2_dof = head[2];
+    out->dof = (int32_t)head[3];
+    out->iterations = done;
+    out->converged = head[5] != 0.0;
+    out->cube_side = P->g;
+    out->ncubes = P->m;
+    out->samples_per_cube = P->p;
+    out->samples_per_iter = P->n;
+    out->kernel_ms = kernel_ms;
+    rc = out->converged ? MCUBES_OK : MCUBES_NOT_CONVERGED;
+    out->status = rc;
+
+cleanup:
+#undef MC_CHECK
+#undef MC_CALL
+    if (ev0) hipEventDestroy(ev0);
+    if (ev1) hipEventDestroy(ev1);
+    hipFree(buf);
+    mcubes_plan_destroy(P);
+    return rc;
+}
+
+}  // extern "C"

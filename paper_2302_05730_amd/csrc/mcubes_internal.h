@@ -1,0 +1,71 @@
+// Internal declarations shared by the HIP sources of libmcubes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mcubes.h"
+
+namespace mcubes {
+
+constexpr int kMaxDim = MCUBES_MAX_DIM;
+constexpr int kMaxBins = MCUBES_MAX_BINS;
+constexpr int kFamilies = 7;
+constexpr int kMaxBlock = 1024;
+
+// Uniform arguments of one V-Sample launch (kernel-argument segment, read
+// through scalar loads).  Integrand coefficients are pre-folded per family:
+//   oscillatory    ca = a,        phase = 2 pi u_0
+//   product peak   ca = 1/(a a),  cu = u
+//   corner peak    ca = a
+//   Gaussian       ca = a a,      cu = u
+//   C0             ca = a,        cu = u
+//   discontinuous  ca = a,        cu = u
+struct VsArgs {
+    double ca[kMaxDim];
+    double cu[kMaxDim];
+    double phase;
+    double inv_g;       // fl(1/g)
+    double nb_d;        // nb as double
+    double nbd;         // fl(nb^d) by repeated multiplication
+    double inv_p;       // fl(1/p)
+    double inv_pm1;     // fl(1/(p-1))
+    uint32_t round_key[20];  // Philox round keys (k0, k1) of rounds 0..9
+    uint32_t stream_id;
+    uint32_t iteration;
+    uint32_t g, m, p, nb;
+    uint32_t mult;            // cube permutation: work item w -> cube (w * mult) mod m
+    uint32_t step;            // (threads * mult) mod m
+    uint32_t step_digit[kMaxDim];  // base-g digits of step
+};
+
+typedef hipError_t (*VsLaunchFn)(const VsArgs &args, const double *grid, double *bins,
+                                 double *partials, int blocks, int block, size_t lds,
+                                 hipStream_t stream);
+
+struct VsKernel {
+    VsLaunchFn launch;
+    const void *func;  // kernel symbol, for occupancy queries and attributes
+};
+
+// Per-family tables, index = dim (1..kMaxDim); defined in vsample_f<family>.hip.
+const VsKernel *kVsOscillatory();
+const VsKernel *kVsProductPeak();
+const VsKernel *kVsCornerPeak();
+const VsKernel *kVsGaussian();
+const VsKernel *kVsC0();
+const VsKernel *kVsDiscontinuous();
+const VsKernel *kVsAddition();
+
+// Small kernels (support.hip).
+hipError_t launch_fill(double *d, int64_t n, double value, hipStream_t stream);
+hipError_t launch_init_grid(double *grid, int dim, int nb, hipStream_t stream);
+hipError_t launch_reduce(const double *partials, int nparts, double n_samples, double var_denom,
+                         double *est, hipStream_t stream);
+hipError_t launch_combine(const double *est, double *state, uint32_t iteration, int skip,
+                          double rel_tol, hipStream_t stream);
+hipError_t launch_refine(const double *grid, const double *bins, double *grid_out, int dim, int nb,
+                         double alpha, hipStream_t stream);
+hipError_t launch_copy(const double *src, double *dst, int64_t n, hipStream_t stream);
+
+}  // namespace mcubes

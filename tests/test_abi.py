@@ -1,0 +1,124 @@
+"""The C interface: libmcubes.so loads, exports every function declared in
+include/mcubes.h, the Python binding's structs match the C layout, and the
+host-side logic (plan sizes, argument validation) behaves -- no GPU needed,
+no kernel is launched."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import oracle
+import paper_2302_05730_amd as mc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mcubes.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mcubes_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert len(names) >= 14
+    L = mc.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", mc.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (mcubes_\w+)", out))
+    assert set(names) <= exported
+    assert set(names) == set(mc._SIGNATURES)
+
+
+_LAYOUT = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "mcubes.h"
+#define F(T, m) printf(#T " " #m " %zu\n", offsetof(T, m));
+int main(void) {
+    printf("mcubes_options size %zu\n", sizeof(mcubes_options));
+    F(mcubes_options, nbins) F(mcubes_options, alpha) F(mcubes_options, stream)
+    F(mcubes_options, stream_id)
+    printf("mcubes_result size %zu\n", sizeof(mcubes_result));
+    F(mcubes_result, chi2_dof) F(mcubes_result, status) F(mcubes_result, cube_side)
+    F(mcubes_result, kernel_ms)
+    printf("mcubes_plan_info size %zu\n", sizeof(mcubes_plan_info));
+    F(mcubes_plan_info, lds_bytes) F(mcubes_plan_info, cube_side) F(mcubes_plan_info, state_len)
+    printf("MCUBES_STATE_LEN x %d\n", MCUBES_STATE_LEN);
+    return 0;
+}
+"""
+
+
+def test_struct_layouts_match_binding(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(_LAYOUT)
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", f"-I{os.path.join(ROOT, 'include')}", str(src), "-o",
+                    str(exe)], check=True)
+    lines = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    for line in filter(None, lines):
+        tname, field, val = line.split()
+        if tname == "MCUBES_STATE_LEN":
+            assert int(val) == mc.MCUBES_STATE_LEN
+            continue
+        T = getattr(mc, tname)
+        if field == "size":
+            assert ctypes.sizeof(T) == int(val), tname
+        else:
+            assert getattr(T, field).offset == int(val), (tname, field)
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3, 5, 8, 10])
+@pytest.mark.parametrize("ncall", [2, 7, 1000, 100_000, 2**26, 2**30, 5 * 10**9])
+def test_plan_sizes_match_oracle(dim, ncall):
+    assert mc.mcubes_plan_sizes(dim, ncall) == oracle.plan(dim, ncall)
+
+
+def _create(family=3, params=None, dim=2, ncall=1000, **opt):
+    if params is None:
+        params = [1.0] * (2 * dim)
+    return mc.mcubes_plan_create(family, params, dim, ncall, 0, mc.mcubes_default_options(**opt))
+
+
+@pytest.mark.parametrize("kwargs,code", [
+    (dict(dim=0), mc.MCUBES_E_ARG),
+    (dict(dim=11), mc.MCUBES_E_ARG),
+    (dict(ncall=1), mc.MCUBES_E_ARG),
+    (dict(family=7), mc.MCUBES_E_INTEGRAND),
+    (dict(family=-1), mc.MCUBES_E_INTEGRAND),
+    (dict(params=[float("nan"), 1.0, 1.0, 1.0]), mc.MCUBES_E_INTEGRAND),
+    (dict(params=[1.0, float("inf"), 1.0, 1.0]), mc.MCUBES_E_INTEGRAND),
+    (dict(family=1, params=[0.0, 1.0, 0.5, 0.5]), mc.MCUBES_E_INTEGRAND),
+    (dict(nbins=1), mc.MCUBES_E_ARG),
+    (dict(nbins=501), mc.MCUBES_E_ARG),
+    (dict(alpha=float("nan")), mc.MCUBES_E_ARG),
+    (dict(skip=-1), mc.MCUBES_E_ARG),
+    (dict(block_size=100), mc.MCUBES_E_ARG),
+    (dict(block_size=2048), mc.MCUBES_E_ARG),
+    (dict(dim=1, ncall=2 * 2**32 + 4), mc.MCUBES_E_ARG),  # m >= 2^32 cubes
+])
+def test_plan_create_rejects(kwargs, code):
+    with pytest.raises(mc.MCubesError) as ei:
+        _create(**kwargs)
+    assert ei.value.code == code
+    assert mc.mcubes_last_error()
+
+
+def test_integrate_rejects_bad_arguments():
+    for itmax, tol in ((0, 0.1), (2000, 0.1), (3, float("nan")), (3, -1.0)):
+        with pytest.raises(mc.MCubesError) as ei:
+            mc.mcubes_integrate(3, [1.0, 0.5], 1, 1000, itmax, tol, 0)
+        assert ei.value.code == mc.MCUBES_E_ARG
+
+
+def test_default_options():
+    o = mc.mcubes_default_options()
+    assert (o.nbins, o.adapt_iters, o.skip, o.block_size, o.blocks, o.alpha) == \
+        (500, -1, 0, 0, 0, 1.5)
+    assert not o.stream

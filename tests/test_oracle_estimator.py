@@ -153,8 +153,9 @@ def test_coverage_over_seeds():
 
 def test_stop_rule():
     params = [4.0, 7.0, 0.35, 0.6]
-    r = oracle.integrate(1, params, 2, 20000, 50, 1e-3, 0, nb=50)
-    assert r["converged"] and r["iterations"] < 50
-    assert r["error"] <= 1e-3 * abs(r["estimate"])
-    r2 = oracle.integrate(1, params, 2, 20000, r["iterations"] - 1, 1e-3, 0, nb=50)
-    assert not r2["converged"]
+    r = oracle.integrate(1, params, 2, 20000, 50, 3e-5, 0, nb=50)
+    assert r["converged"] and 3 <= r["iterations"] < 50
+    assert r["error"] <= 3e-5 * abs(r["estimate"])
+    r2 = oracle.integrate(1, params, 2, 20000, r["iterations"] - 1, 3e-5, 0, nb=50)
+    assert not r2["converged"] and r2["iterations"] == r["iterations"] - 1
+    assert r2["error"] > 3e-5 * abs(r2["estimate"])
