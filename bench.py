@@ -74,6 +74,9 @@ def main():
     ap.add_argument("--no-ttt", action="store_true")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--blocks", type=int, default=0)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="before the steps, run one plain device copy of this many MiB "
+                         "(reference point for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout "
@@ -85,6 +88,13 @@ def main():
     import paper_2302_05730_amd as mc
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy_mib:
+        n = args.calibrate_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     problems = workloads.large_8d_set(ncall=args.ncall)
     opts = mc.mcubes_default_options(nbins=500, block_size=args.block, blocks=args.blocks)
     plans = [mc.mcubes_plan_create(pr.family, pr.params, pr.dim, pr.ncall, pr.seed, opts)

@@ -104,14 +104,14 @@ def uniform_grid(dim, nb):
     return np.tile(e, (dim, 1))
 
 
-def map_point(grid, y):
-    """Map y through the grid -> (x, J, bins)."""
+def map_point(grid, z):
+    """Map a point given in bin units (z = y * nb) through the grid -> (x, J, bins)."""
     grid, gp = _d(grid)
     dim, nbp1 = grid.shape
-    y, yp = _d(y)
+    z, zp = _d(z)
     x = np.zeros(dim)
     bins = (ctypes.c_int * dim)()
-    J = lib().mco_map(dim, nbp1 - 1, gp, yp, x.ctypes.data_as(_dp), bins)
+    J = lib().mco_map(dim, nbp1 - 1, gp, zp, x.ctypes.data_as(_dp), bins)
     return x, J, np.array(list(bins), dtype=np.int64)
 
 

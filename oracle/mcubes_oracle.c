@@ -176,22 +176,22 @@ double mco_integrand(int family, int dim, const double *params, const double *x)
 /* ------------------------------------------------------------------------ */
 /* The separable importance map (§3.2: a step-wise density approximating the */
 /* integrand).  Axis j has nb bins with edges E_j[0]=0 < ... < E_j[nb]=1;    */
-/* each bin holds probability 1/nb.  A point y in (0,1)^d is mapped bin-wise */
-/* linearly: z = y nb, i = floor(z) (clamped to nb-1), x = E_i + W_i (z - i), */
-/* W_i = E_{i+1} - E_i; the Jacobian is prod_j nb W_{i_j}, evaluated as      */
-/* fl(nb^d) * (W_{i_0} W_{i_1} ...), nb^d by repeated multiplication.        */
+/* each bin holds probability 1/nb.  A point is given by its position in    */
+/* bin units z = y nb (y in (0,1)^d) and mapped bin-wise linearly:          */
+/* i = floor(z) (clamped to nb-1), x = E_i + W_i (z - i), W_i = E_{i+1} -   */
+/* E_i; the Jacobian is prod_j nb W_{i_j}, evaluated as fl(nb^d) * (W_{i_0} */
+/* W_{i_1} ...), nb^d by repeated multiplication.                           */
 /* ------------------------------------------------------------------------ */
-double mco_map(int dim, int nb, const double *grid, const double *y, double *x, int *bin)
+double mco_map(int dim, int nb, const double *grid, const double *z, double *x, int *bin)
 {
     double nbd = (double)nb;
     for (int j = 1; j < dim; ++j) nbd = nbd * (double)nb;
     double prod = 1.0;
     for (int j = 0; j < dim; ++j) {
         const double *E = grid + (size_t)j * (size_t)(nb + 1);
-        double z = y[j] * (double)nb;
-        int i = (int)z;
+        int i = (int)z[j];
         if (i > nb - 1) i = nb - 1;
-        double phi = z - (double)i;
+        double phi = z[j] - (double)i;
         double W = E[i + 1] - E[i];
         x[j] = fma(W, phi, E[i]);
         prod = prod * W;
@@ -219,7 +219,8 @@ static void neumaier_add(double *sum, double *comp, double v)
 /*   sums[1] = sum over those cubes of the unbiased in-cube variance of w    */
 /*   bins[j*nb + i] = sum of w^2 over the samples that used bin i on axis j  */
 /* Cube c has base-g digits c_j = floor(c / g^j) mod g; sample k of cube c   */
-/* draws y_j = (c_j + u_j) / g, evaluated as (c_j + u_j) * fl(1/g).          */
+/* draws y_j = (c_j + u_j) / g, i.e. z_j = y_j nb = (c_j + u_j) nb / g in     */
+/* bin units, evaluated as (c_j + u_j) * fl(nb / g) (c_j + u_j is exact).    */
 /* ------------------------------------------------------------------------ */
 int mco_sample_range(int family, int dim, const double *params, int nb,
                      int64_t g, int64_t m, int64_t p, uint64_t seed, uint32_t stream,
@@ -230,7 +231,7 @@ int mco_sample_range(int family, int dim, const double *params, int nb,
     if (c_begin < 0 || c_end > m || c_begin > c_end || p < 2) return -1;
     const int nblk = (dim + 3) / 4;
     const uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
-    const double inv_g = 1.0 / (double)g;
+    const double nb_over_g = (double)nb / (double)g;
 
     double *bin_comp = (double *)calloc((size_t)dim * (size_t)nb, sizeof(double));
     if (!bin_comp) return -2;
@@ -251,10 +252,10 @@ int mco_sample_range(int family, int dim, const double *params, int nb,
                 uint32_t ctr[4] = {(uint32_t)c, stream, (uint32_t)(k * nblk + b), iteration};
                 mco_philox4x32_10(ctr, key, r + 4 * b);
             }
-            double y[MCO_MAX_DIM], x[MCO_MAX_DIM];
+            double z[MCO_MAX_DIM], x[MCO_MAX_DIM];
             int bin[MCO_MAX_DIM];
-            for (int j = 0; j < dim; ++j) y[j] = ((double)digit[j] + mco_uniform(r[j])) * inv_g;
-            double J = mco_map(dim, nb, grid, y, x, bin);
+            for (int j = 0; j < dim; ++j) z[j] = ((double)digit[j] + mco_uniform(r[j])) * nb_over_g;
+            double J = mco_map(dim, nb, grid, z, x, bin);
             double f = mco_integrand(family, dim, params, x);
             double w = f * J;
             S = S + w;

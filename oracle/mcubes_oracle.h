@@ -25,7 +25,7 @@ void mco_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 double mco_uniform(uint32_t r);
 int mco_plan(int dim, int64_t ncall, int64_t out[4]);
 double mco_integrand(int family, int dim, const double *params, const double *x);
-double mco_map(int dim, int nb, const double *grid, const double *y, double *x, int *bin);
+double mco_map(int dim, int nb, const double *grid, const double *z, double *x, int *bin);
 int mco_sample_range(int family, int dim, const double *params, int nb,
                      int64_t g, int64_t m, int64_t p, uint64_t seed, uint32_t stream,
                      uint32_t iteration, const double *grid,

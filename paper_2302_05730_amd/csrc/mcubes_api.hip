@@ -186,7 +186,8 @@ int mcubes_plan_create(int family, const double *params, int dim, int64_t ncall,
 
     const VsKernel kern = family_table(family)[dim];
     const int nb = opt.nbins;
-    const size_t lds = (size_t)(dim * (nb + 1) + dim * nb) * sizeof(double);
+    // (edge, width) pairs and bin sums of every axis
+    const size_t lds = (size_t)(3 * dim * nb) * sizeof(double);
     if (lds + 2 * (kMaxBlock / 64) * sizeof(double) > (size_t)max_lds)
         return fail(MCUBES_E_ARG, "dim %d with %d bins needs %zu bytes of LDS, device has %d", dim,
                     nb, lds, max_lds);
@@ -194,7 +195,7 @@ int mcubes_plan_create(int family, const double *params, int dim, int64_t ncall,
         e = hipFuncSetAttribute(kern.func, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
     }
-    const int block = opt.block_size ? opt.block_size : 512;
+    const int block = opt.block_size ? opt.block_size : 1024;
     int per_cu = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern.func, block, lds);
     if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
@@ -225,20 +226,14 @@ int mcubes_plan_create(int family, const double *params, int dim, int64_t ncall,
     VsArgs &A = P->args;
     memset(&A, 0, sizeof A);
     fold_params(family, params, dim, A);
-    A.inv_g = 1.0 / (double)g;
-    A.nb_d = (double)nb;
+    A.zscale = ((double)nb / (double)g) * 0x1p-32;
     double nbd = (double)nb;
     for (int j = 1; j < dim; ++j) nbd = nbd * (double)nb;
     A.nbd = nbd;
     A.inv_p = 1.0 / (double)p;
     A.inv_pm1 = 1.0 / (double)(p - 1);
-    uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
-    for (int r = 0; r < 10; ++r) {
-        A.round_key[2 * r] = k0;
-        A.round_key[2 * r + 1] = k1;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
+    A.key0 = (uint32_t)(seed & 0xffffffffu);
+    A.key1 = (uint32_t)(seed >> 32);
     A.stream_id = opt.stream_id;
     A.iteration = 0;
     A.g = (uint32_t)g;

@@ -25,12 +25,11 @@ struct VsArgs {
     double ca[kMaxDim];
     double cu[kMaxDim];
     double phase;
-    double inv_g;       // fl(1/g)
-    double nb_d;        // nb as double
+    double zscale;      // fl(nb/g) * 2^-32: bin coordinate per unit of (c_j 2^32 + r + 1/2)
     double nbd;         // fl(nb^d) by repeated multiplication
     double inv_p;       // fl(1/p)
     double inv_pm1;     // fl(1/(p-1))
-    uint32_t round_key[20];  // Philox round keys (k0, k1) of rounds 0..9
+    uint32_t key0, key1;  // Philox key: low and high 32 bits of the seed
     uint32_t stream_id;
     uint32_t iteration;
     uint32_t g, m, p, nb;

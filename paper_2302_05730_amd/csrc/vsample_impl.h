@@ -13,8 +13,8 @@
 // which needs no division in the loop.  The results depend only on the cube
 // id, never on the launch geometry.
 //
-// Per block, the grid edges of all axes are staged once into LDS (read by a
-// ds_read2_b64 per axis and sample), and the bin contributions go into an
+// Per block, the grid of all axes is staged once into LDS as (edge, width)
+// pairs (one 16-byte LDS read per axis and sample), and the bin contributions go into an
 // LDS-private FP64 histogram (ds_add_f64), flushed at the end with one
 // global FP64 atomic per non-empty bin.  Per-thread sums of the cube sums and
 // cube variances are reduced across the wave with shuffles, across the
@@ -31,19 +31,22 @@
 
 namespace mcubes {
 
-// Philox4x32-10 (Salmon et al., SC'11) with precomputed round keys.
+// Philox4x32-10 (Salmon et al., SC'11).  The key is uniform across the
+// wave, so the round keys are scalar adds.
 __device__ __forceinline__ void philox10(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
-                                         const uint32_t *rk, uint32_t out[4]) {
+                                         uint32_t k0, uint32_t k1, uint32_t out[4]) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * x0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ x1 ^ rk[2 * r];
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ x3 ^ rk[2 * r + 1];
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
         x1 = (uint32_t)p1;
         x3 = (uint32_t)p0;
         x0 = n0;
         x2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
     }
     out[0] = x0;
     out[1] = x1;
@@ -153,13 +156,18 @@ __global__ __launch_bounds__(kMaxBlock) void vsample_kernel(const VsArgs A,
     __shared__ double red[2][kMaxBlock / 64];
 
     const int nb = (int)A.nb;
-    const int ne = D * (nb + 1);
     const int nh = D * nb;
-    double *sE = smem;       // edges, axis j at [j*(nb+1), (j+1)*(nb+1))
-    double *sH = smem + ne;  // bin sums, axis j at [j*nb, (j+1)*nb)
+    // LDS: (edge, width) pairs of every axis, 16-byte aligned, then the bin sums.
+    double2 *sEW = reinterpret_cast<double2 *>(smem);  // axis j at [j*nb, (j+1)*nb)
+    double *sH = smem + 2 * nh;                          // axis j at [j*nb, (j+1)*nb)
 
-    for (int i = threadIdx.x; i < ne; i += blockDim.x) sE[i] = grid[i];
-    for (int i = threadIdx.x; i < nh; i += blockDim.x) sH[i] = 0.0;
+    for (int q = threadIdx.x; q < nh; q += blockDim.x) {
+        const int j = q / nb, i = q - j * nb;
+        const double e0 = grid[j * (nb + 1) + i];
+        const double e1 = grid[j * (nb + 1) + i + 1];
+        sEW[q] = make_double2(e0, e1 - e0);
+        sH[q] = 0.0;
+    }
     __syncthreads();
 
     const uint32_t T = gridDim.x * blockDim.x;
@@ -179,33 +187,40 @@ __global__ __launch_bounds__(kMaxBlock) void vsample_kernel(const VsArgs A,
             }
         }
         for (uint32_t n = 0; n < count; ++n) {
-            double base[D];
+            // c_j + u_j = (c_j 2^32 + r + 1/2) 2^-32 with u_j = (r + 1/2) 2^-32; the
+            // integer-plus-half c_j 2^32 + r + 1/2 is exact in FP64 (< 2^53), and
+            // scaling fl(nb/g) by 2^-32 is exact, so z below rounds exactly once,
+            // like (c_j + u_j) * fl(nb/g).
+            double cb[D];
 #pragma unroll
-            for (int j = 0; j < D; ++j) base[j] = (double)dig[j];
+            for (int j = 0; j < D; ++j) cb[j] = __fma_rn((double)dig[j], 0x1p32, 0.5);
 
             double S = 0.0, D1 = 0.0, D2 = 0.0, w0 = 0.0;
             for (uint32_t k = 0; k < A.p; ++k) {
                 uint32_t r[4 * NBLK];
 #pragma unroll
                 for (int b = 0; b < NBLK; ++b)
-                    philox10(c, A.stream_id, k * NBLK + b, A.iteration, A.round_key, r + 4 * b);
+                    philox10(c, A.stream_id, k * NBLK + b, A.iteration, A.key0, A.key1, r + 4 * b);
 
                 double x[D];
                 int bin[D];
                 double prod = 1.0;
 #pragma unroll
                 for (int j = 0; j < D; ++j) {
-                    const double u = __fma_rn((double)r[j], 0x1p-32, 0x1p-33);
-                    const double y = (base[j] + u) * A.inv_g;
-                    const double z = y * A.nb_d;
+                    const double z = ((double)r[j] + cb[j]) * A.zscale;
                     int i = (int)z;
-                    i = i < nb - 1 ? i : nb - 1;
-                    const double phi = z - (double)i;
-                    const double *e = sE + j * (nb + 1) + i;
-                    const double e0 = e[0];
-                    const double W = e[1] - e0;
-                    x[j] = __fma_rn(W, phi, e0);
-                    prod = prod * W;
+                    double phi;
+                    if constexpr (D >= 2) {
+                        // g < 2^16 here, so z < nb and the clamp below never fires:
+                        // fract(z) = z - floor(z) = z - i exactly.
+                        phi = __builtin_amdgcn_fract(z);
+                    } else {
+                        i = i < nb - 1 ? i : nb - 1;
+                        phi = z - (double)i;
+                    }
+                    const double2 ew = sEW[j * nb + i];
+                    x[j] = __fma_rn(ew.y, phi, ew.x);
+                    prod = prod * ew.y;
                     bin[j] = i;
                 }
                 const double J = A.nbd * prod;
