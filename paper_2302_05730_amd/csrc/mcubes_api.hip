@@ -19,7 +19,8 @@ struct mcubes_plan {
     double alpha;
     int64_t g, m, p, n;
     VsArgs args;
-    VsKernel kernel;
+    VsLaunchFn launch;
+    const void *func;
 };
 
 namespace {
@@ -184,7 +185,10 @@ int mcubes_plan_create(int family, const double *params, int dim, int64_t ncall,
     e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute(LDS)");
 
-    const VsKernel kern = family_table(family)[dim];
+    const VsKernel &kern_pair = family_table(family)[dim];
+    const int variant = (p == 2) ? 1 : 0;
+    const VsLaunchFn launch = kern_pair.launch[variant];
+    const void *kfunc = kern_pair.func[variant];
     const int nb = opt.nbins;
     // (edge, width) pairs and bin sums of every axis
     const size_t lds = (size_t)(3 * dim * nb) * sizeof(double);
@@ -192,12 +196,19 @@ int mcubes_plan_create(int family, const double *params, int dim, int64_t ncall,
         return fail(MCUBES_E_ARG, "dim %d with %d bins needs %zu bytes of LDS, device has %d", dim,
                     nb, lds, max_lds);
     if (lds > 65536) {
-        e = hipFuncSetAttribute(kern.func, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        e = hipFuncSetAttribute(kfunc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
     }
-    const int block = opt.block_size ? opt.block_size : 1024;
+    hipFuncAttributes fattr;
+    e = hipFuncGetAttributes(&fattr, kfunc);
+    if (e != hipSuccess) return hip_fail(e, "hipFuncGetAttributes");
+    const int max_block = fattr.maxThreadsPerBlock;
+    if (opt.block_size > max_block)
+        return fail(MCUBES_E_ARG, "block_size %d exceeds this kernel's limit %d", opt.block_size,
+                    max_block);
+    const int block = opt.block_size ? opt.block_size : max_block;
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern.func, block, lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfunc, block, lds);
     if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
     if (per_cu < 1) return fail(MCUBES_E_ARG, "V-Sample does not fit: block %d, LDS %zu", block, lds);
     int64_t blocks = opt.blocks ? opt.blocks : (int64_t)per_cu * cus;
@@ -221,7 +232,8 @@ int mcubes_plan_create(int family, const double *params, int dim, int64_t ncall,
     P->m = m;
     P->p = p;
     P->n = sz[3];
-    P->kernel = kern;
+    P->launch = launch;
+    P->func = kfunc;
 
     VsArgs &A = P->args;
     memset(&A, 0, sizeof A);
@@ -297,8 +309,8 @@ int mcubes_vsample(const mcubes_plan *P, uint32_t iteration, const double *d_gri
     if (!P || !d_grid || !d_bins || !d_partials) return fail(MCUBES_E_ARG, "NULL argument");
     VsArgs A = P->args;
     A.iteration = iteration;
-    const hipError_t e = P->kernel.launch(A, d_grid, d_bins, d_partials, P->blocks, P->block, P->lds,
-                                          as_stream(stream));
+    const hipError_t e = P->launch(A, d_grid, d_bins, d_partials, P->blocks, P->block, P->lds,
+                                   as_stream(stream));
     return e == hipSuccess ? MCUBES_OK : hip_fail(e, "V-Sample launch");
 }
 

@@ -42,9 +42,11 @@ typedef hipError_t (*VsLaunchFn)(const VsArgs &args, const double *grid, double 
                                  double *partials, int blocks, int block, size_t lds,
                                  hipStream_t stream);
 
+// Two variants per (family, dim): [0] any p, [1] p = 2 (both samples of a
+// cube in straight-line code).
 struct VsKernel {
-    VsLaunchFn launch;
-    const void *func;  // kernel symbol, for occupancy queries and attributes
+    VsLaunchFn launch[2];
+    const void *func[2];  // kernel symbols, for occupancy queries and attributes
 };
 
 // Per-family tables, index = dim (1..kMaxDim); defined in vsample_f<family>.hip.

@@ -32,15 +32,20 @@
 namespace mcubes {
 
 // Philox4x32-10 (Salmon et al., SC'11).  The key is uniform across the
-// wave, so the round keys are scalar adds.
+// wave, so the round keys are scalar adds; each output word's two xors are
+// one gfx950 three-input bitwise op (truth table 0x96 = a ^ b ^ c).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ void philox10(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
                                          uint32_t k0, uint32_t k1, uint32_t out[4]) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * x0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), x1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), x3, k1);
         x1 = (uint32_t)p1;
         x3 = (uint32_t)p0;
         x0 = n0;
@@ -54,90 +59,85 @@ __device__ __forceinline__ void philox10(uint32_t x0, uint32_t x1, uint32_t x2, 
     out[3] = x3;
 }
 
+// Integrand families, evaluated axis by axis in axis order (the same
+// operation order as the plain definitions, without keeping x[] alive):
+// begin() -> axis(j, x_j) for j = 0..D-1 -> end().  ca, cu are the folded
+// coefficients (see VsArgs).
+struct Acc {
+    double s;
+    bool inside;
+};
+
 template <int F, int D>
 struct Family;
 
 template <int D>
-struct Family<MCUBES_OSCILLATORY, D> {
-    static __device__ __forceinline__ double eval(const VsArgs &A, const double *x) {
-        double arg = A.phase;
-#pragma unroll
-        for (int i = 0; i < D; ++i) arg = __fma_rn(A.ca[i], x[i], arg);
-        return cos(arg);
+struct Family<MCUBES_OSCILLATORY, D> {  // cos(2 pi u_0 + sum a_i x_i)
+    static __device__ __forceinline__ Acc begin(double phase) { return {phase, true}; }
+    static __device__ __forceinline__ void axis(Acc &a, double ca, double, double x) {
+        a.s = __fma_rn(ca, x, a.s);
     }
+    static __device__ __forceinline__ double end(const Acc &a) { return cos(a.s); }
 };
 
 template <int D>
-struct Family<MCUBES_PRODUCT_PEAK, D> {
-    static __device__ __forceinline__ double eval(const VsArgs &A, const double *x) {
-        double den = 1.0;
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            const double t = x[i] - A.cu[i];
-            den = den * __fma_rn(t, t, A.ca[i]);
-        }
-        return 1.0 / den;
+struct Family<MCUBES_PRODUCT_PEAK, D> {  // prod (a_i^-2 + (x_i - u_i)^2)^-1
+    static __device__ __forceinline__ Acc begin(double) { return {1.0, true}; }
+    static __device__ __forceinline__ void axis(Acc &a, double ca, double cu, double x) {
+        const double t = x - cu;
+        a.s = a.s * __fma_rn(t, t, ca);
     }
+    static __device__ __forceinline__ double end(const Acc &a) { return 1.0 / a.s; }
 };
 
 template <int D>
-struct Family<MCUBES_CORNER_PEAK, D> {
-    static __device__ __forceinline__ double eval(const VsArgs &A, const double *x) {
-        double s = 1.0;
+struct Family<MCUBES_CORNER_PEAK, D> {  // (1 + sum a_i x_i)^-(d+1)
+    static __device__ __forceinline__ Acc begin(double) { return {1.0, true}; }
+    static __device__ __forceinline__ void axis(Acc &a, double ca, double, double x) {
+        a.s = __fma_rn(ca, x, a.s);
+    }
+    static __device__ __forceinline__ double end(const Acc &a) {
+        double pw = a.s;
 #pragma unroll
-        for (int i = 0; i < D; ++i) s = __fma_rn(A.ca[i], x[i], s);
-        double pw = s;
-#pragma unroll
-        for (int k = 0; k < D; ++k) pw = pw * s;
+        for (int k = 0; k < D; ++k) pw = pw * a.s;
         return 1.0 / pw;
     }
 };
 
 template <int D>
-struct Family<MCUBES_GAUSSIAN, D> {
-    static __device__ __forceinline__ double eval(const VsArgs &A, const double *x) {
-        double s = 0.0;
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            const double t = x[i] - A.cu[i];
-            s = __fma_rn(A.ca[i], t * t, s);
-        }
-        return exp(-s);
+struct Family<MCUBES_GAUSSIAN, D> {  // exp(-sum a_i^2 (x_i - u_i)^2)
+    static __device__ __forceinline__ Acc begin(double) { return {0.0, true}; }
+    static __device__ __forceinline__ void axis(Acc &a, double ca, double cu, double x) {
+        const double t = x - cu;
+        a.s = __fma_rn(ca, t * t, a.s);
     }
+    static __device__ __forceinline__ double end(const Acc &a) { return exp(-a.s); }
 };
 
 template <int D>
-struct Family<MCUBES_C0, D> {
-    static __device__ __forceinline__ double eval(const VsArgs &A, const double *x) {
-        double s = 0.0;
-#pragma unroll
-        for (int i = 0; i < D; ++i) s = __fma_rn(A.ca[i], fabs(x[i] - A.cu[i]), s);
-        return exp(-s);
+struct Family<MCUBES_C0, D> {  // exp(-sum a_i |x_i - u_i|)
+    static __device__ __forceinline__ Acc begin(double) { return {0.0, true}; }
+    static __device__ __forceinline__ void axis(Acc &a, double ca, double cu, double x) {
+        a.s = __fma_rn(ca, fabs(x - cu), a.s);
     }
+    static __device__ __forceinline__ double end(const Acc &a) { return exp(-a.s); }
 };
 
 template <int D>
-struct Family<MCUBES_DISCONTINUOUS, D> {
-    static __device__ __forceinline__ double eval(const VsArgs &A, const double *x) {
-        double s = 0.0;
-        bool inside = true;
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            inside = inside && (x[i] < A.cu[i]);
-            s = __fma_rn(A.ca[i], x[i], s);
-        }
-        return inside ? exp(s) : 0.0;
+struct Family<MCUBES_DISCONTINUOUS, D> {  // exp(sum a_i x_i) if x_i < u_i for all i
+    static __device__ __forceinline__ Acc begin(double) { return {0.0, true}; }
+    static __device__ __forceinline__ void axis(Acc &a, double ca, double cu, double x) {
+        a.inside = a.inside && (x < cu);
+        a.s = __fma_rn(ca, x, a.s);
     }
+    static __device__ __forceinline__ double end(const Acc &a) { return a.inside ? exp(a.s) : 0.0; }
 };
 
 template <int D>
-struct Family<MCUBES_ADDITION, D> {
-    static __device__ __forceinline__ double eval(const VsArgs &, const double *x) {
-        double s = 0.0;
-#pragma unroll
-        for (int i = 0; i < D; ++i) s = s + x[i];
-        return s;
-    }
+struct Family<MCUBES_ADDITION, D> {  // sum x_i
+    static __device__ __forceinline__ Acc begin(double) { return {0.0, true}; }
+    static __device__ __forceinline__ void axis(Acc &a, double, double, double x) { a.s = a.s + x; }
+    static __device__ __forceinline__ double end(const Acc &a) { return a.s; }
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -146,17 +146,86 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// One sample k of cube c: Philox words -> bin coordinates -> x through the
+// (edge, width) table -> weight w = f(x) J; bin[j] receives the bin index on
+// axis j.  cb[j] = c_j 2^32 + 1/2 (see below).
 template <int F, int D>
-__global__ __launch_bounds__(kMaxBlock) void vsample_kernel(const VsArgs A,
+__device__ __forceinline__ double draw(const VsArgs &A, const double *ca, const double *cu,
+                                       uint32_t c, uint32_t k, const double *cb,
+                                       const double2 *sEW, int nb, int *bin) {
+    constexpr int NBLK = (D + 3) / 4;  // Philox blocks (4 words each) per sample
+    // Axes in groups of four, one Philox block per group: the group's bin
+    // indices and in-bin fractions first, then its table reads back to back,
+    // then their uses, so that the reads are in flight together instead of
+    // each one stalling the wave for a full LDS round trip.
+    Acc acc = Family<F, D>::begin(A.phase);
+    double prod = 1.0;
+#pragma unroll
+    for (int b = 0; b < NBLK; ++b) {
+        uint32_t r[4];
+        philox10(c, A.stream_id, k * NBLK + b, A.iteration, A.key0, A.key1, r);
+        double phi[4];
+        double2 ew[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = 4 * b + q;
+            if (j < D) {
+                // z = (c_j + u_j) * fl(nb/g): c_j 2^32 + r + 1/2 is exact (< 2^53)
+                // and scaling fl(nb/g) by 2^-32 is exact, so this rounds once.
+                const double z = ((double)r[q] + cb[j]) * A.zscale;
+                int i = (int)z;
+                if constexpr (D >= 2) {
+                    // g < 2^16 here, so z < nb and the bin clamp never fires:
+                    // fract(z) = z - floor(z) = z - i exactly.
+                    phi[q] = __builtin_amdgcn_fract(z);
+                } else {
+                    i = i < nb - 1 ? i : nb - 1;
+                    phi[q] = z - (double)i;
+                }
+                bin[j] = i;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (4 * b + q < D) ew[q] = sEW[(4 * b + q) * nb + bin[4 * b + q]];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = 4 * b + q;
+            if (j < D) {
+                const double x = __fma_rn(ew[q].y, phi[q], ew[q].x);
+                prod = prod * ew[q].y;
+                Family<F, D>::axis(acc, ca[j], cu[j], x);
+            }
+        }
+    }
+    const double J = A.nbd * prod;
+    return Family<F, D>::end(acc) * J;
+}
+
+// Largest block of a V-Sample instantiation.  The LDS tables allow one block
+// per CU, so the block size sets the waves per SIMD and the register budget:
+// 1024 threads -> 4 waves, 128 VGPRs; 768 -> 3 waves, 168 VGPRs for the
+// instantiations whose live state does not fit 128 registers.
+template <int F, int D>
+constexpr int vs_max_block() {
+    return (D >= 9 || (F == MCUBES_DISCONTINUOUS && D >= 8)) ? 768 : 1024;
+}
+
+template <int F, int D, bool P2>
+__global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_kernel(const VsArgs A,
                                                            const double *__restrict__ grid,
                                                            double *__restrict__ bins,
                                                            double *__restrict__ partials) {
-    constexpr int NBLK = (D + 3) / 4;  // Philox blocks (4 words each) per sample
     extern __shared__ double smem[];
     __shared__ double red[2][kMaxBlock / 64];
+    __shared__ double scoef[2 * kMaxDim];
 
     const int nb = (int)A.nb;
     const int nh = D * nb;
+    if (threadIdx.x < D) {
+        scoef[threadIdx.x] = A.ca[threadIdx.x];
+        scoef[kMaxDim + threadIdx.x] = A.cu[threadIdx.x];
+    }
     // LDS: (edge, width) pairs of every axis, 16-byte aligned, then the bin sums.
     double2 *sEW = reinterpret_cast<double2 *>(smem);  // axis j at [j*nb, (j+1)*nb)
     double *sH = smem + 2 * nh;                          // axis j at [j*nb, (j+1)*nb)
@@ -169,6 +238,16 @@ __global__ __launch_bounds__(kMaxBlock) void vsample_kernel(const VsArgs A,
         sH[q] = 0.0;
     }
     __syncthreads();
+
+    // The integrand coefficients are read back from LDS into per-lane
+    // registers: used by every sample, they would otherwise crowd the scalar
+    // register file (and spill) at high dimension.
+    double ca[D], cu[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        ca[j] = scoef[j];
+        cu[j] = scoef[kMaxDim + j];
+    }
 
     const uint32_t T = gridDim.x * blockDim.x;
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -187,56 +266,47 @@ __global__ __launch_bounds__(kMaxBlock) void vsample_kernel(const VsArgs A,
             }
         }
         for (uint32_t n = 0; n < count; ++n) {
-            // c_j + u_j = (c_j 2^32 + r + 1/2) 2^-32 with u_j = (r + 1/2) 2^-32; the
-            // integer-plus-half c_j 2^32 + r + 1/2 is exact in FP64 (< 2^53), and
-            // scaling fl(nb/g) by 2^-32 is exact, so z below rounds exactly once,
-            // like (c_j + u_j) * fl(nb/g).
             double cb[D];
 #pragma unroll
             for (int j = 0; j < D; ++j) cb[j] = __fma_rn((double)dig[j], 0x1p32, 0.5);
 
-            double S = 0.0, D1 = 0.0, D2 = 0.0, w0 = 0.0;
-            for (uint32_t k = 0; k < A.p; ++k) {
-                uint32_t r[4 * NBLK];
-#pragma unroll
-                for (int b = 0; b < NBLK; ++b)
-                    philox10(c, A.stream_id, k * NBLK + b, A.iteration, A.key0, A.key1, r + 4 * b);
-
-                double x[D];
+            if constexpr (P2) {
+                // p = 2: both samples in straight-line code (independent chains
+                // for the scheduler).  With w0 = wa the shifted sums are D1 = dlt,
+                // D2 = dlt^2, and var_c = D2 - D1^2/2 = dlt^2 / 2.
                 int bin[D];
-                double prod = 1.0;
+                const double wa = draw<F, D>(A, ca, cu, c, 0, cb, sEW, nb, bin);
+                const double w2a = wa * wa;
 #pragma unroll
-                for (int j = 0; j < D; ++j) {
-                    const double z = ((double)r[j] + cb[j]) * A.zscale;
-                    int i = (int)z;
-                    double phi;
-                    if constexpr (D >= 2) {
-                        // g < 2^16 here, so z < nb and the clamp below never fires:
-                        // fract(z) = z - floor(z) = z - i exactly.
-                        phi = __builtin_amdgcn_fract(z);
-                    } else {
-                        i = i < nb - 1 ? i : nb - 1;
-                        phi = z - (double)i;
-                    }
-                    const double2 ew = sEW[j * nb + i];
-                    x[j] = __fma_rn(ew.y, phi, ew.x);
-                    prod = prod * ew.y;
-                    bin[j] = i;
+                for (int j = 0; j < D; ++j) atomicAdd(sH + j * nb + bin[j], w2a);
+                // keep the two samples' register live ranges apart (128 VGPRs at
+                // 1024 threads per block)
+                __builtin_amdgcn_sched_barrier(0);
+                const double wb = draw<F, D>(A, ca, cu, c, 1, cb, sEW, nb, bin);
+                const double w2b = wb * wb;
+#pragma unroll
+                for (int j = 0; j < D; ++j) atomicAdd(sH + j * nb + bin[j], w2b);
+                const double dlt = wb - wa;
+                const double d2 = dlt * dlt;
+                tS += wa + wb;
+                tV += d2 - d2 * 0.5;
+            } else {
+                double S = 0.0, D1 = 0.0, D2 = 0.0, w0 = 0.0;
+                for (uint32_t k = 0; k < A.p; ++k) {
+                    int bin[D];
+                    const double w = draw<F, D>(A, ca, cu, c, k, cb, sEW, nb, bin);
+                    S = S + w;
+                    if (k == 0) w0 = w;
+                    const double dlt = w - w0;
+                    D1 = D1 + dlt;
+                    D2 = D2 + dlt * dlt;
+                    const double w2 = w * w;
+#pragma unroll
+                    for (int j = 0; j < D; ++j) atomicAdd(sH + j * nb + bin[j], w2);
                 }
-                const double J = A.nbd * prod;
-                const double f = Family<F, D>::eval(A, x);
-                const double w = f * J;
-                S = S + w;
-                if (k == 0) w0 = w;
-                const double dlt = w - w0;
-                D1 = D1 + dlt;
-                D2 = D2 + dlt * dlt;
-                const double w2 = w * w;
-#pragma unroll
-                for (int j = 0; j < D; ++j) atomicAdd(sH + j * nb + bin[j], w2);
+                tS += S;
+                tV += (D2 - D1 * D1 * A.inv_p) * A.inv_pm1;
             }
-            tS += S;
-            tV += (D2 - D1 * D1 * A.inv_p) * A.inv_pm1;
 
             // advance to the next work item: linear id and digits by `step`
             uint32_t cn = c + A.step;
@@ -279,26 +349,32 @@ __global__ __launch_bounds__(kMaxBlock) void vsample_kernel(const VsArgs A,
     }
 }
 
-template <int F, int D>
+template <int F, int D, bool P2>
 hipError_t launch_vsample(const VsArgs &args, const double *grid, double *bins, double *partials,
                           int blocks, int block, size_t lds, hipStream_t stream) {
-    hipLaunchKernelGGL((vsample_kernel<F, D>), dim3(blocks), dim3(block), lds, stream, args, grid,
-                       bins, partials);
+    hipLaunchKernelGGL((vsample_kernel<F, D, P2>), dim3(blocks), dim3(block), lds, stream, args,
+                       grid, bins, partials);
     return hipGetLastError();
 }
 
-#define MCUBES_VS_ENTRY(F, D) \
-    VsKernel { &launch_vsample<F, D>, reinterpret_cast<const void *>(&vsample_kernel<F, D>) }
+#define MCUBES_VS_ENTRY(F, D)                                                          \
+    VsKernel {                                                                         \
+        {&launch_vsample<F, D, false>, &launch_vsample<F, D, true>}, {                 \
+            reinterpret_cast<const void *>(&vsample_kernel<F, D, false>),              \
+            reinterpret_cast<const void *>(&vsample_kernel<F, D, true>)                \
+        }                                                                              \
+    }
 
 // A host function returning the table of one family (a namespace-scope const
 // array would be promoted to device memory by the HIP compiler).
 #define MCUBES_VS_TABLE(NAME, F)                                                             \
     const VsKernel *NAME() {                                                                 \
         static const VsKernel table[kMaxDim + 1] = {                                         \
-            VsKernel{nullptr, nullptr}, MCUBES_VS_ENTRY(F, 1), MCUBES_VS_ENTRY(F, 2),        \
-            MCUBES_VS_ENTRY(F, 3),      MCUBES_VS_ENTRY(F, 4), MCUBES_VS_ENTRY(F, 5),        \
-            MCUBES_VS_ENTRY(F, 6),      MCUBES_VS_ENTRY(F, 7), MCUBES_VS_ENTRY(F, 8),        \
-            MCUBES_VS_ENTRY(F, 9),      MCUBES_VS_ENTRY(F, 10)};                             \
+            VsKernel{{nullptr, nullptr}, {nullptr, nullptr}},                                \
+            MCUBES_VS_ENTRY(F, 1), MCUBES_VS_ENTRY(F, 2), MCUBES_VS_ENTRY(F, 3),             \
+            MCUBES_VS_ENTRY(F, 4), MCUBES_VS_ENTRY(F, 5), MCUBES_VS_ENTRY(F, 6),             \
+            MCUBES_VS_ENTRY(F, 7), MCUBES_VS_ENTRY(F, 8), MCUBES_VS_ENTRY(F, 9),             \
+            MCUBES_VS_ENTRY(F, 10)};                                                         \
         return table;                                                                        \
     }
 
