@@ -29,13 +29,15 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) 
 
 
 def flops_per_sample(family, d, p):
-    """Algorithmic FP64 operations of one sample (FMA = 2, exp/cos/div = 1 each).
+    """Algorithmic FP64 operations of one sample as the method defines them
+    (FMA = 2; exp, cos and a division count 1 each).
 
-    Per axis: uniform from the random word (fma: 2), stratum (add, mul: 2),
-    map (z mul, phi sub, width sub, x fma, Jacobian mul: 6), bin update (add: 1)
-    -> 11 d.  Per sample: Jacobian scale, weight, cube sum, shift, two shifted
-    sums (add; mul+add), w^2 -> 8.  Per cube, amortised over p: variance (4) and
-    the two thread sums (2) -> 6/p.  Plus the integrand.
+    Per axis: uniform from the random word (fma: 2), stratum offset (add: 1),
+    bin coordinate (mul: 1), in-bin fraction (sub: 1), bin width (sub: 1),
+    mapped point (fma: 2), Jacobian factor (mul: 1), bin update (add: 1)
+    -> 10 d.  Per sample: Jacobian scale, weight, cube sum, shift, two shifted
+    sums (add; mul + add), w^2 -> 8.  Per cube, amortised over p: variance (4)
+    and the two running sums (2) -> 6/p.  Plus the integrand.
     """
     f = {0: 2 * d + 1,          # fma per axis, cos
          1: 4 * d + 1,          # sub, fma, mul per axis, one division
@@ -44,7 +46,42 @@ def flops_per_sample(family, d, p):
          4: 3 * d + 2,          # sub, fma per axis (|.| free), negation, exp
          5: 2 * d + 1,          # fma per axis, exp
          6: d}[family]
-    return 11 * d + 8 + 6.0 / p + f
+    return 10 * d + 8 + 6.0 / p + f
+
+
+def source_digest():
+    """SHA-256 over the HIP sources of the library (identifies the kernel build
+    that a stored counter profile belongs to)."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2302_05730_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "vsample_8d_hbm_traffic.txt")
+
+
+def stored_traffic():
+    """HBM bytes per V-Sample launch from the committed FETCH_SIZE/WRITE_SIZE
+    profile, or None when that profile was taken on different kernel sources."""
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_PROFILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != source_digest():
+        return None
+    try:
+        return float(vals["mean_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(problems, ncall):
@@ -155,7 +192,7 @@ def main():
     achieved = tot_flops / (tot_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": None, "kernel": "vsample_kernel<family, 8>",
+                "traffic": stored_traffic(), "kernel": "vsample_kernel<family, 8, p=2>",
                 "per_family": per_family}
 
     ttt = None

@@ -149,10 +149,20 @@ __device__ __forceinline__ double wave_sum(double v) {
 // One sample k of cube c: Philox words -> bin coordinates -> x through the
 // (edge, width) table -> weight w = f(x) J; bin[j] receives the bin index on
 // axis j.  cb[j] = c_j 2^32 + 1/2 (see below).
+// Grid-table reads of odd axes go through the vector L1 cache (two adjacent
+// edges of the global grid row, 4 KB per axis at 500 bins), those of even
+// axes through LDS, so that the two memory paths share the random reads and
+// the LDS keeps its bandwidth for the bin updates.
+template <int D>
+constexpr bool table_from_l1(int j) {
+    return D >= 2 && (j & 1);
+}
+
 template <int F, int D>
 __device__ __forceinline__ double draw(const VsArgs &A, const double *ca, const double *cu,
                                        uint32_t c, uint32_t k, const double *cb,
-                                       const double2 *sEW, int nb, int *bin) {
+                                       const double2 *sEW, const double *__restrict__ grid,
+                                       int nb, int *bin) {
     constexpr int NBLK = (D + 3) / 4;  // Philox blocks (4 words each) per sample
     // Axes in groups of four, one Philox block per group: the group's bin
     // indices and in-bin fractions first, then its table reads back to back,
@@ -186,14 +196,26 @@ __device__ __forceinline__ double draw(const VsArgs &A, const double *ca, const 
             }
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (4 * b + q < D) ew[q] = sEW[(4 * b + q) * nb + bin[4 * b + q]];
+        for (int q = 0; q < 4; ++q) {
+            const int j = 4 * b + q;
+            if (j < D) {
+                if (table_from_l1<D>(j)) {
+                    const double *e = grid + j * (nb + 1) + bin[j];
+                    ew[q] = make_double2(e[0], e[1]);
+                } else {
+                    ew[q] = sEW[j * nb + bin[j]];
+                }
+            }
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int j = 4 * b + q;
             if (j < D) {
-                const double x = __fma_rn(ew[q].y, phi[q], ew[q].x);
-                prod = prod * ew[q].y;
+                // L1 axes carry (E_i, E_{i+1}); the width is formed here exactly as
+                // when the LDS table is staged
+                const double W = table_from_l1<D>(j) ? ew[q].y - ew[q].x : ew[q].y;
+                const double x = __fma_rn(W, phi[q], ew[q].x);
+                prod = prod * W;
                 Family<F, D>::axis(acc, ca[j], cu[j], x);
             }
         }
@@ -275,14 +297,14 @@ __global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_kernel(const V
                 // for the scheduler).  With w0 = wa the shifted sums are D1 = dlt,
                 // D2 = dlt^2, and var_c = D2 - D1^2/2 = dlt^2 / 2.
                 int bin[D];
-                const double wa = draw<F, D>(A, ca, cu, c, 0, cb, sEW, nb, bin);
+                const double wa = draw<F, D>(A, ca, cu, c, 0, cb, sEW, grid, nb, bin);
                 const double w2a = wa * wa;
 #pragma unroll
                 for (int j = 0; j < D; ++j) atomicAdd(sH + j * nb + bin[j], w2a);
                 // keep the two samples' register live ranges apart (128 VGPRs at
                 // 1024 threads per block)
                 __builtin_amdgcn_sched_barrier(0);
-                const double wb = draw<F, D>(A, ca, cu, c, 1, cb, sEW, nb, bin);
+                const double wb = draw<F, D>(A, ca, cu, c, 1, cb, sEW, grid, nb, bin);
                 const double w2b = wb * wb;
 #pragma unroll
                 for (int j = 0; j < D; ++j) atomicAdd(sH + j * nb + bin[j], w2b);
@@ -294,7 +316,7 @@ __global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_kernel(const V
                 double S = 0.0, D1 = 0.0, D2 = 0.0, w0 = 0.0;
                 for (uint32_t k = 0; k < A.p; ++k) {
                     int bin[D];
-                    const double w = draw<F, D>(A, ca, cu, c, k, cb, sEW, nb, bin);
+                    const double w = draw<F, D>(A, ca, cu, c, k, cb, sEW, grid, nb, bin);
                     S = S + w;
                     if (k == 0) w0 = w;
                     const double dlt = w - w0;
