@@ -63,25 +63,42 @@ def source_digest():
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "vsample_8d_hbm_traffic.txt")
+COUNTER_PROFILE = os.path.join(ROOT, "profiles", "vsample_8d_counters.txt")
 
 
-def stored_traffic():
-    """HBM bytes per V-Sample launch from the committed FETCH_SIZE/WRITE_SIZE
-    profile, or None when that profile was taken on different kernel sources."""
-    if not os.path.exists(TRAFFIC_PROFILE):
+def _profile_values(path):
+    """key: value lines of a committed profile summary, or None when it is
+    missing or was taken on different kernel sources."""
+    if not os.path.exists(path):
         return None
     vals = {}
-    with open(TRAFFIC_PROFILE) as fh:
+    with open(path) as fh:
         for line in fh:
-            if ":" in line and not line.startswith("#"):
+            if ":" in line and not line.startswith(("#", " ", "[")):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
     if vals.get("source_sha256") != source_digest():
         return None
+    return vals
+
+
+def stored_traffic():
+    """HBM bytes per V-Sample launch from the committed FETCH_SIZE/WRITE_SIZE
+    profile (None if it belongs to other kernel sources)."""
+    vals = _profile_values(TRAFFIC_PROFILE)
     try:
-        return float(vals["mean_bytes_per_launch"])
+        return float(vals["mean_bytes_per_launch"]) if vals else None
     except (KeyError, ValueError):
         return None
+
+
+def stored_valu_busy():
+    """Fraction of VALU issue cycles used, per family, from the committed
+    counter profile (None if it belongs to other kernel sources)."""
+    vals = _profile_values(COUNTER_PROFILE)
+    if not vals:
+        return None
+    return {k[len("valu_busy_"):]: float(v) for k, v in vals.items() if k.startswith("valu_busy_")}
 
 
 def cpu_baseline(problems, ncall):
@@ -193,7 +210,7 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
                 "traffic": stored_traffic(), "kernel": "vsample_kernel<family, 8, p=2>",
-                "per_family": per_family}
+                "valu_busy_profiled": stored_valu_busy(), "per_family": per_family}
 
     ttt = None
     if not args.no_ttt:
