@@ -212,6 +212,19 @@ def main():
                 "traffic": stored_traffic(), "kernel": "vsample_kernel<family, 8, p=2>",
                 "valu_busy_profiled": stored_valu_busy(), "per_family": per_family}
 
+    # iterations after the grid has stopped adapting need no bin sums
+    frozen = {}
+    for pr, pl, b in zip(problems, plans, bufs):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for t in range(args.steps):
+            mc.mcubes_vsample(pl, it[0] + t, b.grid[0], None, b.partials)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        frozen[workloads.FAMILY_NAMES[pr.family]] = {"vsample_ms": round(ms, 4),
+                                                     "evals_per_s": n_eval / (ms * 1e-3)}
+
     ttt = None
     if not args.no_ttt:
         ttt = {}
@@ -239,6 +252,7 @@ def main():
                    "samples_per_cube": p, "block": plans[0].info["block_size"],
                    "blocks": plans[0].info["blocks"], "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "time_to_1e-3": ttt,
+        "frozen_grid_vsample": frozen,
     }
     print(json.dumps(out), flush=True)
 

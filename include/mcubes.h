@@ -157,7 +157,9 @@ int mcubes_fill(double *d, int64_t n, double value, void *stream);
 /* V-Sample (Alg. 2) for iteration `iteration` with grid d_grid:
  *   d_bins[j*nbins + i] += sum of w^2 over the samples that used bin i on axis j;
  *   d_partials[2b], d_partials[2b+1] <- block b's sum of cube sums S_c = sum_k w_ck
- *   and of unbiased in-cube variances var_c.  Sizes from mcubes_plan_get_info. */
+ *   and of unbiased in-cube variances var_c.  Sizes from mcubes_plan_get_info.
+ * d_bins may be NULL: the bin sums are then not formed (for iterations whose
+ * grid is not refined afterwards); the partials are the same. */
 int mcubes_vsample(const mcubes_plan *plan, uint32_t iteration, const double *d_grid,
                    double *d_bins, double *d_partials, void *stream);
 
@@ -183,7 +185,8 @@ int mcubes_refine(const mcubes_plan *plan, const double *d_grid, const double *d
                   double *d_grid_out, void *stream);
 
 /* One whole iteration: zero d_bins, V-Sample, reduce, combine, then refine
- * d_grid into d_grid_out (or copy it when iteration >= adapt_iters). */
+ * d_grid into d_grid_out.  When iteration >= adapt_iters the grid is copied
+ * unchanged and V-Sample runs without bin sums (d_bins is left untouched). */
 int mcubes_iteration(const mcubes_plan *plan, uint32_t iteration, const double *d_grid,
                      double *d_grid_out, double *d_bins, double *d_partials, double *d_est,
                      double *d_state, double rel_tol, void *stream);

@@ -232,7 +232,7 @@ def mcubes_fill(d, value, n=None, stream=None):
 def mcubes_vsample(plan, iteration, d_grid, d_bins, d_partials, stream=None):
     i = plan.info
     _check(lib().mcubes_vsample(plan.handle, int(iteration), _dev(d_grid, i["grid_len"], "grid"),
-                                _dev(d_bins, i["bins_len"], "bins"),
+                                _dev(d_bins, i["bins_len"], "bins"),  # None: no bin sums
                                 _dev(d_partials, i["partials_len"], "partials"),
                                 _stream(stream)))
 

@@ -19,7 +19,7 @@ struct mcubes_plan {
     double alpha;
     int64_t g, m, p, n;
     VsArgs args;
-    VsLaunchFn launch;
+    VsLaunchFn launch[2];  // [0] without bin sums, [1] with
     const void *func;
 };
 
@@ -185,10 +185,10 @@ int mcubes_plan_create(int family, const double *params, int dim, int64_t ncall,
     e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute(LDS)");
 
-    const VsKernel &kern_pair = family_table(family)[dim];
+    const VsKernel &kern_set = family_table(family)[dim];
     const int variant = (p == 2) ? 1 : 0;
-    const VsLaunchFn launch = kern_pair.launch[variant];
-    const void *kfunc = kern_pair.func[variant];
+    const void *kfunc = kern_set.func[0][variant];
+    const void *kfunc_nobins = kern_set.func[1][variant];
     const int nb = opt.nbins;
     // (edge, width) pairs and bin sums of every axis
     const size_t lds = (size_t)(3 * dim * nb) * sizeof(double);
@@ -197,6 +197,9 @@ int mcubes_plan_create(int family, const double *params, int dim, int64_t ncall,
                     nb, lds, max_lds);
     if (lds > 65536) {
         e = hipFuncSetAttribute(kfunc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(kfunc_nobins, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds);
         if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
     }
     hipFuncAttributes fattr;
@@ -232,7 +235,8 @@ int mcubes_plan_create(int family, const double *params, int dim, int64_t ncall,
     P->m = m;
     P->p = p;
     P->n = sz[3];
-    P->launch = launch;
+    P->launch[0] = kern_set.launch[1][variant];
+    P->launch[1] = kern_set.launch[0][variant];
     P->func = kfunc;
 
     VsArgs &A = P->args;
@@ -306,11 +310,11 @@ int mcubes_fill(double *d, int64_t n, double value, void *stream) {
 
 int mcubes_vsample(const mcubes_plan *P, uint32_t iteration, const double *d_grid, double *d_bins,
                    double *d_partials, void *stream) {
-    if (!P || !d_grid || !d_bins || !d_partials) return fail(MCUBES_E_ARG, "NULL argument");
+    if (!P || !d_grid || !d_partials) return fail(MCUBES_E_ARG, "NULL argument");
     VsArgs A = P->args;
     A.iteration = iteration;
-    const hipError_t e = P->launch(A, d_grid, d_bins, d_partials, P->blocks, P->block, P->lds,
-                                   as_stream(stream));
+    const hipError_t e = P->launch[d_bins ? 1 : 0](A, d_grid, d_bins, d_partials, P->blocks,
+                                                   P->block, P->lds, as_stream(stream));
     return e == hipSuccess ? MCUBES_OK : hip_fail(e, "V-Sample launch");
 }
 
@@ -351,16 +355,19 @@ int mcubes_iteration(const mcubes_plan *P, uint32_t iteration, const double *d_g
         return fail(MCUBES_E_ARG, "iteration %u >= %d", iteration, MCUBES_MAX_ITERATIONS);
     if (!(rel_tol >= 0.0) || !isfinite(rel_tol)) return fail(MCUBES_E_ARG, "rel_tol must be finite and >= 0");
     hipStream_t s = as_stream(stream);
-    hipError_t e = launch_fill(d_bins, (int64_t)P->dim * P->nb, 0.0, s);
-    if (e != hipSuccess) return hip_fail(e, "fill launch");
-    int rc = mcubes_vsample(P, iteration, d_grid, d_bins, d_partials, stream);
+    const bool refine = P->adapt_iters < 0 || (int64_t)iteration < P->adapt_iters;
+    hipError_t e = hipSuccess;
+    if (refine) {
+        e = launch_fill(d_bins, (int64_t)P->dim * P->nb, 0.0, s);
+        if (e != hipSuccess) return hip_fail(e, "fill launch");
+    }
+    int rc = mcubes_vsample(P, iteration, d_grid, refine ? d_bins : nullptr, d_partials, stream);
     if (rc != MCUBES_OK) return rc;
     rc = mcubes_reduce(P, d_partials, d_est, stream);
     if (rc != MCUBES_OK) return rc;
     rc = mcubes_combine(P, iteration, d_est, d_state, rel_tol, stream);
     if (rc != MCUBES_OK) return rc;
-    if (P->adapt_iters < 0 || (int64_t)iteration < P->adapt_iters)
-        return mcubes_refine(P, d_grid, d_bins, d_grid_out, stream);
+    if (refine) return mcubes_refine(P, d_grid, d_bins, d_grid_out, stream);
     e = launch_copy(d_grid, d_grid_out, (int64_t)P->dim * (P->nb + 1), s);
     return e == hipSuccess ? MCUBES_OK : hip_fail(e, "copy launch");
 }
@@ -419,13 +426,15 @@ int mcubes_integrate(int family, const double *params, int dim, int64_t ncall, i
     MC_CHECK(launch_fill(state, MCUBES_STATE_LEN, 0.0, s), "fill launch");
     for (int t = 0; t < itmax; ++t) {
         double *g_in = grid[t & 1], *g_out = grid[(t + 1) & 1];
-        MC_CHECK(launch_fill(bins, nbn, 0.0, s), "fill launch");
+        const bool refine = P->adapt_iters < 0 || t < P->adapt_iters;
+        if (refine) MC_CHECK(launch_fill(bins, nbn, 0.0, s), "fill launch");
         MC_CHECK(hipEventRecord(ev0, s), "hipEventRecord");
-        MC_CALL(mcubes_vsample(P, (uint32_t)t, g_in, bins, partials, opt.stream));
+        MC_CALL(mcubes_vsample(P, (uint32_t)t, g_in, refine ? bins : nullptr, partials,
+                               opt.stream));
         MC_CHECK(hipEventRecord(ev1, s), "hipEventRecord");
         MC_CALL(mcubes_reduce(P, partials, est, opt.stream));
         MC_CALL(mcubes_combine(P, (uint32_t)t, est, state, rel_tol, opt.stream));
-        if (P->adapt_iters < 0 || t < P->adapt_iters)
+        if (refine)
             MC_CALL(mcubes_refine(P, g_in, bins, g_out, opt.stream));
         else
             MC_CHECK(launch_copy(g_in, g_out, ng, s), "copy launch");

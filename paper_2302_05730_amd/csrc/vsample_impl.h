@@ -233,7 +233,7 @@ constexpr int vs_max_block() {
     return (D >= 9 || (F == MCUBES_DISCONTINUOUS && D >= 8)) ? 768 : 1024;
 }
 
-template <int F, int D, bool P2>
+template <int F, int D, bool P2, bool BINS>
 __global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_kernel(const VsArgs A,
                                                            const double *__restrict__ grid,
                                                            double *__restrict__ bins,
@@ -257,7 +257,7 @@ __global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_kernel(const V
         const double e0 = grid[j * (nb + 1) + i];
         const double e1 = grid[j * (nb + 1) + i + 1];
         sEW[q] = make_double2(e0, e1 - e0);
-        sH[q] = 0.0;
+        if constexpr (BINS) sH[q] = 0.0;
     }
     __syncthreads();
 
@@ -298,16 +298,20 @@ __global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_kernel(const V
                 // D2 = dlt^2, and var_c = D2 - D1^2/2 = dlt^2 / 2.
                 int bin[D];
                 const double wa = draw<F, D>(A, ca, cu, c, 0, cb, sEW, grid, nb, bin);
-                const double w2a = wa * wa;
+                if constexpr (BINS) {
+                    const double w2a = wa * wa;
 #pragma unroll
-                for (int j = 0; j < D; ++j) atomicAdd(sH + j * nb + bin[j], w2a);
+                    for (int j = 0; j < D; ++j) atomicAdd(sH + j * nb + bin[j], w2a);
+                }
                 // keep the two samples' register live ranges apart (128 VGPRs at
                 // 1024 threads per block)
                 __builtin_amdgcn_sched_barrier(0);
                 const double wb = draw<F, D>(A, ca, cu, c, 1, cb, sEW, grid, nb, bin);
-                const double w2b = wb * wb;
+                if constexpr (BINS) {
+                    const double w2b = wb * wb;
 #pragma unroll
-                for (int j = 0; j < D; ++j) atomicAdd(sH + j * nb + bin[j], w2b);
+                    for (int j = 0; j < D; ++j) atomicAdd(sH + j * nb + bin[j], w2b);
+                }
                 const double dlt = wb - wa;
                 const double d2 = dlt * dlt;
                 tS += wa + wb;
@@ -322,9 +326,11 @@ __global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_kernel(const V
                     const double dlt = w - w0;
                     D1 = D1 + dlt;
                     D2 = D2 + dlt * dlt;
-                    const double w2 = w * w;
+                    if constexpr (BINS) {
+                        const double w2 = w * w;
 #pragma unroll
-                    for (int j = 0; j < D; ++j) atomicAdd(sH + j * nb + bin[j], w2);
+                        for (int j = 0; j < D; ++j) atomicAdd(sH + j * nb + bin[j], w2);
+                    }
                 }
                 tS += S;
                 tV += (D2 - D1 * D1 * A.inv_p) * A.inv_pm1;
@@ -365,26 +371,31 @@ __global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_kernel(const V
         partials[2 * blockIdx.x + 1] = v;
     }
     // flush the block's histogram: one global atomic per non-empty bin
-    for (int i = threadIdx.x; i < nh; i += blockDim.x) {
-        const double v = sH[i];
-        if (v != 0.0) unsafeAtomicAdd(bins + i, v);
+    if constexpr (BINS) {
+        for (int i = threadIdx.x; i < nh; i += blockDim.x) {
+            const double v = sH[i];
+            if (v != 0.0) unsafeAtomicAdd(bins + i, v);
+        }
     }
 }
 
-template <int F, int D, bool P2>
+template <int F, int D, bool P2, bool BINS>
 hipError_t launch_vsample(const VsArgs &args, const double *grid, double *bins, double *partials,
                           int blocks, int block, size_t lds, hipStream_t stream) {
-    hipLaunchKernelGGL((vsample_kernel<F, D, P2>), dim3(blocks), dim3(block), lds, stream, args,
-                       grid, bins, partials);
+    hipLaunchKernelGGL((vsample_kernel<F, D, P2, BINS>), dim3(blocks), dim3(block), lds, stream,
+                       args, grid, bins, partials);
     return hipGetLastError();
 }
 
-#define MCUBES_VS_ENTRY(F, D)                                                          \
-    VsKernel {                                                                         \
-        {&launch_vsample<F, D, false>, &launch_vsample<F, D, true>}, {                 \
-            reinterpret_cast<const void *>(&vsample_kernel<F, D, false>),              \
-            reinterpret_cast<const void *>(&vsample_kernel<F, D, true>)                \
-        }                                                                              \
+#define MCUBES_VS_FN(F, D, P2, BINS) &launch_vsample<F, D, P2, BINS>
+#define MCUBES_VS_SYM(F, D, P2, BINS) \
+    reinterpret_cast<const void *>(&vsample_kernel<F, D, P2, BINS>)
+#define MCUBES_VS_ENTRY(F, D)                                                                 \
+    VsKernel {                                                                                \
+        {{MCUBES_VS_FN(F, D, false, true), MCUBES_VS_FN(F, D, true, true)},                   \
+         {MCUBES_VS_FN(F, D, false, false), MCUBES_VS_FN(F, D, true, false)}},                \
+        {{MCUBES_VS_SYM(F, D, false, true), MCUBES_VS_SYM(F, D, true, true)},                 \
+         {MCUBES_VS_SYM(F, D, false, false), MCUBES_VS_SYM(F, D, true, false)}}               \
     }
 
 // A host function returning the table of one family (a namespace-scope const
@@ -392,7 +403,8 @@ hipError_t launch_vsample(const VsArgs &args, const double *grid, double *bins, 
 #define MCUBES_VS_TABLE(NAME, F)                                                             \
     const VsKernel *NAME() {                                                                 \
         static const VsKernel table[kMaxDim + 1] = {                                         \
-            VsKernel{{nullptr, nullptr}, {nullptr, nullptr}},                                \
+            VsKernel{{{nullptr, nullptr}, {nullptr, nullptr}},                               \
+                     {{nullptr, nullptr}, {nullptr, nullptr}}},                              \
             MCUBES_VS_ENTRY(F, 1), MCUBES_VS_ENTRY(F, 2), MCUBES_VS_ENTRY(F, 3),             \
             MCUBES_VS_ENTRY(F, 4), MCUBES_VS_ENTRY(F, 5), MCUBES_VS_ENTRY(F, 6),             \
             MCUBES_VS_ENTRY(F, 7), MCUBES_VS_ENTRY(F, 8), MCUBES_VS_ENTRY(F, 9),             \

@@ -56,8 +56,9 @@ def oracle_iteration_parallel(family, params, dim, nb, ncall, seed, it, grid, th
     return I, var, bins
 
 
-def gpu_iteration(plan, it, grid_np):
-    """One V-Sample + reduce on the GPU for a given grid -> (I_t, var_t, bins)."""
+def gpu_iteration(plan, it, grid_np, with_bins=True):
+    """One V-Sample + reduce on the GPU for a given grid -> (I_t, var_t, bins)
+    (bins None when V-Sample runs without bin sums)."""
     import torch
     import paper_2302_05730_amd as mc
     info = plan.info
@@ -67,11 +68,12 @@ def gpu_iteration(plan, it, grid_np):
     d_part = torch.empty(info["partials_len"], dtype=torch.float64, device="cuda")
     d_est = torch.empty(2, dtype=torch.float64, device="cuda")
     mc.mcubes_fill(d_bins, 0.0)
-    mc.mcubes_vsample(plan, it, d_grid, d_bins, d_part)
+    mc.mcubes_vsample(plan, it, d_grid, d_bins if with_bins else None, d_part)
     mc.mcubes_reduce(plan, d_part, d_est)
     torch.cuda.synchronize()
     est = d_est.cpu().numpy()
-    return float(est[0]), float(est[1]), d_bins.cpu().numpy().reshape(dim, nb)
+    bins = d_bins.cpu().numpy().reshape(dim, nb) if with_bins else None
+    return float(est[0]), float(est[1]), bins
 
 
 def gpu_refine(plan, grid_np, bins_np):

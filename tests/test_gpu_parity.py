@@ -145,6 +145,22 @@ def test_repeatable(mc):
     assert np.allclose(a[2], b[2], rtol=1e-14, atol=0)  # bins: atomics, order varies
 
 
+@pytest.mark.parametrize("family,dim,ncall", [(3, 8, 1_000_000), (2, 5, 300_001), (6, 3, 99_999),
+                                               (1, 2, 17)])
+def test_without_bins_same_estimates(mc, family, dim, ncall):
+    """V-Sample without bin sums (iterations whose grid is not refined) gives the
+    identical estimates: same samples, same arithmetic, same reduction order."""
+    rng = np.random.default_rng(family * 7 + dim)
+    pr = workloads.random_problem(rng, family, dim, ncall, 50)
+    grid = random_grid(rng, dim, 50)
+    plan = mc.mcubes_plan_create(family, pr.params, dim, ncall, 3,
+                                 mc.mcubes_default_options(nbins=50))
+    a = gpu_iteration(plan, 4, grid, with_bins=True)
+    b = gpu_iteration(plan, 4, grid, with_bins=False)
+    assert a[0] == b[0] and a[1] == b[1]
+    assert b[2] is None
+
+
 def test_adapt_iters_and_skip(mc):
     pr = workloads.small_product_peak()
     kw = dict(nb=pr.nbins, adapt_iters=3, skip=2)
@@ -181,6 +197,22 @@ def test_nonfinite_is_reported(mc):
     with pytest.raises(mc.MCubesError) as ei:
         mc.mcubes_integrate(5, [1000.0] * 2 + [2.0] * 2, 2, 10_000, 3, 0.0, 0)
     assert ei.value.code == mc.MCUBES_E_NONFINITE
+
+
+@pytest.mark.parametrize("family", [3, 2])
+def test_8d_covers_closed_form(mc, family):
+    """The 8-D Gaussian and corner peak (a ~ U(5, 15), u ~ U(0, 1), 500 bins) at
+    2^26 samples per iteration integrate to 1e-3 relative error and cover the
+    closed form within 4 standard deviations."""
+    pr = workloads.large_8d(family, ncall=1 << 26, itmax=30, rel_tol=1e-3)
+    exact = float(cf.integral(family, pr.params, 8))
+    r = mc.mcubes_integrate(family, pr.params, 8, pr.ncall, pr.itmax, pr.rel_tol, pr.seed,
+                            mc.mcubes_default_options(nbins=500))
+    _say(f"8-D family={family}: {r['estimate']!r} +- {r['error']!r} vs {exact!r}, "
+         f"{r['iterations']} iterations")
+    assert r["converged"]
+    assert abs(r["estimate"] - exact) <= 4 * r["error"]
+    assert r["chi2_dof"] < 5
 
 
 @pytest.mark.slow
