@@ -225,18 +225,47 @@ def main():
         frozen[workloads.FAMILY_NAMES[pr.family]] = {"vsample_ms": round(ms, 4),
                                                      "evals_per_s": n_eval / (ms * 1e-3)}
 
+    # FP32 map/integrand form: V-Sample throughput and its difference to FP64
+    fp32 = {}
+    opts32 = mc.mcubes_default_options(nbins=500, block_size=args.block, blocks=args.blocks,
+                                       precision=mc.MCUBES_FP32)
+    for pr, b in zip(problems, bufs):
+        pl = mc.mcubes_plan_create(pr.family, pr.params, pr.dim, pr.ncall, pr.seed, opts32)
+        b32 = mc.Buffers(pl)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        mc.mcubes_fill(b32.bins, 0.0)
+        mc.mcubes_vsample(pl, it[0], b.grid[it[0] & 1], b32.bins, b32.partials)
+        e0.record(stream)
+        for t in range(args.steps):
+            mc.mcubes_vsample(pl, it[0], b.grid[it[0] & 1], b32.bins, b32.partials)
+        e1.record(stream)
+        mc.mcubes_reduce(pl, b32.partials, b32.est)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        fp32[workloads.FAMILY_NAMES[pr.family]] = {"vsample_ms": round(ms, 4),
+                                                   "evals_per_s": n_eval / (ms * 1e-3)}
+
     ttt = None
     if not args.no_ttt:
         ttt = {}
+        for prec_name, prec in (("fp64", mc.MCUBES_FP64), ("fp32", mc.MCUBES_FP32)):
+            for pr in problems:
+                t_a = time.perf_counter()
+                r = mc.mcubes_integrate(pr.family, pr.params, pr.dim, pr.ncall, 50, 1e-3, pr.seed,
+                                        mc.mcubes_default_options(nbins=500, precision=prec))
+                t_b = time.perf_counter()
+                ttt[f"{workloads.FAMILY_NAMES[pr.family]}_{prec_name}"] = {
+                    "seconds": round(t_b - t_a, 4), "iterations": r["iterations"],
+                    "converged": r["converged"], "estimate": r["estimate"], "error": r["error"],
+                    "rel_error": (r["error"] / abs(r["estimate"]) if r["estimate"] else None)}
         for pr in problems:
-            t_a = time.perf_counter()
-            r = mc.mcubes_integrate(pr.family, pr.params, pr.dim, pr.ncall, 50, 1e-3, pr.seed,
-                                    mc.mcubes_default_options(nbins=500))
-            t_b = time.perf_counter()
-            ttt[workloads.FAMILY_NAMES[pr.family]] = {
-                "seconds": round(t_b - t_a, 4), "iterations": r["iterations"],
-                "converged": r["converged"], "estimate": r["estimate"], "error": r["error"],
-                "rel_error": (r["error"] / abs(r["estimate"]) if r["estimate"] else None)}
+            name = workloads.FAMILY_NAMES[pr.family]
+            a, b = ttt[f"{name}_fp32"], ttt[f"{name}_fp64"]
+            # same samples in both forms: the difference is the FP32 rounding of the
+            # map and the integrand, stated relative to the FP64 estimate and its error
+            a["diff_vs_fp64"] = a["estimate"] - b["estimate"]
+            a["diff_vs_fp64_in_sigma"] = (abs(a["estimate"] - b["estimate"]) / b["error"]
+                                          if b["error"] else None)
 
     cpu = None if args.no_cpu else cpu_baseline(problems, args.cpu_ncall)
     out = {
@@ -252,7 +281,7 @@ def main():
                    "samples_per_cube": p, "block": plans[0].info["block_size"],
                    "blocks": plans[0].info["blocks"], "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "time_to_1e-3": ttt,
-        "frozen_grid_vsample": frozen,
+        "frozen_grid_vsample": frozen, "fp32_vsample": fp32,
     }
     print(json.dumps(out), flush=True)
 

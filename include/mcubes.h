@@ -79,6 +79,13 @@ typedef enum {
     MCUBES_ADDITION = 6
 } mcubes_family;
 
+/* Arithmetic of the map and the integrand inside V-Sample.  MCUBES_FP32 draws
+ * the same samples into the same bins (bin coordinates stay FP64) but maps
+ * and evaluates the integrand in FP32 from an FP32 copy of the grid; the
+ * Jacobian, weights, cube statistics, bin sums, reductions, refinement and
+ * combination stay FP64. */
+typedef enum { MCUBES_FP64 = 0, MCUBES_FP32 = 1 } mcubes_precision;
+
 typedef struct {
     int32_t nbins;       /* bins per axis, 2..500; default 500 (Alg. 2 uses 500) */
     int32_t adapt_iters; /* refine the grid after iterations t < adapt_iters; <0 = always (default) */
@@ -86,6 +93,7 @@ typedef struct {
     int32_t block_size;  /* V-Sample threads per block (64..1024, multiple of 64); 0 = library choice */
     int32_t blocks;      /* V-Sample blocks; 0 = enough to fill every compute unit */
     uint32_t stream_id;  /* second Philox counter word; default 0 */
+    int32_t precision;   /* mcubes_precision; default MCUBES_FP64 */
     double alpha;        /* refinement damping exponent; default 1.5 */
     void *stream;        /* hipStream_t for mcubes_integrate; NULL = null stream */
 } mcubes_options;
@@ -110,6 +118,7 @@ typedef struct mcubes_plan mcubes_plan;
 typedef struct {
     int32_t family, dim, nbins, block_size, blocks;
     int32_t lds_bytes;     /* dynamic LDS per V-Sample block */
+    int32_t precision;     /* mcubes_precision */
     int64_t cube_side, ncubes, samples_per_cube, samples_per_iter;
     int64_t grid_len;      /* dim * (nbins + 1) */
     int64_t bins_len;      /* dim * nbins */

@@ -24,6 +24,7 @@ MCUBES_E_ARG, MCUBES_E_INTEGRAND, MCUBES_E_NONFINITE, MCUBES_E_DEVICE, MCUBES_E_
     -1, -2, -3, -4, -5)
 (MCUBES_OSCILLATORY, MCUBES_PRODUCT_PEAK, MCUBES_CORNER_PEAK, MCUBES_GAUSSIAN, MCUBES_C0,
  MCUBES_DISCONTINUOUS, MCUBES_ADDITION) = range(7)
+MCUBES_FP64, MCUBES_FP32 = 0, 1
 
 
 class MCubesError(RuntimeError):
@@ -36,7 +37,8 @@ class mcubes_options(ctypes.Structure):
     _fields_ = [("nbins", ctypes.c_int32), ("adapt_iters", ctypes.c_int32),
                 ("skip", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("blocks", ctypes.c_int32), ("stream_id", ctypes.c_uint32),
-                ("alpha", ctypes.c_double), ("stream", ctypes.c_void_p)]
+                ("precision", ctypes.c_int32), ("alpha", ctypes.c_double),
+                ("stream", ctypes.c_void_p)]
 
 
 class mcubes_result(ctypes.Structure):
@@ -51,7 +53,8 @@ class mcubes_result(ctypes.Structure):
 class mcubes_plan_info(ctypes.Structure):
     _fields_ = [("family", ctypes.c_int32), ("dim", ctypes.c_int32), ("nbins", ctypes.c_int32),
                 ("block_size", ctypes.c_int32), ("blocks", ctypes.c_int32),
-                ("lds_bytes", ctypes.c_int32), ("cube_side", ctypes.c_int64),
+                ("lds_bytes", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("cube_side", ctypes.c_int64),
                 ("ncubes", ctypes.c_int64), ("samples_per_cube", ctypes.c_int64),
                 ("samples_per_iter", ctypes.c_int64), ("grid_len", ctypes.c_int64),
                 ("bins_len", ctypes.c_int64), ("partials_len", ctypes.c_int64),

@@ -12,7 +12,7 @@
 using namespace mcubes;
 
 struct mcubes_plan {
-    int family, dim, nb;
+    int family, dim, nb, precision;
     int block, blocks;
     size_t lds;
     int adapt_iters, skip;
@@ -135,6 +135,7 @@ void mcubes_default_options(mcubes_options *opt) {
     opt->block_size = 0;
     opt->blocks = 0;
     opt->stream_id = 0;
+    opt->precision = MCUBES_FP64;
     opt->alpha = 1.5;
     opt->stream = nullptr;
 }
@@ -170,6 +171,8 @@ int mcubes_plan_create(int family, const double *params, int dim, int64_t ncall,
         (opt.block_size < 64 || opt.block_size > kMaxBlock || opt.block_size % 64 != 0))
         return fail(MCUBES_E_ARG, "block_size must be 0 or a multiple of 64 in [64, %d]", kMaxBlock);
     if (opt.blocks < 0) return fail(MCUBES_E_ARG, "blocks must be >= 0");
+    if (opt.precision != MCUBES_FP64 && opt.precision != MCUBES_FP32)
+        return fail(MCUBES_E_ARG, "precision must be MCUBES_FP64 or MCUBES_FP32");
     const int64_t g = sz[0], m = sz[1], p = sz[2];
     const int nblk = (dim + 3) / 4;
     if (m > 0xFFFFFFFFll) return fail(MCUBES_E_ARG, "too many cubes (%lld >= 2^32)", (long long)m);
@@ -185,13 +188,14 @@ int mcubes_plan_create(int family, const double *params, int dim, int64_t ncall,
     e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute(LDS)");
 
+    const int prec = opt.precision == MCUBES_FP32 ? 1 : 0;
     const VsKernel &kern_set = family_table(family)[dim];
     const int variant = (p == 2) ? 1 : 0;
-    const void *kfunc = kern_set.func[0][variant];
-    const void *kfunc_nobins = kern_set.func[1][variant];
+    const void *kfunc = kern_set.func[prec][0][variant];
+    const void *kfunc_nobins = kern_set.func[prec][1][variant];
     const int nb = opt.nbins;
-    // (edge, width) pairs and bin sums of every axis
-    const size_t lds = (size_t)(3 * dim * nb) * sizeof(double);
+    // (edge, width) pairs (FP64, or FP32 in the FP32 form) and bin sums of every axis
+    const size_t lds = (size_t)((prec ? 2 : 3) * dim * nb) * sizeof(double);
     if (lds + 2 * (kMaxBlock / 64) * sizeof(double) > (size_t)max_lds)
         return fail(MCUBES_E_ARG, "dim %d with %d bins needs %zu bytes of LDS, device has %d", dim,
                     nb, lds, max_lds);
@@ -223,6 +227,7 @@ int mcubes_plan_create(int family, const double *params, int dim, int64_t ncall,
     mcubes_plan *P = new (std::nothrow) mcubes_plan();
     if (!P) return fail(MCUBES_E_ALLOC, "out of host memory");
     P->family = family;
+    P->precision = opt.precision;
     P->dim = dim;
     P->nb = nb;
     P->block = block;
@@ -235,8 +240,8 @@ int mcubes_plan_create(int family, const double *params, int dim, int64_t ncall,
     P->m = m;
     P->p = p;
     P->n = sz[3];
-    P->launch[0] = kern_set.launch[1][variant];
-    P->launch[1] = kern_set.launch[0][variant];
+    P->launch[0] = kern_set.launch[prec][1][variant];
+    P->launch[1] = kern_set.launch[prec][0][variant];
     P->func = kfunc;
 
     VsArgs &A = P->args;
@@ -283,6 +288,7 @@ int mcubes_plan_get_info(const mcubes_plan *P, mcubes_plan_info *info) {
     info->block_size = P->block;
     info->blocks = P->blocks;
     info->lds_bytes = (int32_t)P->lds;
+    info->precision = P->precision;
     info->cube_side = P->g;
     info->ncubes = P->m;
     info->samples_per_cube = P->p;

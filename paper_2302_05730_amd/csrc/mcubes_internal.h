@@ -42,12 +42,13 @@ typedef hipError_t (*VsLaunchFn)(const VsArgs &args, const double *grid, double 
                                  double *partials, int blocks, int block, size_t lds,
                                  hipStream_t stream);
 
-// Four variants per (family, dim): [bins][p2] with bins = 0 when the bin sums
-// are not wanted (no later refinement) and p2 = 1 for p = 2 (both samples of
-// a cube in straight-line code).
+// Eight variants per (family, dim): [fp32][nobins][p2] with fp32 = 1 for the
+// FP32 map/integrand form, nobins = 1 when the bin sums are not wanted (no
+// later refinement) and p2 = 1 for p = 2 (both samples of a cube in
+// straight-line code).
 struct VsKernel {
-    VsLaunchFn launch[2][2];
-    const void *func[2][2];  // kernel symbols, for occupancy queries and attributes
+    VsLaunchFn launch[2][2][2];
+    const void *func[2][2][2];  // kernel symbols, for occupancy queries and attributes
 };
 
 // Per-family tables, index = dim (1..kMaxDim); defined in vsample_f<family>.hip.

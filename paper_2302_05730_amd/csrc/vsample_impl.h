@@ -140,6 +140,87 @@ struct Family<MCUBES_ADDITION, D> {  // sum x_i
     static __device__ __forceinline__ double end(const Acc &a) { return a.s; }
 };
 
+// FP32 forms of the families (precision option): same operations in the
+// same axis order, on float values.
+struct Acc32 {
+    float s;
+    bool inside;
+};
+
+template <int F, int D>
+struct Family32;
+
+template <int D>
+struct Family32<MCUBES_OSCILLATORY, D> {
+    static __device__ __forceinline__ Acc32 begin(float phase) { return {phase, true}; }
+    static __device__ __forceinline__ void axis(Acc32 &a, float ca, float, float x) {
+        a.s = __fmaf_rn(ca, x, a.s);
+    }
+    static __device__ __forceinline__ float end(const Acc32 &a) { return cosf(a.s); }
+};
+
+template <int D>
+struct Family32<MCUBES_PRODUCT_PEAK, D> {
+    static __device__ __forceinline__ Acc32 begin(float) { return {1.0f, true}; }
+    static __device__ __forceinline__ void axis(Acc32 &a, float ca, float cu, float x) {
+        const float t = x - cu;
+        a.s = a.s * __fmaf_rn(t, t, ca);
+    }
+    static __device__ __forceinline__ float end(const Acc32 &a) { return 1.0f / a.s; }
+};
+
+template <int D>
+struct Family32<MCUBES_CORNER_PEAK, D> {
+    static __device__ __forceinline__ Acc32 begin(float) { return {1.0f, true}; }
+    static __device__ __forceinline__ void axis(Acc32 &a, float ca, float, float x) {
+        a.s = __fmaf_rn(ca, x, a.s);
+    }
+    static __device__ __forceinline__ float end(const Acc32 &a) {
+        float pw = a.s;
+#pragma unroll
+        for (int k = 0; k < D; ++k) pw = pw * a.s;
+        return 1.0f / pw;
+    }
+};
+
+template <int D>
+struct Family32<MCUBES_GAUSSIAN, D> {
+    static __device__ __forceinline__ Acc32 begin(float) { return {0.0f, true}; }
+    static __device__ __forceinline__ void axis(Acc32 &a, float ca, float cu, float x) {
+        const float t = x - cu;
+        a.s = __fmaf_rn(ca, t * t, a.s);
+    }
+    static __device__ __forceinline__ float end(const Acc32 &a) { return expf(-a.s); }
+};
+
+template <int D>
+struct Family32<MCUBES_C0, D> {
+    static __device__ __forceinline__ Acc32 begin(float) { return {0.0f, true}; }
+    static __device__ __forceinline__ void axis(Acc32 &a, float ca, float cu, float x) {
+        a.s = __fmaf_rn(ca, fabsf(x - cu), a.s);
+    }
+    static __device__ __forceinline__ float end(const Acc32 &a) { return expf(-a.s); }
+};
+
+template <int D>
+struct Family32<MCUBES_DISCONTINUOUS, D> {
+    static __device__ __forceinline__ Acc32 begin(float) { return {0.0f, true}; }
+    static __device__ __forceinline__ void axis(Acc32 &a, float ca, float cu, float x) {
+        a.inside = a.inside && (x < cu);
+        a.s = __fmaf_rn(ca, x, a.s);
+    }
+    static __device__ __forceinline__ float end(const Acc32 &a) {
+        return a.inside ? expf(a.s) : 0.0f;
+    }
+};
+
+template <int D>
+struct Family32<MCUBES_ADDITION, D> {
+    static __device__ __forceinline__ Acc32 begin(float) { return {0.0f, true}; }
+    static __device__ __forceinline__ void axis(Acc32 &a, float, float, float x) { a.s = a.s + x; }
+    static __device__ __forceinline__ float end(const Acc32 &a) { return a.s; }
+};
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -224,6 +305,58 @@ __device__ __forceinline__ double draw(const VsArgs &A, const double *ca, const 
     return Family<F, D>::end(acc) * J;
 }
 
+// FP32 form of one sample: the bin coordinates, bin indices and in-bin
+// fractions are formed in FP64 exactly as in draw() (same samples, same
+// bins); the fraction is rounded to FP32 and the map and the integrand run in
+// FP32 on an FP32 (edge, width) table.  The Jacobian fl(nb^d) prod W is formed
+// in FP64 from the same FP32 widths the map uses, and the weight is returned
+// in FP64.
+template <int F, int D>
+__device__ __forceinline__ double draw32(const VsArgs &A, const float *ca, const float *cu,
+                                         float phase, uint32_t c, uint32_t k, const double *cb,
+                                         const float2 *sEW, int nb, int *bin) {
+    constexpr int NBLK = (D + 3) / 4;
+    Acc32 acc = Family32<F, D>::begin(phase);
+    double prod = 1.0;
+#pragma unroll
+    for (int b = 0; b < NBLK; ++b) {
+        uint32_t r[4];
+        philox10(c, A.stream_id, k * NBLK + b, A.iteration, A.key0, A.key1, r);
+        float phi[4];
+        float2 ew[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = 4 * b + q;
+            if (j < D) {
+                const double z = ((double)r[q] + cb[j]) * A.zscale;
+                int i = (int)z;
+                double ph;
+                if constexpr (D >= 2) {
+                    ph = __builtin_amdgcn_fract(z);
+                } else {
+                    i = i < nb - 1 ? i : nb - 1;
+                    ph = z - (double)i;
+                }
+                phi[q] = (float)ph;
+                bin[j] = i;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (4 * b + q < D) ew[q] = sEW[(4 * b + q) * nb + bin[4 * b + q]];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = 4 * b + q;
+            if (j < D) {
+                const float x = __fmaf_rn(ew[q].y, phi[q], ew[q].x);
+                prod = prod * (double)ew[q].y;
+                Family32<F, D>::axis(acc, ca[j], cu[j], x);
+            }
+        }
+    }
+    return (double)Family32<F, D>::end(acc) * (A.nbd * prod);
+}
+
 // Largest block of a V-Sample instantiation.  The LDS tables allow one block
 // per CU, so the block size sets the waves per SIMD and the register budget:
 // 1024 threads -> 4 waves, 128 VGPRs; 768 -> 3 waves, 168 VGPRs for the
@@ -233,7 +366,7 @@ constexpr int vs_max_block() {
     return (D >= 9 || (F == MCUBES_DISCONTINUOUS && D >= 8)) ? 768 : 1024;
 }
 
-template <int F, int D, bool P2, bool BINS>
+template <int F, int D, bool P2, bool BINS, bool F32>
 __global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_kernel(const VsArgs A,
                                                            const double *__restrict__ grid,
                                                            double *__restrict__ bins,
@@ -248,15 +381,20 @@ __global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_kernel(const V
         scoef[threadIdx.x] = A.ca[threadIdx.x];
         scoef[kMaxDim + threadIdx.x] = A.cu[threadIdx.x];
     }
-    // LDS: (edge, width) pairs of every axis, 16-byte aligned, then the bin sums.
+    // LDS: (edge, width) pairs of every axis (FP64 pairs, 16 bytes, or FP32
+    // pairs, 8 bytes, in the FP32 form), then the FP64 bin sums.
     double2 *sEW = reinterpret_cast<double2 *>(smem);  // axis j at [j*nb, (j+1)*nb)
-    double *sH = smem + 2 * nh;                          // axis j at [j*nb, (j+1)*nb)
+    float2 *sEW32 = reinterpret_cast<float2 *>(smem);  // FP32 form
+    double *sH = smem + (F32 ? nh : 2 * nh);             // axis j at [j*nb, (j+1)*nb)
 
     for (int q = threadIdx.x; q < nh; q += blockDim.x) {
         const int j = q / nb, i = q - j * nb;
         const double e0 = grid[j * (nb + 1) + i];
         const double e1 = grid[j * (nb + 1) + i + 1];
-        sEW[q] = make_double2(e0, e1 - e0);
+        if constexpr (F32)
+            sEW32[q] = make_float2((float)e0, (float)(e1 - e0));
+        else
+            sEW[q] = make_double2(e0, e1 - e0);
         if constexpr (BINS) sH[q] = 0.0;
     }
     __syncthreads();
@@ -265,11 +403,15 @@ __global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_kernel(const V
     // registers: used by every sample, they would otherwise crowd the scalar
     // register file (and spill) at high dimension.
     double ca[D], cu[D];
+    float ca32[D], cu32[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         ca[j] = scoef[j];
         cu[j] = scoef[kMaxDim + j];
+        ca32[j] = (float)ca[j];
+        cu32[j] = (float)cu[j];
     }
+    const float phase32 = (float)A.phase;
 
     const uint32_t T = gridDim.x * blockDim.x;
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -297,7 +439,9 @@ __global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_kernel(const V
                 // for the scheduler).  With w0 = wa the shifted sums are D1 = dlt,
                 // D2 = dlt^2, and var_c = D2 - D1^2/2 = dlt^2 / 2.
                 int bin[D];
-                const double wa = draw<F, D>(A, ca, cu, c, 0, cb, sEW, grid, nb, bin);
+                const double wa =
+                    F32 ? draw32<F, D>(A, ca32, cu32, phase32, c, 0, cb, sEW32, nb, bin)
+                        : draw<F, D>(A, ca, cu, c, 0, cb, sEW, grid, nb, bin);
                 if constexpr (BINS) {
                     const double w2a = wa * wa;
 #pragma unroll
@@ -306,7 +450,9 @@ __global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_kernel(const V
                 // keep the two samples' register live ranges apart (128 VGPRs at
                 // 1024 threads per block)
                 __builtin_amdgcn_sched_barrier(0);
-                const double wb = draw<F, D>(A, ca, cu, c, 1, cb, sEW, grid, nb, bin);
+                const double wb =
+                    F32 ? draw32<F, D>(A, ca32, cu32, phase32, c, 1, cb, sEW32, nb, bin)
+                        : draw<F, D>(A, ca, cu, c, 1, cb, sEW, grid, nb, bin);
                 if constexpr (BINS) {
                     const double w2b = wb * wb;
 #pragma unroll
@@ -320,7 +466,9 @@ __global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_kernel(const V
                 double S = 0.0, D1 = 0.0, D2 = 0.0, w0 = 0.0;
                 for (uint32_t k = 0; k < A.p; ++k) {
                     int bin[D];
-                    const double w = draw<F, D>(A, ca, cu, c, k, cb, sEW, grid, nb, bin);
+                    const double w =
+                        F32 ? draw32<F, D>(A, ca32, cu32, phase32, c, k, cb, sEW32, nb, bin)
+                            : draw<F, D>(A, ca, cu, c, k, cb, sEW, grid, nb, bin);
                     S = S + w;
                     if (k == 0) w0 = w;
                     const double dlt = w - w0;
@@ -379,23 +527,26 @@ __global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_kernel(const V
     }
 }
 
-template <int F, int D, bool P2, bool BINS>
+template <int F, int D, bool P2, bool BINS, bool F32>
 hipError_t launch_vsample(const VsArgs &args, const double *grid, double *bins, double *partials,
                           int blocks, int block, size_t lds, hipStream_t stream) {
-    hipLaunchKernelGGL((vsample_kernel<F, D, P2, BINS>), dim3(blocks), dim3(block), lds, stream,
-                       args, grid, bins, partials);
+    hipLaunchKernelGGL((vsample_kernel<F, D, P2, BINS, F32>), dim3(blocks), dim3(block), lds,
+                       stream, args, grid, bins, partials);
     return hipGetLastError();
 }
 
-#define MCUBES_VS_FN(F, D, P2, BINS) &launch_vsample<F, D, P2, BINS>
-#define MCUBES_VS_SYM(F, D, P2, BINS) \
-    reinterpret_cast<const void *>(&vsample_kernel<F, D, P2, BINS>)
-#define MCUBES_VS_ENTRY(F, D)                                                                 \
-    VsKernel {                                                                                \
-        {{MCUBES_VS_FN(F, D, false, true), MCUBES_VS_FN(F, D, true, true)},                   \
-         {MCUBES_VS_FN(F, D, false, false), MCUBES_VS_FN(F, D, true, false)}},                \
-        {{MCUBES_VS_SYM(F, D, false, true), MCUBES_VS_SYM(F, D, true, true)},                 \
-         {MCUBES_VS_SYM(F, D, false, false), MCUBES_VS_SYM(F, D, true, false)}}               \
+#define MCUBES_VS_FN(F, D, P2, BINS, F32) &launch_vsample<F, D, P2, BINS, F32>
+#define MCUBES_VS_SYM(F, D, P2, BINS, F32) \
+    reinterpret_cast<const void *>(&vsample_kernel<F, D, P2, BINS, F32>)
+#define MCUBES_VS_SET(M, F, D, F32)                                            \
+    {                                                                          \
+        {M(F, D, false, true, F32), M(F, D, true, true, F32)},                 \
+        {M(F, D, false, false, F32), M(F, D, true, false, F32)}                \
+    }
+#define MCUBES_VS_ENTRY(F, D)                                                          \
+    VsKernel {                                                                         \
+        {MCUBES_VS_SET(MCUBES_VS_FN, F, D, false), MCUBES_VS_SET(MCUBES_VS_FN, F, D, true)}, \
+        {MCUBES_VS_SET(MCUBES_VS_SYM, F, D, false), MCUBES_VS_SET(MCUBES_VS_SYM, F, D, true)} \
     }
 
 // A host function returning the table of one family (a namespace-scope const
@@ -403,8 +554,7 @@ hipError_t launch_vsample(const VsArgs &args, const double *grid, double *bins, 
 #define MCUBES_VS_TABLE(NAME, F)                                                             \
     const VsKernel *NAME() {                                                                 \
         static const VsKernel table[kMaxDim + 1] = {                                         \
-            VsKernel{{{nullptr, nullptr}, {nullptr, nullptr}},                               \
-                     {{nullptr, nullptr}, {nullptr, nullptr}}},                              \
+            VsKernel{},                                                                      \
             MCUBES_VS_ENTRY(F, 1), MCUBES_VS_ENTRY(F, 2), MCUBES_VS_ENTRY(F, 3),             \
             MCUBES_VS_ENTRY(F, 4), MCUBES_VS_ENTRY(F, 5), MCUBES_VS_ENTRY(F, 6),             \
             MCUBES_VS_ENTRY(F, 7), MCUBES_VS_ENTRY(F, 8), MCUBES_VS_ENTRY(F, 9),             \

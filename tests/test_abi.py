@@ -43,12 +43,13 @@ _LAYOUT = r"""
 int main(void) {
     printf("mcubes_options size %zu\n", sizeof(mcubes_options));
     F(mcubes_options, nbins) F(mcubes_options, alpha) F(mcubes_options, stream)
-    F(mcubes_options, stream_id)
+    F(mcubes_options, stream_id) F(mcubes_options, precision)
     printf("mcubes_result size %zu\n", sizeof(mcubes_result));
     F(mcubes_result, chi2_dof) F(mcubes_result, status) F(mcubes_result, cube_side)
     F(mcubes_result, kernel_ms)
     printf("mcubes_plan_info size %zu\n", sizeof(mcubes_plan_info));
     F(mcubes_plan_info, lds_bytes) F(mcubes_plan_info, cube_side) F(mcubes_plan_info, state_len)
+    F(mcubes_plan_info, precision)
     printf("MCUBES_STATE_LEN x %d\n", MCUBES_STATE_LEN);
     return 0;
 }
@@ -101,6 +102,7 @@ def _create(family=3, params=None, dim=2, ncall=1000, **opt):
     (dict(skip=-1), mc.MCUBES_E_ARG),
     (dict(block_size=100), mc.MCUBES_E_ARG),
     (dict(block_size=2048), mc.MCUBES_E_ARG),
+    (dict(precision=2), mc.MCUBES_E_ARG),
     (dict(dim=1, ncall=2 * 2**32 + 4), mc.MCUBES_E_ARG),  # m >= 2^32 cubes
 ])
 def test_plan_create_rejects(kwargs, code):
@@ -119,6 +121,6 @@ def test_integrate_rejects_bad_arguments():
 
 def test_default_options():
     o = mc.mcubes_default_options()
-    assert (o.nbins, o.adapt_iters, o.skip, o.block_size, o.blocks, o.alpha) == \
-        (500, -1, 0, 0, 0, 1.5)
+    assert (o.nbins, o.adapt_iters, o.skip, o.block_size, o.blocks, o.alpha, o.precision) == \
+        (500, -1, 0, 0, 0, 1.5, mc.MCUBES_FP64)
     assert not o.stream
