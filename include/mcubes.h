@@ -200,6 +200,31 @@ int mcubes_iteration(const mcubes_plan *plan, uint32_t iteration, const double *
                      double *d_grid_out, double *d_bins, double *d_partials, double *d_est,
                      double *d_state, double rel_tol, void *stream);
 
+/* Microbenchmarks that attribute V-Sample's time (the analogue of the
+ * integrand-invocation experiment of §5.1 of the paper).  Each of the
+ * blocks*block threads (block in {64, 128, 192, 256}) runs calls_per_thread
+ * steps and writes one accumulated value to d_out[thread]:
+ *   MCUBES_MB_INTEGRAND  f(x) of `family` with `params` (as for plans) on
+ *                        points read cyclically from d_points (npts rows of
+ *                        dim FP64 coordinates, device memory);
+ *   MCUBES_MB_PHILOX     the ceil(dim/4) Philox4x32-10 blocks of one sample;
+ *   MCUBES_MB_EXP64..POW32  one libm call (exp, cos, pow^1.5; FP64 / FP32).
+ * d_out must hold blocks*block doubles. */
+typedef enum {
+    MCUBES_MB_INTEGRAND = 0,
+    MCUBES_MB_PHILOX = 1,
+    MCUBES_MB_EXP64 = 2,
+    MCUBES_MB_COS64 = 3,
+    MCUBES_MB_POW64 = 4,
+    MCUBES_MB_EXP32 = 5,
+    MCUBES_MB_COS32 = 6,
+    MCUBES_MB_POW32 = 7
+} mcubes_microbench_kind;
+
+int mcubes_microbench(int kind, int family, const double *params, int dim,
+                      const double *d_points, int64_t npts, int64_t calls_per_thread, int blocks,
+                      int block, double *d_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

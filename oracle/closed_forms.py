@@ -111,27 +111,7 @@ def integral(family, params, dim):
 
 
 def paper_params(k, dim):
-    """Parameters that turn the families into the paper's f_k (eqs. 1-6).
-
-    f1 = cos(sum i x_i)                       oscillatory, a_i = i, u_0 = 0
-    f2 = prod (1/50^2 + (x_i - 1/2)^2)^-1     product peak, a_i = 50, u_i = 1/2
-    f3 = (1 + sum i x_i)^-(d+1)               corner peak, a_i = i
-    f4 = exp(-625 sum (x_i - 1/2)^2)          Gaussian, a_i = 25, u_i = 1/2
-    f5 = exp(-10 sum |x_i - 1/2|)             C0, a_i = 10, u_i = 1/2
-    f6 = exp(sum (i+4) x_i) if x_i < (3+i)/10 discontinuous, a_i = i+4, u_i = (3+i)/10
-    (i counts axes from 1).  Returns (family id, params).
-    """
-    idx = range(1, dim + 1)
-    if k == 1:
-        return 0, [float(i) for i in idx] + [0.0] * dim
-    if k == 2:
-        return 1, [50.0] * dim + [0.5] * dim
-    if k == 3:
-        return 2, [float(i) for i in idx] + [0.0] * dim
-    if k == 4:
-        return 3, [25.0] * dim + [0.5] * dim
-    if k == 5:
-        return 4, [10.0] * dim + [0.5] * dim
-    if k == 6:
-        return 5, [float(i + 4) for i in idx] + [(3.0 + i) / 10.0 for i in idx]
-    raise ValueError(k)
+    """Parameters that turn the families into the paper's f_k (eqs. 1-6); the
+    choice is recorded once, in workloads.paper_integrand."""
+    import workloads
+    return workloads.paper_integrand(k, dim)

@@ -25,6 +25,8 @@ MCUBES_E_ARG, MCUBES_E_INTEGRAND, MCUBES_E_NONFINITE, MCUBES_E_DEVICE, MCUBES_E_
 (MCUBES_OSCILLATORY, MCUBES_PRODUCT_PEAK, MCUBES_CORNER_PEAK, MCUBES_GAUSSIAN, MCUBES_C0,
  MCUBES_DISCONTINUOUS, MCUBES_ADDITION) = range(7)
 MCUBES_FP64, MCUBES_FP32 = 0, 1
+(MCUBES_MB_INTEGRAND, MCUBES_MB_PHILOX, MCUBES_MB_EXP64, MCUBES_MB_COS64, MCUBES_MB_POW64,
+ MCUBES_MB_EXP32, MCUBES_MB_COS32, MCUBES_MB_POW32) = range(8)
 
 
 class MCubesError(RuntimeError):
@@ -88,6 +90,9 @@ _SIGNATURES = {
     "mcubes_refine": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "mcubes_iteration": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp, _vp,
                                         ctypes.c_double, _vp]),
+    "mcubes_microbench": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _vp,
+                                         ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                         _vp, _vp]),
 }
 
 
@@ -269,6 +274,15 @@ def mcubes_iteration(plan, iteration, d_grid, d_grid_out, d_bins, d_partials, d_
                                   _dev(d_partials, i["partials_len"], "partials"),
                                   _dev(d_est, 2, "est"), _dev(d_state, MCUBES_STATE_LEN, "state"),
                                   float(rel_tol), _stream(stream)))
+
+
+def mcubes_microbench(kind, d_out, blocks, block, calls_per_thread, family=0, params=None, dim=1,
+                      d_points=None, npts=0, stream=None):
+    keep, pp = _params(params, dim)
+    _check(lib().mcubes_microbench(int(kind), int(family), pp, int(dim),
+                                   _dev(d_points, npts * dim, "points") if d_points is not None
+                                   else None, int(npts), int(calls_per_thread), int(blocks),
+                                   int(block), _dev(d_out, blocks * block, "out"), _stream(stream)))
 
 
 class Buffers:

@@ -378,6 +378,32 @@ int mcubes_iteration(const mcubes_plan *P, uint32_t iteration, const double *d_g
     return e == hipSuccess ? MCUBES_OK : hip_fail(e, "copy launch");
 }
 
+int mcubes_microbench(int kind, int family, const double *params, int dim,
+                      const double *d_points, int64_t npts, int64_t calls_per_thread, int blocks,
+                      int block, double *d_out, void *stream) {
+    if (kind < MCUBES_MB_INTEGRAND || kind > MCUBES_MB_POW32)
+        return fail(MCUBES_E_ARG, "unknown microbenchmark kind %d", kind);
+    if (calls_per_thread < 0) return fail(MCUBES_E_ARG, "calls_per_thread must be >= 0");
+    if (blocks < 1 || block < 64 || block > 256 || block % 64 != 0)
+        return fail(MCUBES_E_ARG, "blocks >= 1 and block in {64, 128, 192, 256} required");
+    if (!d_out) return fail(MCUBES_E_ARG, "d_out is NULL");
+    VsArgs A;
+    memset(&A, 0, sizeof A);
+    if (kind == MCUBES_MB_INTEGRAND || kind == MCUBES_MB_PHILOX) {
+        if (dim < 1 || dim > MCUBES_MAX_DIM)
+            return fail(MCUBES_E_ARG, "dim must be in [1, %d], got %d", MCUBES_MAX_DIM, dim);
+    }
+    if (kind == MCUBES_MB_INTEGRAND) {
+        const int rc = validate_params(family, params, dim);
+        if (rc != MCUBES_OK) return rc;
+        if (!d_points || npts < 1) return fail(MCUBES_E_ARG, "d_points with npts >= 1 required");
+        fold_params(family, params, dim, A);
+    }
+    const hipError_t e = launch_microbench(kind, family, dim, A, d_points, npts, calls_per_thread,
+                                           blocks, block, d_out, as_stream(stream));
+    return e == hipSuccess ? MCUBES_OK : hip_fail(e, "microbenchmark launch");
+}
+
 int mcubes_integrate(int family, const double *params, int dim, int64_t ncall, int itmax,
                      double rel_tol, uint64_t seed, const mcubes_options *opt_in,
                      mcubes_result *out, double *grid_out, double *trace) {

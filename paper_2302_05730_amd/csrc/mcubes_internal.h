@@ -71,4 +71,9 @@ hipError_t launch_refine(const double *grid, const double *bins, double *grid_ou
                          double alpha, hipStream_t stream);
 hipError_t launch_copy(const double *src, double *dst, int64_t n, hipStream_t stream);
 
+// Microbenchmarks (microbench.hip).
+hipError_t launch_microbench(int kind, int family, int dim, const VsArgs &A, const double *pts,
+                             int64_t npts, int64_t calls, int blocks, int block, double *out,
+                             hipStream_t stream);
+
 }  // namespace mcubes

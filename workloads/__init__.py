@@ -65,6 +65,33 @@ def large_8d_set(ncall=1 << 30, itmax=50, rel_tol=1e-4):
     return [large_8d(f, ncall, itmax, rel_tol) for f in (GAUSSIAN, OSCILLATORY, CORNER_PEAK)]
 
 
+def paper_integrand(k, dim):
+    """(family, params) of the paper's benchmark integrand f_k (eqs. 1-6, §5):
+    f1 = cos(sum i x_i)                       oscillatory, a_i = i, u_0 = 0
+    f2 = prod (1/50^2 + (x_i - 1/2)^2)^-1     product peak, a_i = 50, u_i = 1/2
+    f3 = (1 + sum i x_i)^-(d+1)               corner peak, a_i = i
+    f4 = exp(-625 sum (x_i - 1/2)^2)          Gaussian, a_i = 25, u_i = 1/2
+    f5 = exp(-10 sum |x_i - 1/2|)             C0, a_i = 10, u_i = 1/2
+    f6 = exp(sum (i+4) x_i) if x_i < (3+i)/10 discontinuous, a_i = i+4, u_i = (3+i)/10
+    (i counts axes from 1); k = 7 is the addition integrand sum x_i of §5.3."""
+    idx = range(1, dim + 1)
+    if k == 1:
+        return OSCILLATORY, [float(i) for i in idx] + [0.0] * dim
+    if k == 2:
+        return PRODUCT_PEAK, [50.0] * dim + [0.5] * dim
+    if k == 3:
+        return CORNER_PEAK, [float(i) for i in idx] + [0.0] * dim
+    if k == 4:
+        return GAUSSIAN, [25.0] * dim + [0.5] * dim
+    if k == 5:
+        return C0, [10.0] * dim + [0.5] * dim
+    if k == 6:
+        return DISCONTINUOUS, [float(i + 4) for i in idx] + [(3.0 + i) / 10.0 for i in idx]
+    if k == 7:
+        return ADDITION, [0.0] * (2 * dim)
+    raise ValueError(k)
+
+
 def random_problem(rng, family, dim, ncall, nbins):
     """A random member of a family with parameters in the ranges the paper's
     integrands span (a in [5, 15] scaled down for the peaked families at high
