@@ -225,6 +225,124 @@ int mcubes_microbench(int kind, int family, const double *params, int dim,
                       const double *d_points, int64_t npts, int64_t calls_per_thread, int blocks,
                       int block, double *d_out, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batched form: many integrands of mixed family, dimension and sample budget
+ * integrated together (the paper runs one integrand per launch; this form
+ * keeps the whole GPU busy with small and mid-sized problems).
+ *
+ * Every integrand i runs m-Cubes exactly as mcubes_integrate would with the
+ * same nbins, alpha, adapt_iters and skip and with Philox stream id
+ * opt->stream_id + i: the samples are the same, so the results agree with
+ * the single-integrand path up to the rounding of the sums.  Per iteration
+ * the library launches one V-Sample kernel per (family, dim, p == 2) class,
+ * whose samples are cut into equal contiguous shares and the shares at
+ * integrand boundaries into tiles, one workgroup per tile, then
+ * per-integrand reduction, combination, refinement (in place) and an
+ * iteration counter, all reading the iteration number and the per-integrand
+ * "done" flags from device memory; the sequence is captured once in a HIP
+ * graph and replayed.  An integrand that converges (or produces a
+ * non-finite estimate) is marked done on the device and no longer sampled;
+ * when enough of the planned work has finished the library re-splits the
+ * remaining work and captures a new graph.
+ *
+ * The batch owns its device memory (grids, bins, states: about
+ * 8 * (2 * sum dim_i * (nbins + 1) + n * MCUBES_STATE_LEN) bytes plus the
+ * tile lists) and one internal HIP stream; mcubes_batch_integrate and
+ * mcubes_batch_autotune order themselves after earlier work on opt->stream
+ * and return when done.  Only MCUBES_FP64 is supported.  opt->block_size,
+ * when not 0, fixes the block size of every class; opt->blocks is ignored.
+ * A batch may be used from one host thread at a time.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t family;  /* mcubes_family */
+    int32_t dim;     /* 1..MCUBES_MAX_DIM */
+    int64_t ncall;   /* sample budget per iteration (planned as in mcubes_plan_sizes) */
+    double params[2 * MCUBES_MAX_DIM]; /* a_0..a_{dim-1}, u_0..u_{dim-1}; the rest unused */
+} mcubes_batch_item;
+
+typedef struct mcubes_batch mcubes_batch;
+
+typedef struct {
+    int32_t items;          /* integrands in the batch */
+    int32_t classes;        /* (family, dim, p == 2) classes in the current plan */
+    int32_t tiles;          /* work tiles in the current plan */
+    int32_t launches;       /* kernel launches per iteration */
+    int32_t nbins;
+    int32_t tuned;          /* 1 after mcubes_batch_autotune */
+    int64_t grids_len;      /* sum over i of dim_i * (nbins + 1): packed grids, item order */
+    int64_t samples_per_iter; /* sum of N_i over the integrands still running */
+    int64_t device_bytes;   /* device memory held by the batch */
+    /* the last mcubes_batch_integrate call: */
+    int32_t last_iterations;  /* iterations run (the most any integrand ran) */
+    int32_t last_replans;     /* times the work was re-split */
+    int64_t last_samples;     /* samples evaluated, all integrands */
+    double last_ms;           /* wall time of its iteration loop (HIP events) */
+} mcubes_batch_info;
+
+typedef struct {
+    int32_t family, dim, p2; /* p2 = 1 when the class's integrands have p = 2 */
+    int32_t items;           /* integrands of the class in the current plan */
+    int32_t block_size;      /* V-Sample threads per workgroup */
+    int32_t shares;          /* equal shares the class's samples are split into */
+    int32_t tiles;           /* workgroups per launch: shares cut at integrand boundaries */
+    int32_t lds_bytes;
+    int64_t samples;         /* samples per iteration */
+    double tuned_ms;         /* V-Sample time measured by the autotuner (0 if not tuned) */
+} mcubes_batch_class;
+
+/* Validates every item (errors name the item), plans it, allocates the
+ * batch's device memory and splits the work with the default geometry.
+ * 1 <= n <= 65536.  Returns MCUBES_OK or an error. */
+int mcubes_batch_create(const mcubes_batch_item *items, int n, uint64_t seed,
+                        const mcubes_options *opt, mcubes_batch **batch);
+void mcubes_batch_destroy(mcubes_batch *batch);
+int mcubes_batch_get_info(const mcubes_batch *batch, mcubes_batch_info *info);
+/* Class k (0 <= k < info.classes) of the current plan. */
+int mcubes_batch_get_class(const mcubes_batch *batch, int k, mcubes_batch_class *out);
+
+/* Sets the V-Sample geometry of class k: block_size a multiple of 64 up to
+ * the kernel's limit, shares >= 1 (capped at the class's cube count and at
+ * 2^20).  The samples do not depend on the geometry; only the order of the
+ * partial sums does. */
+int mcubes_batch_configure_class(mcubes_batch *batch, int k, int block_size, int shares);
+
+/* Autotuner: for every class times the V-Sample kernel on the batch's current
+ * grids over candidate block sizes (256, 512, 768, 1024 within the kernel's
+ * limit) and share counts (1, 2 or 4 times the workgroups resident at once,
+ * or fewer shares with at least 4, 16 or 64 cubes per thread for small
+ * classes), and keeps the fastest.  The grids, states and results of later
+ * calls are unaffected (up to the order of the partial sums).  Takes 3
+ * launches per candidate. */
+int mcubes_batch_autotune(mcubes_batch *batch);
+
+/* One iteration of every integrand from caller-given grids, for lock-step
+ * checking against a reference and for warm starts: V-Sample with Philox
+ * iteration word `iteration`, the reduction, and the refinement of every
+ * grid (as mcubes_iteration, without the combination).
+ *   grids (host, grids_len doubles, packed in item order): in, the grids to
+ *     sample with (each row monotone from 0 to 1, checked); out, the refined
+ *     grids.
+ *   est (host, 2 n doubles): out, (I_t, var_t) per integrand.
+ * Afterwards the combined states of mcubes_batch_integrate are undefined
+ * (the next mcubes_batch_integrate starts afresh). */
+int mcubes_batch_step(mcubes_batch *batch, uint32_t iteration, double *grids, double *est);
+
+/* Runs every integrand from a uniform grid: at most itmax iterations, each
+ * integrand stopping after the first iteration whose combined error is
+ * <= rel_tol * |estimate|.  use_graph = 1 replays the captured graph, 0
+ * launches the same kernels one by one (same results).
+ *   results (host, n entries): per-integrand result; status MCUBES_OK,
+ *     MCUBES_NOT_CONVERGED or MCUBES_E_NONFINITE; kernel_ms is 0.
+ *   grids_out (host, grids_len doubles, may be NULL): final grids, packed
+ *     in item order.
+ *   traces (host, n * 2 * itmax doubles, may be NULL): row i holds
+ *     (I_t, var_t) of integrand i for the iterations it ran, zeros after.
+ * Returns MCUBES_OK if every integrand converged, MCUBES_NOT_CONVERGED if
+ * some did not, MCUBES_E_NONFINITE if some produced a non-finite estimate,
+ * or an error (then results are not written). */
+int mcubes_batch_integrate(mcubes_batch *batch, int itmax, double rel_tol, int use_graph,
+                           mcubes_result *results, double *grids_out, double *traces);
+
 #ifdef __cplusplus
 }
 #endif

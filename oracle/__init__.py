@@ -60,8 +60,9 @@ def lib():
     L.mco_combine.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int, _dp]
     L.mco_combine.restype = ctypes.c_int
     L.mco_integrate.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int64, ctypes.c_int,
-                                ctypes.c_double, ctypes.c_uint64, ctypes.c_int, ctypes.c_double,
-                                ctypes.c_int, ctypes.c_int, _dp, _i64p, _dp, _dp, _dp]
+                                ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int,
+                                ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, _i64p, _dp, _dp,
+                                _dp]
     L.mco_integrate.restype = ctypes.c_int
     _lib = L
     return L
@@ -166,8 +167,9 @@ def combine(I, var, skip=0):
 
 
 def integrate(family, params, dim, ncall, itmax, rel_tol, seed, nb=500, alpha=1.5,
-              adapt_iters=None, skip=0):
-    """Whole integrator -> dict with estimate, error, chi2_dof, trace and final grid."""
+              adapt_iters=None, skip=0, stream=0):
+    """Whole integrator -> dict with estimate, error, chi2_dof, trace and final grid.
+    `stream` is the second Philox counter word (the integrand's index in a batch)."""
     if adapt_iters is None:
         adapt_iters = itmax
     params, pp = _d(params if params is not None else np.zeros(2 * dim))
@@ -177,7 +179,8 @@ def integrate(family, params, dim, ncall, itmax, rel_tol, seed, nb=500, alpha=1.
     tI = np.zeros(itmax)
     tV = np.zeros(itmax)
     rc = lib().mco_integrate(int(family), int(dim), pp, int(ncall), int(itmax), float(rel_tol),
-                             int(seed), int(nb), float(alpha), int(adapt_iters), int(skip),
+                             int(seed), int(stream), int(nb), float(alpha), int(adapt_iters),
+                             int(skip),
                              res.ctypes.data_as(_dp), info.ctypes.data_as(_i64p),
                              grid.ctypes.data_as(_dp), tI.ctypes.data_as(_dp),
                              tV.ctypes.data_as(_dp))

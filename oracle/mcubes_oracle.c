@@ -419,8 +419,8 @@ int mco_combine(int T, const double *I, const double *var, int skip, double out[
 /*   trace_var (itmax entries, may be NULL) = the per-iteration estimates.   */
 /* ------------------------------------------------------------------------ */
 int mco_integrate(int family, int dim, const double *params, int64_t ncall, int itmax,
-                  double rel_tol, uint64_t seed, int nb, double alpha, int adapt_iters,
-                  int skip, double res[3], int64_t info[7], double *grid_out,
+                  double rel_tol, uint64_t seed, uint32_t stream, int nb, double alpha,
+                  int adapt_iters, int skip, double res[3], int64_t info[7], double *grid_out,
                   double *trace_I, double *trace_var)
 {
     int64_t plan[4];
@@ -443,7 +443,7 @@ int mco_integrate(int family, int dim, const double *params, int64_t ncall, int 
     int rc = 0;
     for (int t = 0; t < itmax; ++t) {
         double sums[2], est[2];
-        rc = mco_sample_range(family, dim, params, nb, plan[0], plan[1], plan[2], seed, 0,
+        rc = mco_sample_range(family, dim, params, nb, plan[0], plan[1], plan[2], seed, stream,
                               (uint32_t)t, grid, 0, plan[1], sums, bins);
         if (rc != 0) break;
         mco_estimates(plan[1], plan[2], sums, est);

@@ -37,8 +37,8 @@ int mco_iteration(int family, int dim, const double *params, int nb, int64_t nca
 int mco_refine(int dim, int nb, double alpha, const double *grid, const double *bins, double *out);
 int mco_combine(int T, const double *I, const double *var, int skip, double out[3]);
 int mco_integrate(int family, int dim, const double *params, int64_t ncall, int itmax,
-                  double rel_tol, uint64_t seed, int nb, double alpha, int adapt_iters,
-                  int skip, double res[3], int64_t info[7], double *grid_out,
+                  double rel_tol, uint64_t seed, uint32_t stream, int nb, double alpha,
+                  int adapt_iters, int skip, double res[3], int64_t info[7], double *grid_out,
                   double *trace_I, double *trace_var);
 
 #endif

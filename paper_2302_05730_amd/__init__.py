@@ -63,6 +63,29 @@ class mcubes_plan_info(ctypes.Structure):
                 ("state_len", ctypes.c_int64)]
 
 
+class mcubes_batch_item(ctypes.Structure):
+    _fields_ = [("family", ctypes.c_int32), ("dim", ctypes.c_int32), ("ncall", ctypes.c_int64),
+                ("params", ctypes.c_double * (2 * MCUBES_MAX_DIM))]
+
+
+class mcubes_batch_info(ctypes.Structure):
+    _fields_ = [("items", ctypes.c_int32), ("classes", ctypes.c_int32),
+                ("tiles", ctypes.c_int32), ("launches", ctypes.c_int32),
+                ("nbins", ctypes.c_int32), ("tuned", ctypes.c_int32),
+                ("grids_len", ctypes.c_int64), ("samples_per_iter", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64), ("last_iterations", ctypes.c_int32),
+                ("last_replans", ctypes.c_int32), ("last_samples", ctypes.c_int64),
+                ("last_ms", ctypes.c_double)]
+
+
+class mcubes_batch_class(ctypes.Structure):
+    _fields_ = [("family", ctypes.c_int32), ("dim", ctypes.c_int32), ("p2", ctypes.c_int32),
+                ("items", ctypes.c_int32), ("block_size", ctypes.c_int32),
+                ("shares", ctypes.c_int32), ("tiles", ctypes.c_int32),
+                ("lds_bytes", ctypes.c_int32), ("samples", ctypes.c_int64),
+                ("tuned_ms", ctypes.c_double)]
+
+
 _dp = ctypes.POINTER(ctypes.c_double)
 _vp = ctypes.c_void_p
 _lib = None
@@ -93,6 +116,19 @@ _SIGNATURES = {
     "mcubes_microbench": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _vp,
                                          ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                          _vp, _vp]),
+    "mcubes_batch_create": (ctypes.c_int, [ctypes.POINTER(mcubes_batch_item), ctypes.c_int,
+                                           ctypes.c_uint64, ctypes.POINTER(mcubes_options),
+                                           ctypes.POINTER(_vp)]),
+    "mcubes_batch_destroy": (None, [_vp]),
+    "mcubes_batch_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(mcubes_batch_info)]),
+    "mcubes_batch_get_class": (ctypes.c_int, [_vp, ctypes.c_int,
+                                              ctypes.POINTER(mcubes_batch_class)]),
+    "mcubes_batch_configure_class": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int,
+                                                    ctypes.c_int]),
+    "mcubes_batch_autotune": (ctypes.c_int, [_vp]),
+    "mcubes_batch_step": (ctypes.c_int, [_vp, ctypes.c_uint32, _dp, _dp]),
+    "mcubes_batch_integrate": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                              ctypes.POINTER(mcubes_result), _dp, _dp]),
 }
 
 
@@ -297,3 +333,114 @@ class Buffers:
         self.partials = z(i["partials_len"])
         self.est = z(2)
         self.state = z(MCUBES_STATE_LEN)
+
+
+class Batch:
+    """Owns an mcubes_batch* (the batched form); destroyed with the object.
+
+    items: sequence of (family, dim, ncall, params) with params the 2*dim
+    values [a..., u...] (None for the addition integrand)."""
+
+    def __init__(self, items, seed, options=None):
+        n = len(items)
+        arr = (mcubes_batch_item * max(n, 1))()
+        for i, (family, dim, ncall, params) in enumerate(items):
+            arr[i].family = int(family)
+            arr[i].dim = int(dim)
+            arr[i].ncall = int(ncall)
+            if params is not None:
+                for q, v in enumerate(list(params)[:2 * int(dim)]):
+                    arr[i].params[q] = float(v)
+        opt = options if options is not None else mcubes_default_options()
+        h = _vp()
+        _check(lib().mcubes_batch_create(arr, int(n), int(seed) & (2**64 - 1), ctypes.byref(opt),
+                                         ctypes.byref(h)))
+        self.handle = h
+        self.n = n
+        self.dims = [int(it[1]) for it in items]
+        self.nbins = opt.nbins
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.mcubes_batch_destroy(self.handle)
+            self.handle = None
+
+    def destroy(self):
+        if self.handle:
+            lib().mcubes_batch_destroy(self.handle)
+            self.handle = None
+
+    def info(self):
+        info = mcubes_batch_info()
+        _check(lib().mcubes_batch_get_info(self.handle, ctypes.byref(info)))
+        return {f: getattr(info, f) for f, _ in mcubes_batch_info._fields_}
+
+    def classes(self):
+        out = []
+        for k in range(self.info()["classes"]):
+            c = mcubes_batch_class()
+            _check(lib().mcubes_batch_get_class(self.handle, k, ctypes.byref(c)))
+            out.append({f: getattr(c, f) for f, _ in mcubes_batch_class._fields_})
+        return out
+
+    def configure_class(self, k, block_size, shares):
+        _check(lib().mcubes_batch_configure_class(self.handle, int(k), int(block_size),
+                                                  int(shares)))
+
+    def autotune(self):
+        _check(lib().mcubes_batch_autotune(self.handle))
+
+    def step(self, iteration, grids):
+        """One iteration from the given grids (one dim x (nbins+1) array-like
+        per integrand) -> (list of (I_t, var_t), list of refined grids)."""
+        import numpy as np
+        nb1 = self.nbins + 1
+        rows = []
+        for i, (g, d) in enumerate(zip(grids, self.dims)):
+            a = np.asarray(g, dtype=np.float64)
+            if a.shape != (d, nb1):
+                raise ValueError(f"grid {i} must have shape {(d, nb1)}, got {a.shape}")
+            rows.append(a.ravel())
+        if len(rows) != self.n:
+            raise ValueError(f"{self.n} grids needed, got {len(rows)}")
+        buf = np.ascontiguousarray(np.concatenate(rows))
+        est = np.zeros(2 * self.n)
+        _check(lib().mcubes_batch_step(self.handle, int(iteration), buf.ctypes.data_as(_dp),
+                                       est.ctypes.data_as(_dp)))
+        out_grids, off = [], 0
+        for d in self.dims:
+            out_grids.append(buf[off:off + d * nb1].reshape(d, nb1).copy())
+            off += d * nb1
+        return [(float(est[2 * i]), float(est[2 * i + 1])) for i in range(self.n)], out_grids
+
+    def integrate(self, itmax, rel_tol, use_graph=True, grids=False, traces=False):
+        """Runs the batch; returns (status, list of per-integrand dicts).  Each
+        dict holds the mcubes_result fields, plus 'grid' (dim rows) and
+        'trace_I' / 'trace_var' when asked for."""
+        n = self.n
+        res = (mcubes_result * n)()
+        glen = self.info()["grids_len"]
+        g_buf = (ctypes.c_double * glen)() if grids else None
+        t_buf = (ctypes.c_double * (n * 2 * itmax))() if traces else None
+        rc = lib().mcubes_batch_integrate(self.handle, int(itmax), float(rel_tol),
+                                          1 if use_graph else 0, res,
+                                          ctypes.cast(g_buf, _dp) if grids else None,
+                                          ctypes.cast(t_buf, _dp) if traces else None)
+        _check(rc, allow=(MCUBES_OK, MCUBES_NOT_CONVERGED, MCUBES_E_NONFINITE))
+        out = []
+        off = 0
+        nb1 = self.nbins + 1
+        for i in range(n):
+            r = {f: getattr(res[i], f) for f, _ in mcubes_result._fields_}
+            r["converged"] = bool(r["converged"])
+            d = self.dims[i]
+            if grids:
+                r["grid"] = [list(g_buf[off + j * nb1:off + (j + 1) * nb1]) for j in range(d)]
+            off += d * nb1
+            if traces:
+                it = r["iterations"]
+                row = t_buf[i * 2 * itmax:(i + 1) * 2 * itmax]
+                r["trace_I"] = [row[2 * t] for t in range(it)]
+                r["trace_var"] = [row[2 * t + 1] for t in range(it)]
+            out.append(r)
+        return rc, out

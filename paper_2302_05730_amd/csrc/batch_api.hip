@@ -1,0 +1,790 @@
+// Host runtime of the batched form (declared in include/mcubes.h): work
+// split into per-class tile lists, graph capture and replay, re-splitting as
+// integrands finish, and the autotuner.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "mcubes_internal.h"
+
+using namespace mcubes;
+
+namespace {
+
+struct ClassKey {
+    int family, dim, p2;
+    bool operator<(const ClassKey &o) const {
+        return std::tie(family, dim, p2) < std::tie(o.family, o.dim, o.p2);
+    }
+};
+
+// Geometry chosen for a class (0 = library default).
+struct ClassCfg {
+    int block = 0, blocks = 0;
+    double tuned_ms = 0.0;
+};
+
+struct ClassPlan {
+    ClassKey key;
+    std::vector<int> items;
+    int block = 0, blocks = 0, max_block = 0;  // blocks = shares
+    size_t lds = 0;
+    const void *func = nullptr;      // kernel with bin sums (occupancy queries)
+    VsTilesLaunchFn launch[2] = {};  // [nobins]
+    uint32_t tile_off = 0;
+    int ntiles = 0;
+    int64_t samples = 0, cubes = 0;
+};
+
+// Default share: at least this many cubes per thread before another block is
+// added to a class.
+constexpr int64_t kDefaultCubesPerThread = 4;
+constexpr int64_t kMaxShares = 1 << 20;
+
+}  // namespace
+
+struct mcubes_batch {
+    int n = 0, nb = 0, adapt_iters = -1, skip = 0, forced_block = 0;
+    double alpha = 1.5;
+    int cus = 0, max_lds = 0;
+    void *user_stream = nullptr;
+    std::vector<BatchItem> items;
+    std::vector<int> family, dim;
+    std::vector<int64_t> g, m, p;
+    std::vector<uint2> axes;
+    std::map<ClassKey, ClassCfg> cfg;
+    std::vector<ClassPlan> plan;
+    std::vector<char> planned;  // items in the current plan
+    int64_t planned_samples = 0;
+    int ntiles = 0;
+    bool tuned = false;
+    int64_t grids_len = 0, bins_len = 0;
+    size_t device_bytes = 0;
+
+    BatchItem *d_items = nullptr;
+    double *d_grids = nullptr, *d_bins = nullptr, *d_est = nullptr, *d_states = nullptr;
+    uint32_t *d_done = nullptr;  // n flags, then the active count
+    uint32_t *d_iter = nullptr;
+    uint2 *d_axes = nullptr;
+    BatchTile *d_tiles = nullptr;
+    double *d_partials = nullptr;
+    size_t cap_tiles = 0;
+    uint32_t *h_done = nullptr;  // pinned, n + 1
+
+    hipStream_t stream = nullptr;
+    hipEvent_t ev[3] = {};
+    hipGraphExec_t exec[2] = {};  // [frozen]
+
+    int last_iterations = 0, last_replans = 0;
+    int64_t last_samples = 0;
+    double last_ms = 0.0;
+};
+
+namespace {
+
+void drop_graphs(mcubes_batch *B) {
+    for (auto &e : B->exec) {
+        if (e) hipGraphExecDestroy(e);
+        e = nullptr;
+    }
+}
+
+void release(mcubes_batch *B) {
+    if (!B) return;
+    drop_graphs(B);
+    for (auto &e : B->ev)
+        if (e) hipEventDestroy(e);
+    if (B->stream) hipStreamDestroy(B->stream);
+    hipFree(B->d_items);
+    hipFree(B->d_grids);
+    hipFree(B->d_bins);
+    hipFree(B->d_est);
+    hipFree(B->d_states);
+    hipFree(B->d_done);
+    hipFree(B->d_iter);
+    hipFree(B->d_axes);
+    hipFree(B->d_tiles);
+    hipFree(B->d_partials);
+    if (B->h_done) hipHostFree(B->h_done);
+    delete B;
+}
+
+template <typename T>
+int device_alloc(mcubes_batch *B, T **ptr, size_t count) {
+    const size_t bytes = (count ? count : 1) * sizeof(T);
+    const hipError_t e = hipMalloc((void **)ptr, bytes);
+    if (e != hipSuccess) return fail(MCUBES_E_ALLOC, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    B->device_bytes += bytes;
+    return MCUBES_OK;
+}
+
+// Blocks of `block` threads of the class kernel resident on the whole device.
+int resident_blocks(const mcubes_batch *B, const ClassPlan &c, int block) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, c.func, block, c.lds) != hipSuccess)
+        return 0;
+    return per_cu * B->cus;
+}
+
+// Splits the class's samples into `shares` equal contiguous shares (in item
+// order, a share ending inside an item at a cube boundary) and appends one
+// tile per (share, item) pair with work.  A tile's partial slot is its index
+// in the batch's tile list; the tiles of an item are consecutive.
+void split_class(const mcubes_batch *B, const ClassPlan &c, int shares,
+                 std::vector<BatchTile> &tiles) {
+    const int k = (int)c.items.size();
+    std::vector<int64_t> off(k + 1, 0);
+    for (int q = 0; q < k; ++q) off[q + 1] = off[q] + B->m[c.items[q]] * B->p[c.items[q]];
+    const int64_t S = off[k];
+    // position of sample offset T: (item slot, first cube starting at or after T)
+    auto position = [&](int64_t T) {
+        int q = (int)(std::upper_bound(off.begin(), off.end(), T) - off.begin()) - 1;
+        if (q >= k) return std::make_pair(k, (int64_t)0);
+        const int i = c.items[q];
+        int64_t w = (T - off[q] + B->p[i] - 1) / B->p[i];
+        if (w >= B->m[i]) return std::make_pair(q + 1, (int64_t)0);
+        return std::make_pair(q, w);
+    };
+    auto lo = position(0);
+    for (int b = 0; b < shares; ++b) {
+        const int64_t Tb = (int64_t)(((unsigned __int128)S * (uint64_t)(b + 1)) / (uint64_t)shares);
+        const auto hi = position(Tb);
+        for (int q = lo.first; q <= hi.first && q < k; ++q) {
+            const int64_t wb = q == lo.first ? lo.second : 0;
+            const int64_t we = q == hi.first ? hi.second : B->m[c.items[q]];
+            if (we > wb) {
+                BatchTile t;
+                t.item = (uint32_t)c.items[q];
+                t.w_begin = (uint32_t)wb;
+                t.w_end = (uint32_t)we;
+                t.partial = (uint32_t)tiles.size();
+                tiles.push_back(t);
+            }
+        }
+        lo = hi;
+    }
+}
+
+// Shares (workgroups before the split at item boundaries) for a class: the
+// configured count, else one per kDefaultCubesPerThread * block cubes but at
+// most one per workgroup slot of the device; never more than the cubes.
+int class_shares(const mcubes_batch *B, const ClassPlan &c, int block, int want) {
+    const int R = resident_blocks(B, c, block);
+    if (R < 1) return 0;
+    int64_t shares = want;
+    if (shares <= 0) {
+        shares = (c.cubes + block * kDefaultCubesPerThread - 1) / (block * kDefaultCubesPerThread);
+        if (shares > R) shares = R;
+    }
+    if (shares > kMaxShares) shares = kMaxShares;
+    if (shares > c.cubes) shares = c.cubes;
+    if (shares < 1) shares = 1;
+    return (int)shares;
+}
+
+void set_item_step(mcubes_batch *B, int i, int block) {
+    VsArgs tmp = B->items[i].args;
+    set_step(tmp, B->dim[i], (uint64_t)block);
+    B->items[i].step_block = tmp.step;
+    memcpy(B->items[i].step_digit_block, tmp.step_digit, sizeof tmp.step_digit);
+}
+
+ClassPlan make_class(const mcubes_batch *B, const ClassKey &key) {
+    ClassPlan c;
+    c.key = key;
+    const VsKernel &K = family_table(key.family)[key.dim];
+    c.func = K.tiles_func[0][key.p2];
+    c.launch[0] = K.tiles_launch[0][key.p2];
+    c.launch[1] = K.tiles_launch[1][key.p2];
+    c.lds = (size_t)(3 * key.dim * B->nb) * sizeof(double);
+    hipFuncAttributes fa;
+    c.max_block = hipFuncGetAttributes(&fa, c.func) == hipSuccess ? fa.maxThreadsPerBlock : 0;
+    return c;
+}
+
+// (Re)builds the plan over the items not yet done: classes, geometry, tiles,
+// and uploads the descriptors.  Invalidates the captured graphs.
+int build_plan(mcubes_batch *B, const std::vector<char> &active) {
+    // the descriptors are overwritten below: nothing may still read them
+    if (B->stream) {
+        const hipError_t es = hipStreamSynchronize(B->stream);
+        if (es != hipSuccess) return hip_fail(es, "hipStreamSynchronize");
+    }
+    drop_graphs(B);
+    std::map<ClassKey, std::vector<int>> groups;
+    for (int i = 0; i < B->n; ++i)
+        if (active[i]) groups[ClassKey{B->family[i], B->dim[i], B->p[i] == 2 ? 1 : 0}].push_back(i);
+    std::vector<ClassPlan> plan;
+    std::vector<BatchTile> tiles;
+    int64_t samples = 0;
+    for (auto &kv : groups) {
+        ClassPlan c = make_class(B, kv.first);
+        c.items = kv.second;
+        for (int i : c.items) {
+            c.cubes += B->m[i];
+            c.samples += B->m[i] * B->p[i];
+        }
+        if (c.max_block < 64) return fail(MCUBES_E_DEVICE, "V-Sample batch kernel unavailable");
+        const ClassCfg &cf = B->cfg[kv.first];
+        int block = B->forced_block ? B->forced_block : (cf.block ? cf.block : c.max_block);
+        if (block > c.max_block) block = c.max_block / 64 * 64;
+        c.block = block;
+        c.blocks = class_shares(B, c, block, cf.blocks);
+        if (c.blocks < 1)
+            return fail(MCUBES_E_ARG, "V-Sample (family %d, dim %d) does not fit: block %d, LDS %zu",
+                        c.key.family, c.key.dim, block, c.lds);
+        for (int i : c.items) set_item_step(B, i, block);
+        c.tile_off = (uint32_t)tiles.size();
+        split_class(B, c, c.blocks, tiles);
+        c.ntiles = (int)(tiles.size() - c.tile_off);
+        samples += c.samples;
+        plan.push_back(std::move(c));
+    }
+    // per-item partial ranges (the tiles of an item are consecutive)
+    for (int i = 0; i < B->n; ++i) B->items[i].part_begin = B->items[i].part_end = 0;
+    std::vector<char> seen(B->n, 0);
+    for (size_t t = 0; t < tiles.size(); ++t) {
+        BatchItem &it = B->items[tiles[t].item];
+        if (!seen[tiles[t].item]) {
+            seen[tiles[t].item] = 1;
+            it.part_begin = tiles[t].partial;
+        } else if (it.part_end != tiles[t].partial) {
+            return fail(MCUBES_E_DEVICE, "internal: tiles of item %u are not consecutive",
+                        tiles[t].item);
+        }
+        it.part_end = tiles[t].partial + 1;
+    }
+    if (tiles.size() > B->cap_tiles) {
+        hipFree(B->d_tiles);
+        hipFree(B->d_partials);
+        B->d_tiles = nullptr;
+        B->d_partials = nullptr;
+        const size_t cap = tiles.size() + tiles.size() / 4 + 64;
+        int rc = device_alloc(B, &B->d_tiles, cap);
+        if (rc == MCUBES_OK) rc = device_alloc(B, &B->d_partials, 2 * cap);
+        if (rc != MCUBES_OK) {
+            B->cap_tiles = 0;
+            return rc;
+        }
+        B->cap_tiles = cap;
+    }
+    hipError_t e = hipMemcpy(B->d_items, B->items.data(), B->items.size() * sizeof(BatchItem),
+                             hipMemcpyHostToDevice);
+    if (e == hipSuccess && !tiles.empty())
+        e = hipMemcpy(B->d_tiles, tiles.data(), tiles.size() * sizeof(BatchTile),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy (batch plan)");
+    B->plan = std::move(plan);
+    B->planned = active;
+    B->planned_samples = samples;
+    B->ntiles = (int)tiles.size();
+    return MCUBES_OK;
+}
+
+hipError_t launch_class(const mcubes_batch *B, const ClassPlan &c, bool frozen, hipStream_t s) {
+    return c.launch[frozen ? 1 : 0](B->d_items, B->d_tiles + c.tile_off, c.ntiles, B->d_grids,
+                                    B->d_bins, B->d_partials, B->d_iter, B->d_done, c.block, c.lds,
+                                    s);
+}
+
+// One iteration: [zero bins] -> V-Sample per class -> reduce -> combine ->
+// [refine] -> advance the iteration counter.  `frozen` = no refinement.
+hipError_t enqueue_iteration(const mcubes_batch *B, bool frozen, double rel_tol, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    if (!frozen) e = launch_fill(B->d_bins, B->bins_len, 0.0, s);
+    for (const ClassPlan &c : B->plan)
+        if (e == hipSuccess) e = launch_class(B, c, frozen, s);
+    if (e == hipSuccess) e = launch_batch_reduce(B->d_items, B->n, B->d_partials, B->d_done, B->d_est, s);
+    if (e == hipSuccess)
+        e = launch_batch_combine(B->n, B->d_est, B->d_states, B->d_done, B->d_done + B->n, B->d_iter,
+                                 B->skip, rel_tol, s);
+    if (e == hipSuccess && !frozen)
+        e = launch_batch_refine(B->d_items, B->d_axes, (int)B->axes.size(), B->d_grids, B->d_bins,
+                                B->d_states, B->d_iter, B->alpha, false, s);
+    if (e == hipSuccess) e = launch_batch_advance(B->d_iter, s);
+    return e;
+}
+
+int capture(mcubes_batch *B, bool frozen, double rel_tol) {
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    const hipError_t el = enqueue_iteration(B, frozen, rel_tol, B->stream);
+    e = hipStreamEndCapture(B->stream, &graph);
+    if (el != hipSuccess) {
+        if (graph) hipGraphDestroy(graph);
+        return hip_fail(el, "batch iteration launch (capture)");
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&B->exec[frozen ? 1 : 0], graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        B->exec[frozen ? 1 : 0] = nullptr;
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    return MCUBES_OK;
+}
+
+// zero bins, one V-Sample per class, reduce, combine, refine, advance
+int launches_per_iteration(const mcubes_batch *B) { return (int)B->plan.size() + 5; }
+
+}  // namespace
+
+extern "C" {
+
+int mcubes_batch_create(const mcubes_batch_item *items, int n, uint64_t seed,
+                        const mcubes_options *opt_in, mcubes_batch **out) {
+    if (!out) return fail(MCUBES_E_ARG, "batch is NULL");
+    if (!items) return fail(MCUBES_E_ARG, "items is NULL");
+    if (n < 1 || n > 65536) return fail(MCUBES_E_ARG, "n must be in [1, 65536], got %d", n);
+    mcubes_options opt;
+    mcubes_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    if (opt.nbins < 2 || opt.nbins > MCUBES_MAX_BINS)
+        return fail(MCUBES_E_ARG, "nbins must be in [2, %d], got %d", MCUBES_MAX_BINS, opt.nbins);
+    if (!(opt.alpha >= 0.0) || !isfinite(opt.alpha))
+        return fail(MCUBES_E_ARG, "alpha must be finite and >= 0");
+    if (opt.skip < 0) return fail(MCUBES_E_ARG, "skip must be >= 0");
+    if (opt.block_size != 0 &&
+        (opt.block_size < 64 || opt.block_size > kMaxBlock || opt.block_size % 64 != 0))
+        return fail(MCUBES_E_ARG, "block_size must be 0 or a multiple of 64 in [64, %d]", kMaxBlock);
+    if (opt.precision != MCUBES_FP64)
+        return fail(MCUBES_E_ARG, "the batched form supports MCUBES_FP64 only");
+    // validate every item before touching the device
+    std::vector<int64_t> sizes(4 * (size_t)n);
+    for (int i = 0; i < n; ++i) {
+        const mcubes_batch_item &it = items[i];
+        int rc = plan_sizes(it.dim, it.ncall, &sizes[4 * (size_t)i]);
+        if (rc == MCUBES_OK) rc = validate_params(it.family, it.params, it.dim);
+        if (rc == MCUBES_OK) rc = check_sizes(sizes[4 * (size_t)i + 1], sizes[4 * (size_t)i + 2], it.dim);
+        if (rc != MCUBES_OK) {
+            const std::string msg = mcubes_last_error();
+            return fail(rc, "item %d: %s", i, msg.c_str());
+        }
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    mcubes_batch *B = new (std::nothrow) mcubes_batch();
+    if (!B) return fail(MCUBES_E_ALLOC, "out of host memory");
+    e = hipDeviceGetAttribute(&B->cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&B->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) {
+        release(B);
+        return hip_fail(e, "hipDeviceGetAttribute");
+    }
+    B->n = n;
+    B->nb = opt.nbins;
+    B->adapt_iters = opt.adapt_iters;
+    B->skip = opt.skip;
+    B->alpha = opt.alpha;
+    B->forced_block = opt.block_size;
+    B->user_stream = opt.stream;
+    B->items.resize(n);
+    B->family.resize(n);
+    B->dim.resize(n);
+    B->g.resize(n);
+    B->m.resize(n);
+    B->p.resize(n);
+    int64_t goff = 0, boff = 0;
+    for (int i = 0; i < n; ++i) {
+        const mcubes_batch_item &it = items[i];
+        const int64_t *sz = &sizes[4 * (size_t)i];
+        B->family[i] = it.family;
+        B->dim[i] = it.dim;
+        B->g[i] = sz[0];
+        B->m[i] = sz[1];
+        B->p[i] = sz[2];
+        BatchItem &bi = B->items[i];
+        memset(&bi, 0, sizeof bi);
+        make_args(it.family, it.params, it.dim, sz[0], sz[1], sz[2], B->nb, seed,
+                  opt.stream_id + (uint32_t)i, bi.args);
+        bi.grid_off = goff;
+        bi.bins_off = boff;
+        bi.dim = it.dim;
+        bi.nb = B->nb;
+        bi.n_samples = (double)sz[1] * (double)sz[2];
+        bi.var_denom = (double)sz[2] * (double)sz[1] * (double)sz[1];
+        goff += (int64_t)it.dim * (B->nb + 1);
+        boff += (int64_t)it.dim * B->nb;
+        for (int j = 0; j < it.dim; ++j) B->axes.push_back(make_uint2((unsigned)i, (unsigned)j));
+    }
+    B->grids_len = goff;
+    B->bins_len = boff;
+    // LDS: every class needs 3 dim nb doubles per block
+    for (int i = 0; i < n; ++i) {
+        const size_t lds = (size_t)(3 * B->dim[i] * B->nb) * sizeof(double);
+        if (lds + 2 * (kMaxBlock / 64) * sizeof(double) > (size_t)B->max_lds) {
+            const int d = B->dim[i];
+            release(B);
+            return fail(MCUBES_E_ARG, "item %d: dim %d with %d bins needs %zu bytes of LDS", i, d,
+                        opt.nbins, lds);
+        }
+        if (lds > 65536) {
+            const VsKernel &K = family_table(B->family[i])[B->dim[i]];
+            for (int nob = 0; nob < 2 && e == hipSuccess; ++nob)
+                for (int p2 = 0; p2 < 2 && e == hipSuccess; ++p2)
+                    e = hipFuncSetAttribute(K.tiles_func[nob][p2],
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) {
+                release(B);
+                return hip_fail(e, "hipFuncSetAttribute");
+            }
+        }
+    }
+    int rc = device_alloc(B, &B->d_items, (size_t)n);
+    if (rc == MCUBES_OK) rc = device_alloc(B, &B->d_grids, (size_t)B->grids_len);
+    if (rc == MCUBES_OK) rc = device_alloc(B, &B->d_bins, (size_t)B->bins_len);
+    if (rc == MCUBES_OK) rc = device_alloc(B, &B->d_est, 2 * (size_t)n);
+    if (rc == MCUBES_OK) rc = device_alloc(B, &B->d_states, (size_t)n * MCUBES_STATE_LEN);
+    if (rc == MCUBES_OK) rc = device_alloc(B, &B->d_done, (size_t)n + 1);
+    if (rc == MCUBES_OK) rc = device_alloc(B, &B->d_iter, 1);
+    if (rc == MCUBES_OK) rc = device_alloc(B, &B->d_axes, B->axes.size());
+    if (rc != MCUBES_OK) {
+        release(B);
+        return rc;
+    }
+    e = hipHostMalloc((void **)&B->h_done, ((size_t)n + 1) * sizeof(uint32_t), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        B->h_done = nullptr;
+        release(B);
+        return fail(MCUBES_E_ALLOC, "hipHostMalloc: %s", hipGetErrorString(e));
+    }
+    e = hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking);
+    for (int q = 0; q < 3 && e == hipSuccess; ++q) e = hipEventCreate(&B->ev[q]);
+    if (e == hipSuccess)
+        e = hipMemcpy(B->d_axes, B->axes.data(), B->axes.size() * sizeof(uint2),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        release(B);
+        return hip_fail(e, "batch set-up");
+    }
+    rc = build_plan(B, std::vector<char>(n, 1));
+    if (rc != MCUBES_OK) {
+        release(B);
+        return rc;
+    }
+    // uniform grids and a clean state, so that the autotuner can run at once
+    e = launch_batch_init_grids(B->d_items, B->d_axes, (int)B->axes.size(), B->d_grids, B->stream);
+    if (e == hipSuccess)
+        e = launch_batch_reset(B->d_states, (int64_t)n * MCUBES_STATE_LEN, B->d_done, n, B->d_iter,
+                               B->stream);
+    if (e == hipSuccess) e = launch_fill(B->d_bins, B->bins_len, 0.0, B->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(B->stream);
+    if (e != hipSuccess) {
+        release(B);
+        return hip_fail(e, "batch initialisation");
+    }
+    *out = B;
+    return MCUBES_OK;
+}
+
+void mcubes_batch_destroy(mcubes_batch *B) {
+    if (B && B->stream) hipStreamSynchronize(B->stream);
+    release(B);
+}
+
+int mcubes_batch_get_info(const mcubes_batch *B, mcubes_batch_info *info) {
+    if (!B || !info) return fail(MCUBES_E_ARG, "NULL argument");
+    info->items = B->n;
+    info->classes = (int32_t)B->plan.size();
+    info->tiles = B->ntiles;
+    info->launches = launches_per_iteration(B);
+    info->nbins = B->nb;
+    info->tuned = B->tuned ? 1 : 0;
+    info->grids_len = B->grids_len;
+    info->samples_per_iter = B->planned_samples;
+    info->device_bytes = (int64_t)B->device_bytes;
+    info->last_iterations = B->last_iterations;
+    info->last_replans = B->last_replans;
+    info->last_samples = B->last_samples;
+    info->last_ms = B->last_ms;
+    return MCUBES_OK;
+}
+
+int mcubes_batch_get_class(const mcubes_batch *B, int k, mcubes_batch_class *out) {
+    if (!B || !out) return fail(MCUBES_E_ARG, "NULL argument");
+    if (k < 0 || k >= (int)B->plan.size())
+        return fail(MCUBES_E_ARG, "class %d out of range [0, %zu)", k, B->plan.size());
+    const ClassPlan &c = B->plan[k];
+    out->family = c.key.family;
+    out->dim = c.key.dim;
+    out->p2 = c.key.p2;
+    out->items = (int32_t)c.items.size();
+    out->block_size = c.block;
+    out->shares = c.blocks;
+    out->tiles = c.ntiles;
+    out->lds_bytes = (int32_t)c.lds;
+    out->samples = c.samples;
+    auto it = B->cfg.find(c.key);
+    out->tuned_ms = it == B->cfg.end() ? 0.0 : it->second.tuned_ms;
+    return MCUBES_OK;
+}
+
+int mcubes_batch_configure_class(mcubes_batch *B, int k, int block_size, int shares) {
+    if (!B) return fail(MCUBES_E_ARG, "NULL argument");
+    if (k < 0 || k >= (int)B->plan.size())
+        return fail(MCUBES_E_ARG, "class %d out of range [0, %zu)", k, B->plan.size());
+    const ClassPlan &c = B->plan[k];
+    if (block_size < 64 || block_size > c.max_block || block_size % 64 != 0)
+        return fail(MCUBES_E_ARG, "block_size must be a multiple of 64 in [64, %d]", c.max_block);
+    if (shares < 1) return fail(MCUBES_E_ARG, "shares must be >= 1");
+    ClassCfg &cf = B->cfg[c.key];
+    cf.block = block_size;
+    cf.blocks = shares;
+    cf.tuned_ms = 0.0;
+    const int saved = B->forced_block;
+    B->forced_block = 0;
+    const std::vector<char> active = B->planned;
+    const int rc = build_plan(B, active);
+    B->forced_block = saved;
+    return rc;
+}
+
+int mcubes_batch_autotune(mcubes_batch *B) {
+    if (!B) return fail(MCUBES_E_ARG, "NULL argument");
+    hipError_t e = hipSuccess;
+    if (B->user_stream) {
+        e = hipEventRecord(B->ev[2], as_stream(B->user_stream));
+        if (e == hipSuccess) e = hipStreamWaitEvent(B->stream, B->ev[2], 0);
+        if (e != hipSuccess) return hip_fail(e, "stream ordering");
+    }
+    const std::vector<char> active = B->planned;
+    std::vector<ClassPlan> classes = B->plan;
+    static const int kBlocks[] = {256, 512, 768, 1024};
+    static const int kCubesPerThread[] = {4, 16, 64};
+    for (const ClassPlan &c0 : classes) {
+        ClassPlan c = c0;
+        double best_ms = -1.0;
+        int best_block = 0, best_blocks = 0;
+        for (int bs : kBlocks) {
+            if (bs > c.max_block || (B->forced_block && bs != B->forced_block)) continue;
+            const int R = resident_blocks(B, c, bs);
+            if (R < 1) continue;
+            std::vector<int> counts = {R, 2 * R, 4 * R};
+            for (int cpt : kCubesPerThread) {
+                int64_t q = (c.cubes + (int64_t)bs * cpt - 1) / ((int64_t)bs * cpt);
+                if (q < 1) q = 1;
+                if (q < R) counts.push_back((int)q);
+            }
+            for (int &q : counts) q = (int)std::min<int64_t>(q, std::min<int64_t>(c.cubes, kMaxShares));
+            std::sort(counts.begin(), counts.end());
+            counts.erase(std::unique(counts.begin(), counts.end()), counts.end());
+            for (int nblk : counts) {
+                ClassCfg &cf = B->cfg[c.key];
+                cf.block = bs;
+                cf.blocks = nblk;
+                const int saved = B->forced_block;
+                B->forced_block = 0;
+                int rc = build_plan(B, active);
+                B->forced_block = saved;
+                if (rc != MCUBES_OK) return rc;
+                const ClassPlan *cp = nullptr;
+                for (const ClassPlan &x : B->plan)
+                    if (!(x.key < c.key) && !(c.key < x.key)) cp = &x;
+                if (!cp) return fail(MCUBES_E_DEVICE, "internal: class lost while tuning");
+                e = launch_class(B, *cp, false, B->stream);  // warm-up
+                if (e == hipSuccess) e = hipEventRecord(B->ev[0], B->stream);
+                for (int r = 0; r < 2 && e == hipSuccess; ++r) e = launch_class(B, *cp, false, B->stream);
+                if (e == hipSuccess) e = hipEventRecord(B->ev[1], B->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(B->ev[1]);
+                float ms = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, B->ev[0], B->ev[1]);
+                if (e != hipSuccess) return hip_fail(e, "autotune launch");
+                const double t = ms / 2.0;
+                if (best_ms < 0.0 || t < best_ms) {
+                    best_ms = t;
+                    best_block = bs;
+                    best_blocks = nblk;
+                }
+            }
+        }
+        if (best_ms < 0.0)
+            return fail(MCUBES_E_DEVICE, "no launch geometry fits class (family %d, dim %d)",
+                        c.key.family, c.key.dim);
+        ClassCfg &cf = B->cfg[c.key];
+        cf.block = best_block;
+        cf.blocks = best_blocks;
+        cf.tuned_ms = best_ms;
+    }
+    const int saved = B->forced_block;
+    B->forced_block = 0;
+    const int rc = build_plan(B, active);
+    B->forced_block = saved;
+    if (rc != MCUBES_OK) return rc;
+    // the tuning launches added to the bin sums and partials: start clean
+    e = launch_fill(B->d_bins, B->bins_len, 0.0, B->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(B->stream);
+    if (e != hipSuccess) return hip_fail(e, "autotune");
+    B->tuned = true;
+    return MCUBES_OK;
+}
+
+int mcubes_batch_step(mcubes_batch *B, uint32_t iteration, double *grids, double *est) {
+    if (!B || !grids || !est) return fail(MCUBES_E_ARG, "NULL argument");
+    if (iteration >= MCUBES_MAX_ITERATIONS)
+        return fail(MCUBES_E_ARG, "iteration %u >= %d", iteration, MCUBES_MAX_ITERATIONS);
+    // host-side check of the grids: the kernels assume monotone edges 0 .. 1
+    const int64_t nb1 = B->nb + 1;
+    for (int64_t r = 0; r < B->grids_len / nb1; ++r) {
+        const double *row = grids + r * nb1;
+        if (row[0] != 0.0 || row[B->nb] != 1.0)
+            return fail(MCUBES_E_ARG, "grid row %lld must run from 0 to 1", (long long)r);
+        for (int i = 0; i < B->nb; ++i)
+            if (!(row[i + 1] >= row[i]))
+                return fail(MCUBES_E_ARG, "grid row %lld is not monotone", (long long)r);
+    }
+    hipStream_t s = B->stream;
+    hipError_t e = hipSuccess;
+    if (B->user_stream) {
+        e = hipEventRecord(B->ev[2], as_stream(B->user_stream));
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, B->ev[2], 0);
+        if (e != hipSuccess) return hip_fail(e, "stream ordering");
+    }
+    const std::vector<char> all(B->n, 1);
+    if (B->planned != all) {
+        const int rc = build_plan(B, all);
+        if (rc != MCUBES_OK) return rc;
+    }
+    e = launch_batch_reset(B->d_states, (int64_t)B->n * MCUBES_STATE_LEN, B->d_done, B->n,
+                           B->d_iter, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(B->d_iter, &iteration, sizeof iteration, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(B->d_grids, grids, (size_t)B->grids_len * sizeof(double),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_fill(B->d_bins, B->bins_len, 0.0, s);
+    for (const ClassPlan &c : B->plan)
+        if (e == hipSuccess) e = launch_class(B, c, false, s);
+    if (e == hipSuccess) e = launch_batch_reduce(B->d_items, B->n, B->d_partials, B->d_done, B->d_est, s);
+    if (e == hipSuccess)
+        e = launch_batch_refine(B->d_items, B->d_axes, (int)B->axes.size(), B->d_grids, B->d_bins,
+                                B->d_states, B->d_iter, B->alpha, true, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(est, B->d_est, 2 * (size_t)B->n * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(grids, B->d_grids, (size_t)B->grids_len * sizeof(double),
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? MCUBES_OK : hip_fail(e, "batch step");
+}
+
+int mcubes_batch_integrate(mcubes_batch *B, int itmax, double rel_tol, int use_graph,
+                           mcubes_result *results, double *grids_out, double *traces) {
+    if (!B || !results) return fail(MCUBES_E_ARG, "NULL argument");
+    if (itmax < 1 || itmax > MCUBES_MAX_ITERATIONS)
+        return fail(MCUBES_E_ARG, "itmax must be in [1, %d]", MCUBES_MAX_ITERATIONS);
+    if (!(rel_tol >= 0.0) || !isfinite(rel_tol))
+        return fail(MCUBES_E_ARG, "rel_tol must be finite and >= 0");
+    const int n = B->n;
+    hipStream_t s = B->stream;
+    hipError_t e = hipSuccess;
+    int rc = MCUBES_OK;
+    if (B->user_stream) {
+        e = hipEventRecord(B->ev[2], as_stream(B->user_stream));
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, B->ev[2], 0);
+        if (e != hipSuccess) return hip_fail(e, "stream ordering");
+    }
+    std::vector<char> active(n, 1);
+    if (B->planned != active) {
+        rc = build_plan(B, active);
+        if (rc != MCUBES_OK) return rc;
+    }
+    // graphs bake rel_tol in: capture afresh for every call
+    drop_graphs(B);
+    e = launch_batch_init_grids(B->d_items, B->d_axes, (int)B->axes.size(), B->d_grids, s);
+    if (e == hipSuccess)
+        e = launch_batch_reset(B->d_states, (int64_t)n * MCUBES_STATE_LEN, B->d_done, n, B->d_iter, s);
+    if (e != hipSuccess) return hip_fail(e, "batch reset");
+    int replans = 0, iterations = 0;
+    int64_t samples = 0, running = 0;
+    for (int i = 0; i < n; ++i) running += B->m[i] * B->p[i];
+    e = hipEventRecord(B->ev[0], s);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    for (int t = 0; t < itmax; ++t) {
+        const bool frozen = B->adapt_iters >= 0 && t >= B->adapt_iters;
+        if (use_graph) {
+            if (!B->exec[frozen ? 1 : 0]) {
+                rc = capture(B, frozen, rel_tol);
+                if (rc != MCUBES_OK) return rc;
+            }
+            e = hipGraphLaunch(B->exec[frozen ? 1 : 0], s);
+            if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+        } else {
+            e = enqueue_iteration(B, frozen, rel_tol, s);
+            if (e != hipSuccess) return hip_fail(e, "batch iteration launch");
+        }
+        samples += running;  // integrands not done when iteration t starts
+        iterations = t + 1;
+        e = hipMemcpyAsync(B->h_done, B->d_done, ((size_t)n + 1) * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "batch flags");
+        if (B->h_done[n] == 0u) break;
+        // re-split the remaining work once a noticeable share has finished
+        int64_t left = 0;
+        for (int i = 0; i < n; ++i) {
+            active[i] = B->h_done[i] == 0u;
+            if (active[i]) left += B->m[i] * B->p[i];
+        }
+        running = left;
+        if (t + 1 < itmax && left < B->planned_samples - B->planned_samples / 50) {
+            rc = build_plan(B, active);
+            if (rc != MCUBES_OK) return rc;
+            ++replans;
+        }
+    }
+    e = hipEventRecord(B->ev[1], s);
+    if (e == hipSuccess) e = hipEventSynchronize(B->ev[1]);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, B->ev[0], B->ev[1]);
+    if (e != hipSuccess) return hip_fail(e, "batch timing");
+    std::vector<double> head((size_t)n * MCUBES_STATE_HEADER);
+    e = hipMemcpy2D(head.data(), MCUBES_STATE_HEADER * sizeof(double), B->d_states,
+                    MCUBES_STATE_LEN * sizeof(double), MCUBES_STATE_HEADER * sizeof(double), n,
+                    hipMemcpyDeviceToHost);
+    if (e == hipSuccess && traces)
+        e = hipMemcpy2D(traces, 2 * (size_t)itmax * sizeof(double),
+                        B->d_states + MCUBES_STATE_HEADER, MCUBES_STATE_LEN * sizeof(double),
+                        2 * (size_t)itmax * sizeof(double), n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && grids_out)
+        e = hipMemcpy(grids_out, B->d_grids, (size_t)B->grids_len * sizeof(double),
+                      hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "batch results");
+    int status = MCUBES_OK;
+    for (int i = 0; i < n; ++i) {
+        const double *h = &head[(size_t)i * MCUBES_STATE_HEADER];
+        mcubes_result &r = results[i];
+        r.estimate = h[0];
+        r.error = h[1];
+        r.chi2_dof = h[2];
+        r.dof = (int32_t)h[3];
+        r.iterations = (int32_t)h[4];
+        r.converged = h[5] != 0.0;
+        r.status = h[6] != 0.0 ? MCUBES_E_NONFINITE : (r.converged ? MCUBES_OK : MCUBES_NOT_CONVERGED);
+        r.cube_side = B->g[i];
+        r.ncubes = B->m[i];
+        r.samples_per_cube = B->p[i];
+        r.samples_per_iter = B->m[i] * B->p[i];
+        r.kernel_ms = 0.0;
+        if (r.status == MCUBES_E_NONFINITE)
+            status = MCUBES_E_NONFINITE;
+        else if (r.status == MCUBES_NOT_CONVERGED && status == MCUBES_OK)
+            status = MCUBES_NOT_CONVERGED;
+    }
+    B->last_iterations = iterations;
+    B->last_replans = replans;
+    B->last_samples = samples;
+    B->last_ms = ms;
+    if (status == MCUBES_E_NONFINITE) fail(status, "some integrand produced a non-finite estimate");
+    return status;
+}
+
+}  // extern "C"

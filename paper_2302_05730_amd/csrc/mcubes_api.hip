@@ -24,8 +24,10 @@ struct mcubes_plan {
 };
 
 namespace {
-
 thread_local std::string g_error;
+}  // namespace
+
+namespace mcubes {
 
 int fail(int code, const char *fmt, ...) {
     char buf[512];
@@ -123,7 +125,50 @@ void fold_params(int family, const double *params, int dim, VsArgs &A) {
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
-}  // namespace
+void set_step(VsArgs &A, int dim, uint64_t threads) {
+    const uint64_t step = (uint64_t)(((unsigned __int128)threads * A.mult) % A.m);
+    A.step = (uint32_t)step;
+    uint64_t rest = step;
+    for (int j = 0; j < kMaxDim; ++j) {
+        A.step_digit[j] = j < dim ? (uint32_t)(rest % A.g) : 0u;
+        if (j < dim) rest /= A.g;
+    }
+}
+
+void make_args(int family, const double *params, int dim, int64_t g, int64_t m, int64_t p, int nb,
+               uint64_t seed, uint32_t stream_id, VsArgs &A) {
+    memset(&A, 0, sizeof A);
+    fold_params(family, params, dim, A);
+    A.zscale = ((double)nb / (double)g) * 0x1p-32;
+    double nbd = (double)nb;
+    for (int j = 1; j < dim; ++j) nbd = nbd * (double)nb;
+    A.nbd = nbd;
+    A.inv_p = 1.0 / (double)p;
+    A.inv_pm1 = 1.0 / (double)(p - 1);
+    A.key0 = (uint32_t)(seed & 0xffffffffu);
+    A.key1 = (uint32_t)(seed >> 32);
+    A.stream_id = stream_id;
+    A.iteration = 0;
+    A.g = (uint32_t)g;
+    A.m = (uint32_t)m;
+    A.p = (uint32_t)p;
+    A.nb = (uint32_t)nb;
+    // cube permutation multiplier: near m (sqrt(5)-1)/2, coprime to g (hence to m = g^d)
+    int64_t mult = (int64_t)floor((double)m * 0.6180339887498949);
+    if (mult < 1) mult = 1;
+    while (gcd64(mult, g) != 1) ++mult;
+    mult %= m;
+    if (m == 1) mult = 0;
+    A.mult = (uint32_t)mult;
+}
+
+int check_sizes(int64_t m, int64_t p, int dim) {
+    if (m > 0xFFFFFFFFll) return fail(MCUBES_E_ARG, "too many cubes (%lld >= 2^32)", (long long)m);
+    if (p * ((dim + 3) / 4) > 0xFFFFFFFFll) return fail(MCUBES_E_ARG, "too many samples per cube");
+    return MCUBES_OK;
+}
+
+}  // namespace mcubes
 
 extern "C" {
 
@@ -174,9 +219,8 @@ int mcubes_plan_create(int family, const double *params, int dim, int64_t ncall,
     if (opt.precision != MCUBES_FP64 && opt.precision != MCUBES_FP32)
         return fail(MCUBES_E_ARG, "precision must be MCUBES_FP64 or MCUBES_FP32");
     const int64_t g = sz[0], m = sz[1], p = sz[2];
-    const int nblk = (dim + 3) / 4;
-    if (m > 0xFFFFFFFFll) return fail(MCUBES_E_ARG, "too many cubes (%lld >= 2^32)", (long long)m);
-    if (p * nblk > 0xFFFFFFFFll) return fail(MCUBES_E_ARG, "too many samples per cube");
+    rc = check_sizes(m, p, dim);
+    if (rc != MCUBES_OK) return rc;
 
     // device and launch geometry
     int dev = 0;
@@ -244,38 +288,8 @@ int mcubes_plan_create(int family, const double *params, int dim, int64_t ncall,
     P->launch[1] = kern_set.launch[prec][0][variant];
     P->func = kfunc;
 
-    VsArgs &A = P->args;
-    memset(&A, 0, sizeof A);
-    fold_params(family, params, dim, A);
-    A.zscale = ((double)nb / (double)g) * 0x1p-32;
-    double nbd = (double)nb;
-    for (int j = 1; j < dim; ++j) nbd = nbd * (double)nb;
-    A.nbd = nbd;
-    A.inv_p = 1.0 / (double)p;
-    A.inv_pm1 = 1.0 / (double)(p - 1);
-    A.key0 = (uint32_t)(seed & 0xffffffffu);
-    A.key1 = (uint32_t)(seed >> 32);
-    A.stream_id = opt.stream_id;
-    A.iteration = 0;
-    A.g = (uint32_t)g;
-    A.m = (uint32_t)m;
-    A.p = (uint32_t)p;
-    A.nb = (uint32_t)nb;
-    // cube permutation multiplier: near m (sqrt(5)-1)/2, coprime to g (hence to m = g^d)
-    int64_t mult = (int64_t)floor((double)m * 0.6180339887498949);
-    if (mult < 1) mult = 1;
-    while (gcd64(mult, g) != 1) ++mult;
-    mult %= m;
-    if (m == 1) mult = 0;
-    A.mult = (uint32_t)mult;
-    const int64_t threads = blocks * block;
-    const int64_t step = (int64_t)(((unsigned __int128)threads * (uint64_t)mult) % (uint64_t)m);
-    A.step = (uint32_t)step;
-    int64_t rest = step;
-    for (int j = 0; j < kMaxDim; ++j) {
-        A.step_digit[j] = j < dim ? (uint32_t)(rest % g) : 0u;
-        if (j < dim) rest /= g;
-    }
+    make_args(family, params, dim, g, m, p, nb, seed, opt.stream_id, P->args);
+    set_step(P->args, dim, (uint64_t)blocks * (uint64_t)block);
     *plan_out = P;
     return MCUBES_OK;
 }

@@ -42,6 +42,29 @@ typedef hipError_t (*VsLaunchFn)(const VsArgs &args, const double *grid, double 
                                  double *partials, int blocks, int block, size_t lds,
                                  hipStream_t stream);
 
+// Batched form: one integrand of a batch (device-resident descriptor) and one
+// tile of work (a range of permuted work items of one integrand).
+struct BatchItem {
+    VsArgs args;                         // folded problem (iteration is read elsewhere)
+    uint32_t step_block;                 // (block * mult) mod m for the class kernel's block
+    uint32_t step_digit_block[kMaxDim];  // its base-g digits
+    int64_t grid_off, bins_off;          // offsets (doubles) into the packed grids / bins
+    uint32_t part_begin, part_end;       // the item's partials (one per tile)
+    int32_t dim, nb;
+    double n_samples, var_denom;         // N = m p and p m^2
+};
+
+// Work items [w_begin, w_end) of integrand `item`; its (sum S_c, sum var_c)
+// go to partials[2 partial], [2 partial + 1].
+struct BatchTile {
+    uint32_t item, w_begin, w_end, partial;
+};
+
+typedef hipError_t (*VsTilesLaunchFn)(const BatchItem *items, const BatchTile *tiles, int ntiles,
+                                      const double *grids, double *bins, double *partials,
+                                      const uint32_t *iter, const uint32_t *done, int block,
+                                      size_t lds, hipStream_t stream);
+
 // Eight variants per (family, dim): [fp32][nobins][p2] with fp32 = 1 for the
 // FP32 map/integrand form, nobins = 1 when the bin sums are not wanted (no
 // later refinement) and p2 = 1 for p = 2 (both samples of a cube in
@@ -49,6 +72,8 @@ typedef hipError_t (*VsLaunchFn)(const VsArgs &args, const double *grid, double 
 struct VsKernel {
     VsLaunchFn launch[2][2][2];
     const void *func[2][2][2];  // kernel symbols, for occupancy queries and attributes
+    VsTilesLaunchFn tiles_launch[2][2];  // batched form, [nobins][p2]
+    const void *tiles_func[2][2];
 };
 
 // Per-family tables, index = dim (1..kMaxDim); defined in vsample_f<family>.hip.
@@ -70,6 +95,38 @@ hipError_t launch_combine(const double *est, double *state, uint32_t iteration, 
 hipError_t launch_refine(const double *grid, const double *bins, double *grid_out, int dim, int nb,
                          double alpha, hipStream_t stream);
 hipError_t launch_copy(const double *src, double *dst, int64_t n, hipStream_t stream);
+
+// Batched support kernels (batch.hip).  done[i] != 0 marks integrand i as
+// finished (converged or non-finite): it is no longer sampled or combined.
+hipError_t launch_batch_reset(double *states, int64_t state_len, uint32_t *done, int n,
+                              uint32_t *iter, hipStream_t stream);
+hipError_t launch_batch_reduce(const BatchItem *items, int n, const double *partials,
+                               const uint32_t *done, double *est, hipStream_t stream);
+hipError_t launch_batch_combine(int n, const double *est, double *states, uint32_t *done,
+                                uint32_t *active, const uint32_t *iter, int skip, double rel_tol,
+                                hipStream_t stream);
+hipError_t launch_batch_refine(const BatchItem *items, const uint2 *axes, int naxes,
+                               double *grids, const double *bins, const double *states,
+                               const uint32_t *iter, double alpha, bool all, hipStream_t stream);
+hipError_t launch_batch_init_grids(const BatchItem *items, const uint2 *axes, int naxes,
+                                   double *grids, hipStream_t stream);
+hipError_t launch_batch_advance(uint32_t *iter, hipStream_t stream);
+
+// Host helpers (mcubes_api.hip).  fail() records a message for
+// mcubes_last_error() and returns `code`.
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+const VsKernel *family_table(int family);
+int plan_sizes(int dim, int64_t ncall, int64_t out[4]);
+int validate_params(int family, const double *params, int dim);
+int check_sizes(int64_t m, int64_t p, int dim);
+// Folded problem for V-Sample (step and step digits left zero).
+void make_args(int family, const double *params, int dim, int64_t g, int64_t m, int64_t p, int nb,
+               uint64_t seed, uint32_t stream_id, VsArgs &A);
+// step = (threads * mult) mod m and its base-g digits: the advance of a work
+// item when `threads` threads stride over the work items.
+void set_step(VsArgs &A, int dim, uint64_t threads);
+hipStream_t as_stream(void *s);
 
 // Microbenchmarks (microbench.hip).
 hipError_t launch_microbench(int kind, int family, int dim, const VsArgs &A, const double *pts,

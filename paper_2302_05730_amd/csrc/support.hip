@@ -2,7 +2,7 @@
 // the iteration combination, the VEGAS grid refinement, fills and copies.
 #include <math.h>
 
-#include "mcubes_internal.h"
+#include "support_impl.h"
 
 namespace mcubes {
 
@@ -59,138 +59,18 @@ __global__ __launch_bounds__(256) void reduce_kernel(const double *__restrict__ 
 __global__ void combine_kernel(const double *__restrict__ est, double *__restrict__ state,
                                uint32_t t, int skip, double rel_tol) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double *hist = state + MCUBES_STATE_HEADER;
-    const double It = est[0], Vt = est[1];
-    hist[2 * t] = It;
-    hist[2 * t + 1] = Vt;
-    if (!isfinite(It) || !isfinite(Vt)) state[6] = 1.0;
-    const int T = (int)t + 1;
-    state[4] = (double)T;
-    const int n = T - skip;
-    double Ibar = 0.0, sigma = INFINITY, chi2dof = 0.0;
-    int dof = 0;
-    if (n >= 1) {
-        double sw = 0.0, swi = 0.0;
-        int exact = -1;
-        for (int q = skip; q < T; ++q) {
-            const double v = hist[2 * q + 1];
-            if (v == 0.0) {
-                exact = q;
-            } else {
-                sw = sw + 1.0 / v;
-                swi = swi + hist[2 * q] / v;
-            }
-        }
-        dof = n - 1;
-        if (exact >= 0) {
-            Ibar = hist[2 * exact];
-            sigma = 0.0;
-        } else {
-            Ibar = swi / sw;
-            double chi2 = 0.0;
-            for (int q = skip; q < T; ++q) {
-                const double dv = hist[2 * q] - Ibar;
-                chi2 = chi2 + dv * dv / hist[2 * q + 1];
-            }
-            sigma = 1.0 / sqrt(sw);
-            chi2dof = n > 1 ? chi2 / (double)(n - 1) : 0.0;
-        }
-    }
-    state[0] = Ibar;
-    state[1] = sigma;
-    state[2] = chi2dof;
-    state[3] = (double)dof;
-    state[5] = (n >= 1 && sigma <= rel_tol * fabs(Ibar)) ? 1.0 : 0.0;
+    combine_state(est[0], est[1], state, t, skip, rel_tol);
 }
 
-// VEGAS rebinning, one block per axis, one thread per bin.  The two running
-// sums (total smoothed weight, cumulative damped weight) are taken in bin
-// order by one thread so that they round exactly like a sequential loop; the
-// damping (log, pow) and the placement of the new edges run in parallel.  New
-// edge k lies in the first old bin i whose cumulative damped weight reaches
-// k T, found by binary search.
+// VEGAS rebinning, one block per axis.
 __global__ __launch_bounds__(512) void refine_kernel(const double *__restrict__ grid,
                                                      const double *__restrict__ bins,
                                                      double *__restrict__ grid_out, int nb,
                                                      double alpha) {
-    __shared__ double sE[kMaxBins + 1], sd[kMaxBins], ss[kMaxBins], sr[kMaxBins],
-        sR[kMaxBins + 1];
-    __shared__ double sTot;
+    __shared__ RefineLds lds;
     const int j = blockIdx.x;
-    const int k = threadIdx.x;
-    const double *E = grid + (size_t)j * (nb + 1);
-    const double *dj = bins + (size_t)j * nb;
-    double *En = grid_out + (size_t)j * (nb + 1);
-
-    if (k <= nb) sE[k] = E[k];
-    if (k < nb) sd[k] = dj[k];
-    __syncthreads();
-    if (k < nb) {
-        double s;
-        if (k == 0)
-            s = (sd[0] + sd[1]) / 2.0;
-        else if (k == nb - 1)
-            s = (sd[nb - 2] + sd[nb - 1]) / 2.0;
-        else
-            s = (sd[k - 1] + sd[k] + sd[k + 1]) / 3.0;
-        ss[k] = s;
-    }
-    __syncthreads();
-    if (k == 0) {
-        double S = 0.0;
-        for (int i = 0; i < nb; ++i) S = S + ss[i];
-        sTot = S;
-    }
-    __syncthreads();
-    const double S = sTot;
-    if (!(S > 0.0)) {  // no weight on this axis: keep it
-        if (k <= nb) En[k] = sE[k];
-        return;
-    }
-    if (k < nb) {
-        const double s = ss[k];
-        const double rho = s / S;
-        double r;
-        if (s == 0.0)
-            r = 0.0;
-        else if (rho == 1.0)
-            r = 1.0;
-        else
-            r = pow((rho - 1.0) / log(rho), alpha);
-        sr[k] = r;
-    }
-    __syncthreads();
-    if (k == 0) {
-        double R = 0.0;
-        sR[0] = 0.0;
-        for (int i = 0; i < nb; ++i) {
-            R = R + sr[i];
-            sR[i + 1] = R;
-        }
-    }
-    __syncthreads();
-    const double T = sR[nb] / (double)nb;
-    if (k == 0) {
-        En[0] = 0.0;
-        En[nb] = 1.0;
-    } else if (k < nb) {
-        const double target = (double)k * T;
-        // first q in [1, nb] with R[q] >= target (nb if none), bin i = q - 1
-        int lo = 1, hi = nb;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (sR[mid] >= target)
-                hi = mid;
-            else
-                lo = mid + 1;
-        }
-        const int i = lo - 1;
-        const double W = sE[i + 1] - sE[i];
-        double frac = (target - sR[i]) / sr[i];
-        if (frac > 1.0) frac = 1.0;
-        const double e = sE[i] + frac * W;
-        En[k] = e < sE[i + 1] ? e : sE[i + 1];
-    }
+    refine_axis(grid + (size_t)j * (nb + 1), bins + (size_t)j * nb, grid_out + (size_t)j * (nb + 1),
+                nb, alpha, lds);
 }
 
 }  // namespace

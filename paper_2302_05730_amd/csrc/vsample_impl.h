@@ -240,8 +240,8 @@ constexpr bool table_from_l1(int j) {
 }
 
 template <int F, int D>
-__device__ __forceinline__ double draw(const VsArgs &A, const double *ca, const double *cu,
-                                       uint32_t c, uint32_t k, const double *cb,
+__device__ __forceinline__ double draw(const VsArgs &A, uint32_t iteration, const double *ca,
+                                       const double *cu, uint32_t c, uint32_t k, const double *cb,
                                        const double2 *sEW, const double *__restrict__ grid,
                                        int nb, int *bin) {
     constexpr int NBLK = (D + 3) / 4;  // Philox blocks (4 words each) per sample
@@ -254,7 +254,7 @@ __device__ __forceinline__ double draw(const VsArgs &A, const double *ca, const 
 #pragma unroll
     for (int b = 0; b < NBLK; ++b) {
         uint32_t r[4];
-        philox10(c, A.stream_id, k * NBLK + b, A.iteration, A.key0, A.key1, r);
+        philox10(c, A.stream_id, k * NBLK + b, iteration, A.key0, A.key1, r);
         double phi[4];
         double2 ew[4];
 #pragma unroll
@@ -312,8 +312,9 @@ __device__ __forceinline__ double draw(const VsArgs &A, const double *ca, const 
 // in FP64 from the same FP32 widths the map uses, and the weight is returned
 // in FP64.
 template <int F, int D>
-__device__ __forceinline__ double draw32(const VsArgs &A, const float *ca, const float *cu,
-                                         float phase, uint32_t c, uint32_t k, const double *cb,
+__device__ __forceinline__ double draw32(const VsArgs &A, uint32_t iteration, const float *ca,
+                                         const float *cu, float phase, uint32_t c, uint32_t k,
+                                         const double *cb,
                                          const float2 *sEW, int nb, int *bin) {
     constexpr int NBLK = (D + 3) / 4;
     Acc32 acc = Family32<F, D>::begin(phase);
@@ -321,7 +322,7 @@ __device__ __forceinline__ double draw32(const VsArgs &A, const float *ca, const
 #pragma unroll
     for (int b = 0; b < NBLK; ++b) {
         uint32_t r[4];
-        philox10(c, A.stream_id, k * NBLK + b, A.iteration, A.key0, A.key1, r);
+        philox10(c, A.stream_id, k * NBLK + b, iteration, A.key0, A.key1, r);
         float phi[4];
         float2 ew[4];
 #pragma unroll
@@ -366,15 +367,20 @@ constexpr int vs_max_block() {
     return (D >= 9 || (F == MCUBES_DISCONTINUOUS && D >= 8)) ? 768 : 1024;
 }
 
+// The work of one block on a set of work items of one integrand: thread t
+// handles `count` work items w0, w0 + stride, ... (cube (w * mult) mod m each;
+// `step` = (stride * mult) mod m and its base-g digits advance the cube).
+// Stages the grid into LDS, samples, reduces the block's (sum S_c, sum var_c)
+// into partial[0..1] and flushes the block's bin sums into `bins`.  Callable
+// repeatedly by a block (it synchronises before restaging).
 template <int F, int D, bool P2, bool BINS, bool F32>
-__global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_kernel(const VsArgs A,
-                                                           const double *__restrict__ grid,
-                                                           double *__restrict__ bins,
-                                                           double *__restrict__ partials) {
-    extern __shared__ double smem[];
-    __shared__ double red[2][kMaxBlock / 64];
-    __shared__ double scoef[2 * kMaxDim];
-
+__device__ __forceinline__ void vs_block(const VsArgs &A, const double *__restrict__ grid,
+                                         double *__restrict__ bins, double *__restrict__ partial,
+                                         uint32_t w0, uint32_t stride, uint32_t count,
+                                         uint32_t step, const uint32_t *step_digit,
+                                         uint32_t iteration, double *smem,
+                                         double (*red)[kMaxBlock / 64], double *scoef) {
+    __syncthreads();  // a previous call may still read the LDS tables
     const int nb = (int)A.nb;
     const int nh = D * nb;
     if (threadIdx.x < D) {
@@ -413,13 +419,10 @@ __global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_kernel(const V
     }
     const float phase32 = (float)A.phase;
 
-    const uint32_t T = gridDim.x * blockDim.x;
-    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     double tS = 0.0, tV = 0.0;
 
-    if (tid < A.m) {
-        const uint32_t count = (A.m - 1u - tid) / T + 1u;
-        uint32_t c = (uint32_t)(((uint64_t)tid * (uint64_t)A.mult) % (uint64_t)A.m);
+    if (count > 0) {
+        uint32_t c = (uint32_t)(((uint64_t)w0 * (uint64_t)A.mult) % (uint64_t)A.m);
         uint32_t dig[D];
         {
             uint32_t rest = c;
@@ -440,8 +443,8 @@ __global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_kernel(const V
                 // D2 = dlt^2, and var_c = D2 - D1^2/2 = dlt^2 / 2.
                 int bin[D];
                 const double wa =
-                    F32 ? draw32<F, D>(A, ca32, cu32, phase32, c, 0, cb, sEW32, nb, bin)
-                        : draw<F, D>(A, ca, cu, c, 0, cb, sEW, grid, nb, bin);
+                    F32 ? draw32<F, D>(A, iteration, ca32, cu32, phase32, c, 0, cb, sEW32, nb, bin)
+                        : draw<F, D>(A, iteration, ca, cu, c, 0, cb, sEW, grid, nb, bin);
                 if constexpr (BINS) {
                     const double w2a = wa * wa;
 #pragma unroll
@@ -451,8 +454,8 @@ __global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_kernel(const V
                 // 1024 threads per block)
                 __builtin_amdgcn_sched_barrier(0);
                 const double wb =
-                    F32 ? draw32<F, D>(A, ca32, cu32, phase32, c, 1, cb, sEW32, nb, bin)
-                        : draw<F, D>(A, ca, cu, c, 1, cb, sEW, grid, nb, bin);
+                    F32 ? draw32<F, D>(A, iteration, ca32, cu32, phase32, c, 1, cb, sEW32, nb, bin)
+                        : draw<F, D>(A, iteration, ca, cu, c, 1, cb, sEW, grid, nb, bin);
                 if constexpr (BINS) {
                     const double w2b = wb * wb;
 #pragma unroll
@@ -467,8 +470,8 @@ __global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_kernel(const V
                 for (uint32_t k = 0; k < A.p; ++k) {
                     int bin[D];
                     const double w =
-                        F32 ? draw32<F, D>(A, ca32, cu32, phase32, c, k, cb, sEW32, nb, bin)
-                            : draw<F, D>(A, ca, cu, c, k, cb, sEW, grid, nb, bin);
+                        F32 ? draw32<F, D>(A, iteration, ca32, cu32, phase32, c, k, cb, sEW32, nb, bin)
+                            : draw<F, D>(A, iteration, ca, cu, c, k, cb, sEW, grid, nb, bin);
                     S = S + w;
                     if (k == 0) w0 = w;
                     const double dlt = w - w0;
@@ -485,13 +488,13 @@ __global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_kernel(const V
             }
 
             // advance to the next work item: linear id and digits by `step`
-            uint32_t cn = c + A.step;
+            uint32_t cn = c + step;
             if (cn < c || cn >= A.m) cn -= A.m;
             c = cn;
             uint32_t carry = 0;
 #pragma unroll
             for (int j = 0; j < D; ++j) {
-                const uint32_t t = dig[j] + A.step_digit[j] + carry;
+                const uint32_t t = dig[j] + step_digit[j] + carry;
                 carry = t >= A.g ? 1u : 0u;
                 dig[j] = carry ? t - A.g : t;
             }
@@ -515,8 +518,8 @@ __global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_kernel(const V
             s += red[0][q];
             v += red[1][q];
         }
-        partials[2 * blockIdx.x] = s;
-        partials[2 * blockIdx.x + 1] = v;
+        partial[0] = s;
+        partial[1] = v;
     }
     // flush the block's histogram: one global atomic per non-empty bin
     if constexpr (BINS) {
@@ -525,6 +528,56 @@ __global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_kernel(const V
             if (v != 0.0) unsafeAtomicAdd(bins + i, v);
         }
     }
+}
+
+template <int F, int D, bool P2, bool BINS, bool F32>
+__global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_kernel(const VsArgs A,
+                                                           const double *__restrict__ grid,
+                                                           double *__restrict__ bins,
+                                                           double *__restrict__ partials) {
+    extern __shared__ double smem[];
+    __shared__ double red[2][kMaxBlock / 64];
+    __shared__ double scoef[2 * kMaxDim];
+    // persistent grid: thread tid walks work items tid, tid + T, ... < m
+    const uint32_t T = gridDim.x * blockDim.x;
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t count = tid < A.m ? (A.m - 1u - tid) / T + 1u : 0u;
+    vs_block<F, D, P2, BINS, F32>(A, grid, bins, partials + 2 * blockIdx.x, tid, T, count, A.step,
+                                  A.step_digit, A.iteration, smem, red, scoef);
+}
+
+// Batched form: one launch per (family, dim, p = 2?) class of a batch, one
+// workgroup per tile of the class's tile list (a tile is a range of work
+// items of one integrand; the hardware dispatcher hands out the tiles as
+// workgroups finish).  Tiles of integrands marked done exit at once.  The
+// iteration number is read from device memory so that one captured graph
+// serves every iteration.
+template <int F, int D, bool P2, bool BINS>
+__global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_tiles_kernel(
+    const BatchItem *__restrict__ items, const BatchTile *__restrict__ tiles,
+    const double *__restrict__ grids, double *__restrict__ bins, double *__restrict__ partials,
+    const uint32_t *__restrict__ iter, const uint32_t *__restrict__ done) {
+    extern __shared__ double smem[];
+    __shared__ double red[2][kMaxBlock / 64];
+    __shared__ double scoef[2 * kMaxDim];
+    const BatchTile tile = tiles[blockIdx.x];
+    if (done[tile.item] != 0u) return;
+    const BatchItem &B = items[tile.item];
+    const uint32_t w0 = tile.w_begin + threadIdx.x;
+    const uint32_t count = w0 < tile.w_end ? (tile.w_end - 1u - w0) / blockDim.x + 1u : 0u;
+    vs_block<F, D, P2, BINS, false>(B.args, grids + B.grid_off, bins + B.bins_off,
+                                    partials + 2 * (size_t)tile.partial, w0, blockDim.x, count,
+                                    B.step_block, B.step_digit_block, *iter, smem, red, scoef);
+}
+
+template <int F, int D, bool P2, bool BINS>
+hipError_t launch_vsample_tiles(const BatchItem *items, const BatchTile *tiles, int ntiles,
+                                const double *grids, double *bins, double *partials,
+                                const uint32_t *iter, const uint32_t *done, int block, size_t lds,
+                                hipStream_t stream) {
+    hipLaunchKernelGGL((vsample_tiles_kernel<F, D, P2, BINS>), dim3(ntiles), dim3(block), lds,
+                       stream, items, tiles, grids, bins, partials, iter, done);
+    return hipGetLastError();
 }
 
 template <int F, int D, bool P2, bool BINS, bool F32>
@@ -546,7 +599,14 @@ hipError_t launch_vsample(const VsArgs &args, const double *grid, double *bins, 
 #define MCUBES_VS_ENTRY(F, D)                                                          \
     VsKernel {                                                                         \
         {MCUBES_VS_SET(MCUBES_VS_FN, F, D, false), MCUBES_VS_SET(MCUBES_VS_FN, F, D, true)}, \
-        {MCUBES_VS_SET(MCUBES_VS_SYM, F, D, false), MCUBES_VS_SET(MCUBES_VS_SYM, F, D, true)} \
+        {MCUBES_VS_SET(MCUBES_VS_SYM, F, D, false), MCUBES_VS_SET(MCUBES_VS_SYM, F, D, true)}, \
+        {{&launch_vsample_tiles<F, D, false, true>, &launch_vsample_tiles<F, D, true, true>}, \
+         {&launch_vsample_tiles<F, D, false, false>,                                   \
+          &launch_vsample_tiles<F, D, true, false>}},                                  \
+        {{reinterpret_cast<const void *>(&vsample_tiles_kernel<F, D, false, true>),    \
+          reinterpret_cast<const void *>(&vsample_tiles_kernel<F, D, true, true>)},    \
+         {reinterpret_cast<const void *>(&vsample_tiles_kernel<F, D, false, false>),   \
+          reinterpret_cast<const void *>(&vsample_tiles_kernel<F, D, true, false>)}}   \
     }
 
 // A host function returning the table of one family (a namespace-scope const

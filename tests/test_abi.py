@@ -50,6 +50,13 @@ int main(void) {
     printf("mcubes_plan_info size %zu\n", sizeof(mcubes_plan_info));
     F(mcubes_plan_info, lds_bytes) F(mcubes_plan_info, cube_side) F(mcubes_plan_info, state_len)
     F(mcubes_plan_info, precision)
+    printf("mcubes_batch_item size %zu\n", sizeof(mcubes_batch_item));
+    F(mcubes_batch_item, ncall) F(mcubes_batch_item, params)
+    printf("mcubes_batch_info size %zu\n", sizeof(mcubes_batch_info));
+    F(mcubes_batch_info, grids_len) F(mcubes_batch_info, last_iterations)
+    F(mcubes_batch_info, last_samples) F(mcubes_batch_info, last_ms)
+    printf("mcubes_batch_class size %zu\n", sizeof(mcubes_batch_class));
+    F(mcubes_batch_class, shares) F(mcubes_batch_class, samples) F(mcubes_batch_class, tuned_ms)
     printf("MCUBES_STATE_LEN x %d\n", MCUBES_STATE_LEN);
     return 0;
 }
@@ -124,3 +131,31 @@ def test_default_options():
     assert (o.nbins, o.adapt_iters, o.skip, o.block_size, o.blocks, o.alpha, o.precision) == \
         (500, -1, 0, 0, 0, 1.5, mc.MCUBES_FP64)
     assert not o.stream
+
+
+_GOOD = (3, 2, 1000, [1.0, 1.0, 0.5, 0.5])
+
+
+@pytest.mark.parametrize("items,opt,code", [
+    ([], {}, mc.MCUBES_E_ARG),
+    ([_GOOD, (9, 2, 1000, [1.0] * 4)], {}, mc.MCUBES_E_INTEGRAND),
+    ([_GOOD, (3, 0, 1000, None)], {}, mc.MCUBES_E_ARG),
+    ([_GOOD, (3, 11, 1000, None)], {}, mc.MCUBES_E_ARG),
+    ([(3, 2, 1, [1.0] * 4)], {}, mc.MCUBES_E_ARG),
+    ([_GOOD, _GOOD, (1, 2, 1000, [0.0, 1.0, 0.5, 0.5])], {}, mc.MCUBES_E_INTEGRAND),
+    ([(0, 2, 1000, [float("nan"), 1.0, 0.5, 0.5])], {}, mc.MCUBES_E_INTEGRAND),
+    ([(3, 1, 2 * 2**32 + 4, [1.0, 0.5])], {}, mc.MCUBES_E_ARG),
+    ([_GOOD], dict(precision=mc.MCUBES_FP32), mc.MCUBES_E_ARG),
+    ([_GOOD], dict(nbins=501), mc.MCUBES_E_ARG),
+    ([_GOOD], dict(block_size=96), mc.MCUBES_E_ARG),
+    ([_GOOD], dict(skip=-2), mc.MCUBES_E_ARG),
+])
+def test_batch_create_rejects(items, opt, code):
+    """Every item is validated on the host before the device is touched; the
+    message names the offending item."""
+    with pytest.raises(mc.MCubesError) as ei:
+        mc.Batch(items, 0, mc.mcubes_default_options(**opt))
+    assert ei.value.code == code
+    msg = mc.mcubes_last_error()
+    if len(items) > 1:
+        assert f"item {len(items) - 1}" in msg, msg

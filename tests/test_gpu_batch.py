@@ -1,0 +1,370 @@
+"""GPU parity of the batched form: every integrand of a batch against the CPU
+oracle run alone with Philox stream id = its index in the batch.
+
+* Lock-step (mcubes_batch_step fed the oracle's grid every iteration): I_t and
+  var_t to the tolerances of parity_util (1e-12 relative; the RMS weight for
+  the oscillatory family; the var_t bound for integrands with libm calls),
+  refined grids to 1e-12 relative + 1e-15 absolute.
+* Free-running (whole runs, graph replay against eager launches, re-splitting
+  as integrands converge, the autotuner): the grids of two runs drift apart
+  by an ulp or two per refinement (pow and log round differently on the two
+  sides; bin sums are added in different orders), and m-Cubes amplifies
+  such drift from one iteration to the next (a bin of width W whose edges
+  move by an ulp of E changes the Jacobian by about eps E / W, the bin sums
+  feed the next refinement; with few samples per bin the growth reaches
+  100x per iteration).  The tolerance of iteration t is therefore measured
+  on the oracle itself: ten times the largest change that random 4-ulp
+  perturbations of the oracle's refined edges produce in I_t, var_t and the
+  final grid (two perturbed runs), and at least 1e-12.
+* At the full 512-integrand size, sampled integrands against the
+  single-integrand GPU path (itself pinned to the oracle): lock-step at a
+  fixed grid to 1e-12, and free-running."""
+import math
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from parity_util import EPS, LIBM_FAMILIES, host_threads, random_grid, var_tolerance
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2302_05730_amd as m
+    m.lib()
+    return m
+
+
+def _say(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+def _items(problems):
+    return [(p.family, p.dim, p.ncall, p.params) for p in problems]
+
+
+def _pmap(fn, xs):
+    with ThreadPoolExecutor(max_workers=host_threads()) as ex:
+        return list(ex.map(fn, xs))
+
+
+def _stepwise(pr, stream, itmax, seed, nb, adapt, alpha, ulps, rng):
+    """The oracle's iterations written out, the refined edges moved by up to
+    `ulps` ulp at random after each refinement (none for ulps = 0)."""
+    grid = oracle.uniform_grid(pr.dim, nb)
+    I, V = [], []
+    for t in range(itmax):
+        a, v, bins = oracle.iteration(pr.family, pr.params, pr.dim, nb, pr.ncall, seed, t, grid,
+                                      stream=stream)
+        I.append(a)
+        V.append(v)
+        if not (math.isfinite(a) and math.isfinite(v)):
+            break
+        if t < adapt:
+            grid = oracle.refine(grid, bins, alpha)
+            for _ in range(ulps):
+                inner = grid[:, 1:-1]
+                up = rng.random(inner.shape) < 0.5
+                grid[:, 1:-1] = np.nextafter(inner, np.where(up, 2.0, -1.0))
+            grid[:, 1:] = np.maximum.accumulate(grid[:, 1:], axis=1)
+    return np.array(I), np.array(V), grid
+
+
+def _oracle_run(pr, stream, itmax, rel_tol, seed, nb, adapt_iters=None, skip=0, alpha=1.5):
+    """oracle.integrate plus the drift tolerances of its trace and grid."""
+    r = oracle.integrate(pr.family, pr.params, pr.dim, pr.ncall, itmax, rel_tol, seed, nb=nb,
+                         stream=stream, adapt_iters=adapt_iters, skip=skip, alpha=alpha)
+    T = r["iterations"]
+    adapt = itmax if adapt_iters is None else adapt_iters
+    I0, V0, G0 = _stepwise(pr, stream, T, seed, nb, adapt, alpha, 0, None)
+    assert np.array_equal(I0, r["trace_I"]) and np.array_equal(V0, r["trace_var"])
+    assert np.array_equal(G0, r["grid"])
+    tI, tV, tG = np.full(T, 1e-12), np.full(T, 1e-12), 1e-15
+    for k in range(2):
+        rng = np.random.default_rng(1000 * stream + k)
+        I1, V1, G1 = _stepwise(pr, stream, T, seed, nb, adapt, alpha, 4, rng)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            tI = np.maximum(tI, 10 * np.nan_to_num(np.abs(I1 - I0) / np.abs(I0)))
+            tV = np.maximum(tV, 10 * np.nan_to_num(np.abs(V1 - V0) / np.abs(V0)))
+        tG = max(tG, 10 * float(np.max(np.abs(G1 - G0))))
+    r["tol_I"], r["tol_V"], r["tol_grid"] = tI, tV, tG
+    return r
+
+
+def _oracle_all(problems, itmax, rel_tol, seed, nb, stream0=0, **kw):
+    return _pmap(lambda ip: _oracle_run(ip[1], stream0 + ip[0], itmax, rel_tol, seed, nb, **kw),
+                 enumerate(problems))
+
+
+def _trace_close(family, gI, gV, rI, rV, m, p, tol_I, tol_V, what):
+    """Free-running traces against a reference; returns the largest relative
+    tolerance used."""
+    n = m * p
+    assert len(gI) == len(rI), f"{what}: {len(gI)} vs {len(rI)} iterations"
+    worst = 0.0
+    for t, (a, b, va, vb) in enumerate(zip(gI, rI, gV, rV)):
+        rms = math.sqrt(max(n * vb + b * b, 0.0))
+        scale = max(abs(b), rms) if family == 0 else abs(b)
+        assert abs(a - b) <= tol_I[t] * scale + 1e-300, \
+            f"{what} t={t}: I {a!r} vs {b!r} (tol {tol_I[t]:.2e})"
+        tol = tol_V[t]
+        if family in LIBM_FAMILIES and vb > 0:
+            Q = n * (n * vb + b * b)
+            tol = max(tol, 16 * EPS * math.sqrt(Q / (2 * vb * p * m * m)))
+        assert abs(va - vb) <= tol * abs(vb) + 1e-300, \
+            f"{what} t={t}: var {va!r} vs {vb!r} (tol {tol:.2e})"
+        worst = max(worst, tol, tol_I[t] * scale / max(abs(b), 1e-300))
+    return worst
+
+
+def _compare(problems, got, ref, what, grids=True):
+    for i, (pr, g, r) in enumerate(zip(problems, got, ref)):
+        tag = f"{what} item {i} ({pr.name}, ncall {pr.ncall})"
+        assert g["iterations"] == r["iterations"], tag
+        assert g["converged"] == r["converged"], tag
+        assert (g["cube_side"], g["ncubes"], g["samples_per_cube"]) == (r["g"], r["m"], r["p"])
+        tol = _trace_close(pr.family, g["trace_I"], g["trace_var"], r["trace_I"],
+                           r["trace_var"], r["m"], r["p"], r["tol_I"], r["tol_V"], tag)
+        # the combination is a weighted mean of the traces: relative errors carry over
+        assert g["estimate"] == pytest.approx(r["estimate"], rel=4 * tol, abs=1e-300), tag
+        assert g["error"] == pytest.approx(r["error"], rel=4 * tol, abs=1e-300), tag
+        # chi^2 = sum (I_t - Ibar)^2 / var_t: each term moves by at most
+        # 2 |I_t - Ibar| |dI| / var_t + (I_t - Ibar)^2 / var_t * dvar/var
+        I, V, Ib = np.array(r["trace_I"]), np.array(r["trace_var"]), r["estimate"]
+        if len(I) > 1 and np.all(V > 0):
+            dev = np.abs(I - Ib)
+            dI = 2 * tol * (np.abs(I) + abs(Ib))
+            bound = np.sum(2 * dev * dI / V + dev ** 2 / V * 2 * tol + dI ** 2 / V) / (len(I) - 1)
+            assert abs(g["chi2_dof"] - r["chi2_dof"]) <= bound + 1e-12 * r["chi2_dof"], tag
+        if grids:
+            assert np.allclose(np.array(g["grid"]), r["grid"], rtol=1e-12, atol=r["tol_grid"]), tag
+
+
+SMALL = dict(n=24, seed=11, ncall_lo=2e3, ncall_hi=4e4)
+
+
+def test_batch_lockstep_matches_oracle(mc):
+    """24 integrands (six families, dims 2-10, budgets 2e3-4e4, 500 bins): four
+    iterations, each fed the oracle's grid; I_t, var_t and the refined grid of
+    every integrand."""
+    probs = workloads.batch_problems(**SMALL)
+    b = mc.Batch(_items(probs), seed=77)
+    grids = [oracle.uniform_grid(p.dim, 500) for p in probs]
+    for t in range(4):
+        _say(f"batch lock-step t={t}")
+        est, new = b.step(t, grids)
+        refs = _pmap(lambda ip: oracle.iteration(ip[1].family, ip[1].params, ip[1].dim, 500,
+                                                 ip[1].ncall, 77, t, grids[ip[0]],
+                                                 stream=ip[0]), enumerate(probs))
+        for i, (pr, (gI, gV), (rI, rV, rB)) in enumerate(zip(probs, est, refs)):
+            g, m, p, n = oracle.plan(pr.dim, pr.ncall)
+            tag = f"t={t} item {i} ({pr.name})"
+            scale = max(abs(rI), math.sqrt(float(rB[0].sum()) / n)) if pr.family == 0 else abs(rI)
+            assert abs(gI - rI) <= 1e-12 * scale + 1e-300, f"{tag}: I {gI!r} vs {rI!r}"
+            tol = var_tolerance(pr.family, rV, rB, m, p)
+            assert abs(gV - rV) <= tol * abs(rV) + 1e-300, f"{tag}: var {gV!r} vs {rV!r}"
+            ref_grid = oracle.refine(grids[i], rB)
+            assert np.allclose(np.array(new[i]), ref_grid, rtol=1e-12, atol=1e-15), tag
+            grids[i] = ref_grid
+
+
+def test_batch_matches_oracle_free_running(mc):
+    """24 integrands, six families, dims 2-10, budgets 2e3-4e4, 500 bins, five
+    iterations: every integrand's trace, result and final grid."""
+    probs = workloads.batch_problems(**SMALL)
+    _say("batch oracle parity: building")
+    b = mc.Batch(_items(probs), seed=77)
+    info = b.info()
+    assert info["items"] == 24 and info["classes"] >= 10
+    rc, got = b.integrate(5, 0.0, use_graph=True, grids=True, traces=True)
+    assert rc == mc.MCUBES_NOT_CONVERGED
+    ref = _oracle_all(probs, 5, 0.0, 77, 500)
+    _compare(probs, got, ref, "graph")
+
+
+def _compare_runs(problems, runs, base, ref, what):
+    """GPU runs against a base GPU run of the same batch, to the drift bound of
+    the oracle's conditioning (ref)."""
+    for i, pr in enumerate(problems):
+        for k, other in enumerate(runs):
+            tag = f"{what} run {k} item {i} ({pr.name})"
+            assert other[i]["iterations"] == base[i]["iterations"], tag
+            _trace_close(pr.family, other[i]["trace_I"], other[i]["trace_var"],
+                         base[i]["trace_I"], base[i]["trace_var"], base[i]["ncubes"],
+                         base[i]["samples_per_cube"], ref[i]["tol_I"], ref[i]["tol_V"], tag)
+            assert np.allclose(np.array(other[i]["grid"]), np.array(base[i]["grid"]),
+                               rtol=1e-12, atol=ref[i]["tol_grid"]), tag
+
+
+def test_graph_replays_match_eager(mc):
+    """The captured graph, replayed once per iteration with host
+    synchronisation and flag reads between replays, against the same kernels
+    launched one by one: every iteration of every integrand (the first
+    iteration, on the uniform grid, to 1e-12; later ones to the drift bound)."""
+    probs = workloads.batch_problems(n=16, seed=12, ncall_lo=5e3, ncall_hi=2e5)
+    b = mc.Batch(_items(probs), seed=5)
+    rc_e, eager = b.integrate(6, 0.0, use_graph=False, grids=True, traces=True)
+    rc_g, graph = b.integrate(6, 0.0, use_graph=True, grids=True, traces=True)
+    rc_g2, graph2 = b.integrate(6, 0.0, use_graph=True, grids=True, traces=True)
+    assert rc_e == rc_g == rc_g2 == mc.MCUBES_NOT_CONVERGED
+    ref = _oracle_all(probs, 6, 0.0, 5, 500)
+    _compare(probs, eager, ref, "eager")
+    _compare_runs(probs, [graph, graph2], eager, ref, "graph vs eager")
+    for e, g in zip(eager, graph):
+        assert e["trace_I"][0] == pytest.approx(g["trace_I"][0], rel=1e-15, abs=1e-300)
+
+
+def test_convergence_and_resplit(mc):
+    """Integrands stop at different iterations (rel_tol 2e-3); the work of the
+    finished ones is re-split.  Each integrand's stopping iteration and result
+    match the oracle's."""
+    probs = workloads.batch_problems(n=20, seed=13, ncall_lo=5e3, ncall_hi=5e4,
+                                     families=(workloads.PRODUCT_PEAK, workloads.GAUSSIAN,
+                                               workloads.C0, workloads.CORNER_PEAK),
+                                     dims=(2, 3, 4, 5))
+    b = mc.Batch(_items(probs), seed=9, options=mc.mcubes_default_options(nbins=100))
+    rc, got = b.integrate(12, 2e-3, use_graph=True, grids=True, traces=True)
+    ref = _oracle_all(probs, 12, 2e-3, 9, 100)
+    _compare(probs, got, ref, "converging")
+    its = sorted(set(r["iterations"] for r in ref))
+    assert len(its) >= 3, its  # the integrands really stop at different iterations
+    info = b.info()
+    assert info["last_replans"] >= 1
+    assert info["last_iterations"] == max(r["iterations"] for r in ref)
+    assert info["last_samples"] == sum(r["iterations"] * r["n"] for r in ref)
+
+
+def test_frozen_grid_phase_and_skip(mc):
+    """adapt_iters = 2 (the last iterations run without bin sums and without
+    refinement) and skip = 1, as in the single-integrand form."""
+    probs = workloads.batch_problems(n=10, seed=14, ncall_lo=3e3, ncall_hi=3e4)
+    opt = mc.mcubes_default_options(nbins=60, adapt_iters=2, skip=1, alpha=1.2)
+    b = mc.Batch(_items(probs), seed=21, options=opt)
+    rc, got = b.integrate(5, 0.0, use_graph=True, grids=True, traces=True)
+    ref = _oracle_all(probs, 5, 0.0, 21, 60, adapt_iters=2, skip=1, alpha=1.2)
+    _compare(probs, got, ref, "frozen")
+
+
+def test_stream_offset_and_degenerate_items(mc):
+    """stream_id offsets the per-integrand streams; one-cube items (m = 1,
+    p = ncall), p > 2, the addition integrand and a 1-D item share a batch."""
+    probs = [
+        workloads.Problem("one_cube_10d", workloads.GAUSSIAN, 10, [1.5] * 10 + [0.4] * 10, 1500),
+        workloads.Problem("p_gt_2", workloads.PRODUCT_PEAK, 6, [3.0] * 6 + [0.6] * 6, 50_000),
+        workloads.Problem("addition_8d", workloads.ADDITION, 8, [0.0] * 16, 20_000),
+        workloads.Problem("oscill_1d", workloads.OSCILLATORY, 1, [4.0, 0.3], 777),
+        workloads.Problem("c0_2d_tiny", workloads.C0, 2, [3.0, 5.0, 0.5, 0.2], 9),
+    ]
+    opt = mc.mcubes_default_options(nbins=40, stream_id=1000)
+    b = mc.Batch(_items(probs), seed=3, options=opt)
+    rc, got = b.integrate(4, 0.0, use_graph=True, grids=True, traces=True)
+    ref = _oracle_all(probs, 4, 0.0, 3, 40, stream0=1000)
+    _compare(probs, got, ref, "degenerate")
+    assert got[0]["ncubes"] == 1 and got[0]["samples_per_cube"] == 1500
+
+
+def test_nonfinite_item_is_isolated(mc):
+    """exp(sum a x) with a = 1000 and no cut overflows to infinity: that
+    integrand is reported as MCUBES_E_NONFINITE and stops after its first
+    iteration; the others run on unchanged."""
+    good = workloads.batch_problems(n=4, seed=15, ncall_lo=2e3, ncall_hi=1e4,
+                                    families=(workloads.GAUSSIAN,), dims=(3,))
+    bad = workloads.Problem("bad", workloads.DISCONTINUOUS, 2, [1000.0, 1000.0, 2.0, 2.0], 4000)
+    probs = good[:2] + [bad] + good[2:]
+    b = mc.Batch(_items(probs), seed=8, options=mc.mcubes_default_options(nbins=50))
+    rc, got = b.integrate(4, 0.0, use_graph=True, grids=True, traces=True)
+    assert rc == mc.MCUBES_E_NONFINITE
+    assert got[2]["status"] == mc.MCUBES_E_NONFINITE and got[2]["iterations"] == 1
+    others = [p for i, p in enumerate(probs) if i != 2]
+    ref = _oracle_all(probs, 4, 0.0, 8, 50)
+    _compare(others, [g for i, g in enumerate(got) if i != 2],
+             [r for i, r in enumerate(ref) if i != 2], "beside nonfinite")
+    for i, g in enumerate(got):
+        if i != 2:
+            assert g["status"] == mc.MCUBES_NOT_CONVERGED and g["iterations"] == 4
+
+
+def test_autotune_and_geometry_are_result_neutral(mc):
+    """Results after the autotuner, and with deliberately odd geometries (64
+    threads per workgroup, a tile per few cubes), agree with the default."""
+    probs = workloads.batch_problems(n=12, seed=16, ncall_lo=1e4, ncall_hi=3e5)
+    b = mc.Batch(_items(probs), seed=31)
+    rc0, base = b.integrate(4, 0.0, grids=True, traces=True)
+    b.autotune()
+    classes = b.classes()
+    assert b.info()["tuned"] == 1 and all(c["tuned_ms"] > 0 for c in classes)
+    rc1, tuned = b.integrate(4, 0.0, grids=True, traces=True)
+    for k, c in enumerate(classes):
+        b.configure_class(k, 64, max(1, c["samples"] // 512))
+    odd_info = b.info()
+    assert all(c["block_size"] == 64 for c in b.classes())
+    rc2, odd = b.integrate(4, 0.0, grids=True, traces=True)
+    assert odd_info["tiles"] > 4 * len(probs)
+    ref = _oracle_all(probs, 4, 0.0, 31, 500)
+    _compare(probs, base, ref, "default geometry")
+    _compare_runs(probs, [tuned, odd], base, ref, "geometry")
+
+
+def test_full_size_batch_against_single_integrand_path(mc):
+    """The 512-integrand workload (budgets 1e6-1e8, 9.4e9 samples/iteration).
+    Lock-step: one iteration of the whole batch from fixed random grids
+    against sampled integrands (the largest, a 10-D one, a p > 2 one and a few
+    more) run alone through a plan with the same Philox stream and grid, to
+    1e-12.  Free-running: three iterations of the whole batch against the same
+    integrands run alone through mcubes_integrate."""
+    import torch  # noqa: F401  (device memory of the single-integrand path)
+    from parity_util import gpu_iteration, gpu_refine
+    probs = workloads.batch_problems()
+    plans = [oracle.plan(p.dim, p.ncall) for p in probs]
+    pick = {int(np.argmax([pl[3] for pl in plans])),
+            next(i for i, p in enumerate(probs) if p.dim == 10),
+            next(i for i, pl in enumerate(plans) if pl[2] > 2)}
+    pick |= {0, 101, 257, 511}
+    _say("full batch: create, 512 integrands")
+    b = mc.Batch(_items(probs), seed=0)
+    rng = np.random.default_rng(2024)
+    grids = [random_grid(rng, p.dim, 500) for p in probs]
+    est, new = b.step(2, grids)
+    for i in sorted(pick):
+        pr = probs[i]
+        _say(f"full batch lock-step: item {i} {pr.name} ncall {pr.ncall}")
+        plan = mc.mcubes_plan_create(pr.family, pr.params, pr.dim, pr.ncall, 0,
+                                     mc.mcubes_default_options(stream_id=i))
+        sI, sV, sB = gpu_iteration(plan, 2, grids[i])
+        g, m, p, n = plans[i]
+        scale = max(abs(sI), math.sqrt(float(sB[0].sum()) / n)) if pr.family == 0 else abs(sI)
+        assert abs(est[i][0] - sI) <= 1e-12 * scale + 1e-300, (i, est[i][0], sI)
+        assert abs(est[i][1] - sV) <= 1e-12 * abs(sV) + 1e-300, (i, est[i][1], sV)
+        assert np.allclose(np.array(new[i]), gpu_refine(plan, grids[i], sB), rtol=1e-12,
+                           atol=1e-15), i
+    _say("full batch: integrate, 3 iterations")
+    rc, got = b.integrate(3, 0.0, grids=True, traces=True)
+    info = b.info()
+    _say(f"full batch: {info['last_ms']:.1f} ms for {info['last_samples']:.3e} samples")
+    assert info["last_samples"] == 3 * sum(pl[3] for pl in plans)
+    for i in sorted(pick):
+        pr = probs[i]
+        _say(f"full batch free-running: item {i} {pr.name}")
+        single = mc.mcubes_integrate(pr.family, pr.params, pr.dim, pr.ncall, 3, 0.0, 0,
+                                     mc.mcubes_default_options(stream_id=i))
+        # the first iteration samples the same uniform grid: 1e-12; no oracle
+        # run measures the drift bound at this size, so later iterations are
+        # held to agreement within the two runs' combined standard deviation
+        one = np.array([1e-12])
+        _trace_close(pr.family, got[i]["trace_I"][:1], got[i]["trace_var"][:1],
+                     single["trace_I"][:1], single["trace_var"][:1], single["ncubes"],
+                     single["samples_per_cube"], one, one, f"item {i}")
+        for t in (1, 2):
+            sd = math.sqrt(got[i]["trace_var"][t] + single["trace_var"][t])
+            assert abs(got[i]["trace_I"][t] - single["trace_I"][t]) <= 3 * sd, (i, t)
+    for g in got:
+        assert g["status"] == mc.MCUBES_NOT_CONVERGED and g["iterations"] == 3
+        assert math.isfinite(g["estimate"]) and g["error"] > 0

@@ -159,3 +159,26 @@ def test_stop_rule():
     r2 = oracle.integrate(1, params, 2, 20000, r["iterations"] - 1, 3e-5, 0, nb=50)
     assert not r2["converged"] and r2["iterations"] == r["iterations"] - 1
     assert r2["error"] > 3e-5 * abs(r2["estimate"])
+
+
+def test_integrate_stream_is_the_second_counter_word():
+    """integrate(stream=s) is the loop of iteration(stream=s), refine and
+    combine (the stream word reaches every Philox counter), and differs from
+    another stream's run only through the samples: both estimate the same
+    integral within their errors."""
+    params = [6.0, 3.0, 0.3, 0.7]
+    r5 = oracle.integrate(3, params, 2, 6000, 3, 0.0, 4, nb=30, stream=5)
+    grid = oracle.uniform_grid(2, 30)
+    I, V = [], []
+    for t in range(3):
+        i_t, v_t, bins = oracle.iteration(3, params, 2, 30, 6000, 4, t, grid, stream=5)
+        I.append(i_t)
+        V.append(v_t)
+        grid = oracle.refine(grid, bins)
+    assert list(r5["trace_I"]) == I and list(r5["trace_var"]) == V
+    assert np.array_equal(r5["grid"], grid)
+    r0 = oracle.integrate(3, params, 2, 6000, 3, 0.0, 4, nb=30)
+    assert r0["trace_I"][0] != r5["trace_I"][0]
+    exact = float(cf.integral(3, params, 2))
+    for r in (r0, r5):
+        assert abs(r["estimate"] - exact) <= 4 * r["error"]

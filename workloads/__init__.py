@@ -106,3 +106,26 @@ def random_problem(rng, family, dim, ncall, nbins):
         params = genz_params(rng, dim, 2.0, 12.0, 0.0, 1.0)
     return Problem(f"{FAMILY_NAMES[family]}_{dim}d", family, dim, params, ncall=ncall,
                    nbins=nbins)
+
+
+# Parameter seed of the batched workload.
+BATCH_SEED = 4
+
+
+def batch_problems(n=512, seed=BATCH_SEED, ncall_lo=1e6, ncall_hi=1e8, nbins=500,
+                   families=(OSCILLATORY, PRODUCT_PEAK, CORNER_PEAK, GAUSSIAN, C0, DISCONTINUOUS),
+                   dims=tuple(range(2, 11))):
+    """n integrands for the batched form: family uniform over the six Genz
+    families of the paper's benchmark, dimension uniform over 2..10, sample
+    budget per iteration log-uniform in [ncall_lo, ncall_hi], parameters as in
+    random_problem.  The default is the 512-integrand workload."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        fam = int(families[rng.integers(0, len(families))])
+        dim = int(dims[rng.integers(0, len(dims))])
+        ncall = int(round(float(np.exp(rng.uniform(np.log(ncall_lo), np.log(ncall_hi))))))
+        pr = random_problem(rng, fam, dim, ncall, nbins)
+        pr.name = f"batch{i}_{pr.name}"
+        out.append(pr)
+    return out
