@@ -117,6 +117,56 @@ def cpu_baseline(problems, ncall):
                        f"{dt:.1f} s single-threaded")}
 
 
+def bench_batch(mc, n, iters):
+    """The batched form on the n-integrand workload: throughput of `iters`
+    fixed iterations (rel_tol 0) with the default split and after the
+    autotuner, graph replay against eager launches, and the time until every
+    integrand reaches 1e-3 relative error (or 20 iterations)."""
+    problems = workloads.batch_problems(n=n)
+    items = [(p.family, p.dim, p.ncall, p.params) for p in problems]
+    t_a = time.perf_counter()
+    b = mc.Batch(items, seed=0)
+    t_b = time.perf_counter()
+    plans = [mc.mcubes_plan_sizes(p.dim, p.ncall) for p in problems]
+    flops_iter = sum(flops_per_sample(p.family, p.dim, pl[2]) * pl[3]
+                     for p, pl in zip(problems, plans))
+
+    def run(use_graph, itmax=iters, rel_tol=0.0):
+        rc, res = b.integrate(itmax, rel_tol, use_graph=use_graph)
+        info = b.info()
+        ms = info["last_ms"]
+        return {"ms": round(ms, 3), "iterations": info["last_iterations"],
+                "samples": info["last_samples"],
+                "evals_per_s": info["last_samples"] / (ms * 1e-3),
+                "ms_per_iteration": round(ms / info["last_iterations"], 3),
+                "replans": info["last_replans"]}, res
+
+    b.integrate(1, 0.0)  # warm-up: graph capture, first-touch of the buffers
+    default_graph, _ = run(True)
+    default_eager, _ = run(False)
+    t_c = time.perf_counter()
+    b.autotune()
+    t_d = time.perf_counter()
+    b.integrate(1, 0.0)
+    tuned, _ = run(True)
+    info = b.info()
+    tuned["tflops"] = flops_iter * tuned["iterations"] / (tuned["ms"] * 1e-3) / 1e12
+    tuned["frac_of_fp64_vector_peak"] = tuned["tflops"] / FP64_VECTOR_PEAK_TFLOPS
+    to_tol, res = run(True, itmax=20, rel_tol=1e-3)
+    to_tol["converged"] = sum(1 for r in res if r["converged"])
+    to_tol["nonfinite"] = sum(1 for r in res if r["status"] == mc.MCUBES_E_NONFINITE)
+    return {"workload": (f"{n} Genz integrands (6 families, dims 2-10 uniform, budgets "
+                         "log-uniform 1e6-1e8 samples/iter, seeded parameters), 500 bins"),
+            "integrands": n, "samples_per_iter": sum(pl[3] for pl in plans),
+            "classes": info["classes"], "tiles": info["tiles"],
+            "launches_per_iteration": info["launches"],
+            "device_mib": round(info["device_bytes"] / 2**20, 1),
+            "create_s": round(t_b - t_a, 3), "autotune_s": round(t_d - t_c, 3),
+            "fixed_iterations_default_graph": default_graph,
+            "fixed_iterations_default_eager": default_eager,
+            "fixed_iterations_tuned_graph": tuned, "to_1e-3_tuned_graph": to_tol}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +178,9 @@ def main():
     ap.add_argument("--no-ttt", action="store_true")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--blocks", type=int, default=0)
+    ap.add_argument("--batch-n", type=int, default=512,
+                    help="integrands of the batched-form measurement (0 = skip it)")
+    ap.add_argument("--batch-iters", type=int, default=5)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the steps, run one plain device copy of this many MiB "
                          "(reference point for the HBM byte counters)")
@@ -267,6 +320,7 @@ def main():
             a["diff_vs_fp64_in_sigma"] = (abs(a["estimate"] - b["estimate"]) / b["error"]
                                           if b["error"] else None)
 
+    batched = bench_batch(mc, args.batch_n, args.batch_iters) if args.batch_n > 0 else None
     cpu = None if args.no_cpu else cpu_baseline(problems, args.cpu_ncall)
     out = {
         "metric": "integrand evals/s + time to 1e-3 rel err, plain FP64 vs FP32/flow form",
@@ -281,7 +335,7 @@ def main():
                    "samples_per_cube": p, "block": plans[0].info["block_size"],
                    "blocks": plans[0].info["blocks"], "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "time_to_1e-3": ttt,
-        "frozen_grid_vsample": frozen, "fp32_vsample": fp32,
+        "frozen_grid_vsample": frozen, "fp32_vsample": fp32, "batched": batched,
     }
     print(json.dumps(out), flush=True)
 

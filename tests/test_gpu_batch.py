@@ -85,7 +85,8 @@ def _oracle_run(pr, stream, itmax, rel_tol, seed, nb, adapt_iters=None, skip=0, 
     T = r["iterations"]
     adapt = itmax if adapt_iters is None else adapt_iters
     I0, V0, G0 = _stepwise(pr, stream, T, seed, nb, adapt, alpha, 0, None)
-    assert np.array_equal(I0, r["trace_I"]) and np.array_equal(V0, r["trace_var"])
+    assert np.array_equal(I0, r["trace_I"], equal_nan=True)
+    assert np.array_equal(V0, r["trace_var"], equal_nan=True)
     assert np.array_equal(G0, r["grid"])
     tI, tV, tG = np.full(T, 1e-12), np.full(T, 1e-12), 1e-15
     for k in range(2):
