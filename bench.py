@@ -117,10 +117,10 @@ def cpu_baseline(problems, ncall):
                        f"{dt:.1f} s single-threaded")}
 
 
-def bench_batch(mc, n, iters):
+def bench_batch(mc, n, iters, full=True):
     """The batched form on the n-integrand workload: throughput of `iters`
-    fixed iterations (rel_tol 0) with the default split and after the
-    autotuner, graph replay against eager launches, and the time until every
+    fixed iterations (rel_tol 0) with the default split, graph replay against
+    eager launches, and (full) after the autotuner and the time until every
     integrand reaches 1e-3 relative error (or 20 iterations)."""
     problems = workloads.batch_problems(n=n)
     items = [(p.family, p.dim, p.ncall, p.params) for p in problems]
@@ -144,6 +144,20 @@ def bench_batch(mc, n, iters):
     b.integrate(1, 0.0)  # warm-up: graph capture, first-touch of the buffers
     default_graph, _ = run(True)
     default_eager, _ = run(False)
+    info = b.info()
+    default_graph["tflops"] = flops_iter * default_graph["iterations"] / (
+        default_graph["ms"] * 1e-3) / 1e12
+    default_graph["frac_of_fp64_vector_peak"] = default_graph["tflops"] / FP64_VECTOR_PEAK_TFLOPS
+    out = {"workload": (f"{n} Genz integrands (6 families, dims 2-10 uniform, budgets "
+                        "log-uniform 1e6-1e8 samples/iter, seeded parameters), 500 bins"),
+           "integrands": n, "samples_per_iter": sum(pl[3] for pl in plans),
+           "classes": info["classes"], "default_tiles": info["tiles"],
+           "default_streams": info["streams"], "launches_per_iteration": info["launches"],
+           "device_mib": round(info["device_bytes"] / 2**20, 1), "create_s": round(t_b - t_a, 3),
+           "fixed_iterations_default_graph": default_graph,
+           "fixed_iterations_default_eager": default_eager}
+    if not full:
+        return out
     t_c = time.perf_counter()
     b.autotune()
     t_d = time.perf_counter()
@@ -155,16 +169,10 @@ def bench_batch(mc, n, iters):
     to_tol, res = run(True, itmax=20, rel_tol=1e-3)
     to_tol["converged"] = sum(1 for r in res if r["converged"])
     to_tol["nonfinite"] = sum(1 for r in res if r["status"] == mc.MCUBES_E_NONFINITE)
-    return {"workload": (f"{n} Genz integrands (6 families, dims 2-10 uniform, budgets "
-                         "log-uniform 1e6-1e8 samples/iter, seeded parameters), 500 bins"),
-            "integrands": n, "samples_per_iter": sum(pl[3] for pl in plans),
-            "classes": info["classes"], "tiles": info["tiles"],
-            "launches_per_iteration": info["launches"],
-            "device_mib": round(info["device_bytes"] / 2**20, 1),
-            "create_s": round(t_b - t_a, 3), "autotune_s": round(t_d - t_c, 3),
-            "fixed_iterations_default_graph": default_graph,
-            "fixed_iterations_default_eager": default_eager,
-            "fixed_iterations_tuned_graph": tuned, "to_1e-3_tuned_graph": to_tol}
+    out.update({"autotune_s": round(t_d - t_c, 3), "tuned_tiles": info["tiles"],
+                "tuned_streams": info["streams"], "fixed_iterations_tuned_graph": tuned,
+                "to_1e-3_tuned_graph": to_tol})
+    return out
 
 
 def main():
@@ -181,6 +189,9 @@ def main():
     ap.add_argument("--batch-n", type=int, default=512,
                     help="integrands of the batched-form measurement (0 = skip it)")
     ap.add_argument("--batch-iters", type=int, default=5)
+    ap.add_argument("--only-batch", action="store_true",
+                    help="measure only the batched form at its default geometry (no autotuner)"
+                         " and print its figures as one JSON line (for profiling)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the steps, run one plain device copy of this many MiB "
                          "(reference point for the HBM byte counters)")
@@ -195,6 +206,10 @@ def main():
     import paper_2302_05730_amd as mc
 
     torch.cuda.set_device(0)
+    if args.only_batch:
+        print(json.dumps({"batched": bench_batch(mc, args.batch_n or 512, args.batch_iters,
+                                                 full=False)}), flush=True)
+        return
     if args.calibrate_copy_mib:
         n = args.calibrate_copy_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")

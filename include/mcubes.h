@@ -269,6 +269,8 @@ typedef struct {
     int32_t launches;       /* kernel launches per iteration */
     int32_t nbins;
     int32_t tuned;          /* 1 after mcubes_batch_autotune */
+    int32_t streams;        /* streams the class launches are spread over */
+    int32_t reserved;
     int64_t grids_len;      /* sum over i of dim_i * (nbins + 1): packed grids, item order */
     int64_t samples_per_iter; /* sum of N_i over the integrands still running */
     int64_t device_bytes;   /* device memory held by the batch */
@@ -287,7 +289,9 @@ typedef struct {
     int32_t tiles;           /* workgroups per launch: shares cut at integrand boundaries */
     int32_t lds_bytes;
     int64_t samples;         /* samples per iteration */
-    double tuned_ms;         /* V-Sample time measured by the autotuner (0 if not tuned) */
+    double tuned_ms;         /* V-Sample time of the chosen geometry, measured by the
+                                autotuner (0 if not tuned) */
+    double default_ms;       /* ... and of the library's default geometry */
 } mcubes_batch_class;
 
 /* Validates every item (errors name the item), plans it, allocates the
@@ -306,13 +310,21 @@ int mcubes_batch_get_class(const mcubes_batch *batch, int k, mcubes_batch_class 
  * partial sums does. */
 int mcubes_batch_configure_class(mcubes_batch *batch, int k, int block_size, int shares);
 
+/* Spreads the per-class V-Sample launches over `streams` (1..4) concurrent
+ * HIP streams (branches of the captured graph), longest classes first onto
+ * the least loaded stream, so that one class's tail overlaps the next
+ * class's work.  Default 4. */
+int mcubes_batch_set_streams(mcubes_batch *batch, int streams);
+
 /* Autotuner: for every class times the V-Sample kernel on the batch's current
- * grids over candidate block sizes (256, 512, 768, 1024 within the kernel's
- * limit) and share counts (1, 2 or 4 times the workgroups resident at once,
- * or fewer shares with at least 4, 16 or 64 cubes per thread for small
- * classes), and keeps the fastest.  The grids, states and results of later
- * calls are unaffected (up to the order of the partial sums).  Takes 3
- * launches per candidate. */
+ * grids at the default geometry and over candidate block sizes (256, 512,
+ * 768, 1024 within the kernel's limit) and share counts (2, 4, 8 or 16 times
+ * the workgroups resident at once, or fewer shares with at least 4, 16 or 64
+ * cubes per thread for small classes), and keeps the fastest.  The grids
+ * and the results of later calls are unaffected (up to the order of the
+ * partial sums); the combined states of the last mcubes_batch_integrate are
+ * cleared.  Then times all classes together on 1 to 4 streams and keeps the
+ * fastest (see mcubes_batch_set_streams).  Takes 3 launches per candidate. */
 int mcubes_batch_autotune(mcubes_batch *batch);
 
 /* One iteration of every integrand from caller-given grids, for lock-step

@@ -72,6 +72,7 @@ class mcubes_batch_info(ctypes.Structure):
     _fields_ = [("items", ctypes.c_int32), ("classes", ctypes.c_int32),
                 ("tiles", ctypes.c_int32), ("launches", ctypes.c_int32),
                 ("nbins", ctypes.c_int32), ("tuned", ctypes.c_int32),
+                ("streams", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("grids_len", ctypes.c_int64), ("samples_per_iter", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("last_iterations", ctypes.c_int32),
                 ("last_replans", ctypes.c_int32), ("last_samples", ctypes.c_int64),
@@ -83,7 +84,7 @@ class mcubes_batch_class(ctypes.Structure):
                 ("items", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("shares", ctypes.c_int32), ("tiles", ctypes.c_int32),
                 ("lds_bytes", ctypes.c_int32), ("samples", ctypes.c_int64),
-                ("tuned_ms", ctypes.c_double)]
+                ("tuned_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
 
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -126,6 +127,7 @@ _SIGNATURES = {
     "mcubes_batch_configure_class": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int,
                                                     ctypes.c_int]),
     "mcubes_batch_autotune": (ctypes.c_int, [_vp]),
+    "mcubes_batch_set_streams": (ctypes.c_int, [_vp, ctypes.c_int]),
     "mcubes_batch_step": (ctypes.c_int, [_vp, ctypes.c_uint32, _dp, _dp]),
     "mcubes_batch_integrate": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                               ctypes.POINTER(mcubes_result), _dp, _dp]),
@@ -389,6 +391,9 @@ class Batch:
 
     def autotune(self):
         _check(lib().mcubes_batch_autotune(self.handle))
+
+    def set_streams(self, streams):
+        _check(lib().mcubes_batch_set_streams(self.handle, int(streams)))
 
     def step(self, iteration, grids):
         """One iteration from the given grids (one dim x (nbins+1) array-like

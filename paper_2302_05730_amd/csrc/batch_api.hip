@@ -27,7 +27,7 @@ struct ClassKey {
 // Geometry chosen for a class (0 = library default).
 struct ClassCfg {
     int block = 0, blocks = 0;
-    double tuned_ms = 0.0;
+    double tuned_ms = 0.0, default_ms = 0.0;
 };
 
 struct ClassPlan {
@@ -39,12 +39,16 @@ struct ClassPlan {
     VsTilesLaunchFn launch[2] = {};  // [nobins]
     uint32_t tile_off = 0;
     int ntiles = 0;
+    int branch = 0;  // stream of the class's launch
     int64_t samples = 0, cubes = 0;
 };
 
-// Default share: at least this many cubes per thread before another block is
-// added to a class.
-constexpr int64_t kDefaultCubesPerThread = 4;
+// Default split: kSharesPerSlot shares per workgroup slot of the device (the
+// hardware dispatcher then balances the unequal tile times; one share per
+// slot measured 1.6x slower on the 512-integrand workload), but at least one
+// cube per thread.
+constexpr int64_t kSharesPerSlot = 8;
+constexpr int kMaxStreams = 4;
 constexpr int64_t kMaxShares = 1 << 20;
 
 }  // namespace
@@ -80,6 +84,10 @@ struct mcubes_batch {
     hipStream_t stream = nullptr;
     hipEvent_t ev[3] = {};
     hipGraphExec_t exec[2] = {};  // [frozen]
+    // concurrent class launches: branch 0 runs on `stream`, branch k on side[k-1]
+    int streams = kMaxStreams;
+    hipStream_t side[kMaxStreams - 1] = {};
+    hipEvent_t fork = nullptr, join[kMaxStreams - 1] = {};
 
     int last_iterations = 0, last_replans = 0;
     int64_t last_samples = 0;
@@ -100,6 +108,11 @@ void release(mcubes_batch *B) {
     drop_graphs(B);
     for (auto &e : B->ev)
         if (e) hipEventDestroy(e);
+    for (auto &e : B->join)
+        if (e) hipEventDestroy(e);
+    if (B->fork) hipEventDestroy(B->fork);
+    for (auto &q : B->side)
+        if (q) hipStreamDestroy(q);
     if (B->stream) hipStreamDestroy(B->stream);
     hipFree(B->d_items);
     hipFree(B->d_grids);
@@ -172,20 +185,28 @@ void split_class(const mcubes_batch *B, const ClassPlan &c, int shares,
 }
 
 // Shares (workgroups before the split at item boundaries) for a class: the
-// configured count, else one per kDefaultCubesPerThread * block cubes but at
-// most one per workgroup slot of the device; never more than the cubes.
+// configured count, else kSharesPerSlot per workgroup slot of the device but
+// at most one per `block` cubes; never more than the cubes.
 int class_shares(const mcubes_batch *B, const ClassPlan &c, int block, int want) {
     const int R = resident_blocks(B, c, block);
     if (R < 1) return 0;
     int64_t shares = want;
     if (shares <= 0) {
-        shares = (c.cubes + block * kDefaultCubesPerThread - 1) / (block * kDefaultCubesPerThread);
-        if (shares > R) shares = R;
+        shares = (c.cubes + block - 1) / block;
+        if (shares > kSharesPerSlot * R) shares = kSharesPerSlot * R;
     }
     if (shares > kMaxShares) shares = kMaxShares;
     if (shares > c.cubes) shares = c.cubes;
     if (shares < 1) shares = 1;
     return (int)shares;
+}
+
+// Default workgroup size: small for low dimensions, where the LDS tables are
+// small and finer tiles balance better (the autotuner's choice on the
+// 512-integrand workload), the kernel's limit from 7-D on.
+int default_block(const ClassPlan &c) {
+    const int want = c.key.dim <= 3 ? 256 : (c.key.dim <= 6 ? 512 : 1024);
+    return std::min(want, c.max_block / 64 * 64);
 }
 
 void set_item_step(mcubes_batch *B, int i, int block) {
@@ -208,12 +229,39 @@ ClassPlan make_class(const mcubes_batch *B, const ClassKey &key) {
     return c;
 }
 
+// Spreads the classes over B->streams branches, longest first onto the least
+// loaded branch; the cost of a class is its tuned time, else its samples
+// weighted by dimension.
+void assign_branches(mcubes_batch *B) {
+    std::vector<std::pair<double, int>> cost;
+    for (int k = 0; k < (int)B->plan.size(); ++k) {
+        const ClassPlan &c = B->plan[k];
+        auto it = B->cfg.find(c.key);
+        const double t = (it != B->cfg.end() && it->second.tuned_ms > 0.0)
+                             ? it->second.tuned_ms
+                             : (double)c.samples * (c.key.dim + 4) * 1e-9;
+        cost.push_back({t, k});
+    }
+    std::sort(cost.begin(), cost.end(), [](const std::pair<double, int> &a,
+                                           const std::pair<double, int> &b) {
+        return a.first > b.first || (a.first == b.first && a.second < b.second);
+    });
+    std::vector<double> load(B->streams, 0.0);
+    for (const auto &ck : cost) {
+        const int br = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        B->plan[ck.second].branch = br;
+        load[br] += ck.first;
+    }
+}
+
 // (Re)builds the plan over the items not yet done: classes, geometry, tiles,
 // and uploads the descriptors.  Invalidates the captured graphs.
 int build_plan(mcubes_batch *B, const std::vector<char> &active) {
     // the descriptors are overwritten below: nothing may still read them
     if (B->stream) {
-        const hipError_t es = hipStreamSynchronize(B->stream);
+        hipError_t es = hipStreamSynchronize(B->stream);
+        for (int q = 0; q < kMaxStreams - 1 && es == hipSuccess; ++q)
+            if (B->side[q]) es = hipStreamSynchronize(B->side[q]);
         if (es != hipSuccess) return hip_fail(es, "hipStreamSynchronize");
     }
     drop_graphs(B);
@@ -232,7 +280,7 @@ int build_plan(mcubes_batch *B, const std::vector<char> &active) {
         }
         if (c.max_block < 64) return fail(MCUBES_E_DEVICE, "V-Sample batch kernel unavailable");
         const ClassCfg &cf = B->cfg[kv.first];
-        int block = B->forced_block ? B->forced_block : (cf.block ? cf.block : c.max_block);
+        int block = B->forced_block ? B->forced_block : (cf.block ? cf.block : default_block(c));
         if (block > c.max_block) block = c.max_block / 64 * 64;
         c.block = block;
         c.blocks = class_shares(B, c, block, cf.blocks);
@@ -284,6 +332,7 @@ int build_plan(mcubes_batch *B, const std::vector<char> &active) {
     B->planned = active;
     B->planned_samples = samples;
     B->ntiles = (int)tiles.size();
+    assign_branches(B);
     return MCUBES_OK;
 }
 
@@ -295,11 +344,26 @@ hipError_t launch_class(const mcubes_batch *B, const ClassPlan &c, bool frozen, 
 
 // One iteration: [zero bins] -> V-Sample per class -> reduce -> combine ->
 // [refine] -> advance the iteration counter.  `frozen` = no refinement.
+// Every class's V-Sample, forked over the branches after the work already on
+// s and joined back into s.
+hipError_t enqueue_vsample(const mcubes_batch *B, bool frozen, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    const int side = B->streams - 1;
+    if (side > 0) e = hipEventRecord(B->fork, s);
+    for (int k = 0; k < side && e == hipSuccess; ++k) e = hipStreamWaitEvent(B->side[k], B->fork, 0);
+    for (const ClassPlan &c : B->plan)
+        if (e == hipSuccess) e = launch_class(B, c, frozen, c.branch ? B->side[c.branch - 1] : s);
+    for (int k = 0; k < side && e == hipSuccess; ++k) {
+        e = hipEventRecord(B->join[k], B->side[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, B->join[k], 0);
+    }
+    return e;
+}
+
 hipError_t enqueue_iteration(const mcubes_batch *B, bool frozen, double rel_tol, hipStream_t s) {
     hipError_t e = hipSuccess;
     if (!frozen) e = launch_fill(B->d_bins, B->bins_len, 0.0, s);
-    for (const ClassPlan &c : B->plan)
-        if (e == hipSuccess) e = launch_class(B, c, frozen, s);
+    if (e == hipSuccess) e = enqueue_vsample(B, frozen, s);
     if (e == hipSuccess) e = launch_batch_reduce(B->d_items, B->n, B->d_partials, B->d_done, B->d_est, s);
     if (e == hipSuccess)
         e = launch_batch_combine(B->n, B->d_est, B->d_states, B->d_done, B->d_done + B->n, B->d_iter,
@@ -459,6 +523,11 @@ int mcubes_batch_create(const mcubes_batch_item *items, int n, uint64_t seed,
     }
     e = hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking);
     for (int q = 0; q < 3 && e == hipSuccess; ++q) e = hipEventCreate(&B->ev[q]);
+    for (int q = 0; q < kMaxStreams - 1 && e == hipSuccess; ++q) {
+        e = hipStreamCreateWithFlags(&B->side[q], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&B->join[q], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&B->fork, hipEventDisableTiming);
     if (e == hipSuccess)
         e = hipMemcpy(B->d_axes, B->axes.data(), B->axes.size() * sizeof(uint2),
                       hipMemcpyHostToDevice);
@@ -497,6 +566,7 @@ int mcubes_batch_get_info(const mcubes_batch *B, mcubes_batch_info *info) {
     info->classes = (int32_t)B->plan.size();
     info->tiles = B->ntiles;
     info->launches = launches_per_iteration(B);
+    info->streams = B->streams;
     info->nbins = B->nb;
     info->tuned = B->tuned ? 1 : 0;
     info->grids_len = B->grids_len;
@@ -525,6 +595,7 @@ int mcubes_batch_get_class(const mcubes_batch *B, int k, mcubes_batch_class *out
     out->samples = c.samples;
     auto it = B->cfg.find(c.key);
     out->tuned_ms = it == B->cfg.end() ? 0.0 : it->second.tuned_ms;
+    out->default_ms = it == B->cfg.end() ? 0.0 : it->second.default_ms;
     return MCUBES_OK;
 }
 
@@ -540,12 +611,25 @@ int mcubes_batch_configure_class(mcubes_batch *B, int k, int block_size, int sha
     cf.block = block_size;
     cf.blocks = shares;
     cf.tuned_ms = 0.0;
+    cf.default_ms = 0.0;
     const int saved = B->forced_block;
     B->forced_block = 0;
     const std::vector<char> active = B->planned;
     const int rc = build_plan(B, active);
     B->forced_block = saved;
     return rc;
+}
+
+int mcubes_batch_set_streams(mcubes_batch *B, int streams) {
+    if (!B) return fail(MCUBES_E_ARG, "NULL argument");
+    if (streams < 1 || streams > kMaxStreams)
+        return fail(MCUBES_E_ARG, "streams must be in [1, %d], got %d", kMaxStreams, streams);
+    const hipError_t e = hipStreamSynchronize(B->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    B->streams = streams;
+    assign_branches(B);
+    drop_graphs(B);
+    return MCUBES_OK;
 }
 
 int mcubes_batch_autotune(mcubes_batch *B) {
@@ -556,70 +640,152 @@ int mcubes_batch_autotune(mcubes_batch *B) {
         if (e == hipSuccess) e = hipStreamWaitEvent(B->stream, B->ev[2], 0);
         if (e != hipSuccess) return hip_fail(e, "stream ordering");
     }
-    const std::vector<char> active = B->planned;
-    std::vector<ClassPlan> classes = B->plan;
+    // tune every class, with no integrand marked done
+    const std::vector<char> all(B->n, 1);
+    if (B->planned != all) {
+        const int prc = build_plan(B, all);
+        if (prc != MCUBES_OK) return prc;
+    }
+    e = launch_batch_reset(B->d_states, (int64_t)B->n * MCUBES_STATE_LEN, B->d_done, B->n,
+                           B->d_iter, B->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(B->stream);
+    if (e != hipSuccess) return hip_fail(e, "autotune set-up");
     static const int kBlocks[] = {256, 512, 768, 1024};
     static const int kCubesPerThread[] = {4, 16, 64};
-    for (const ClassPlan &c0 : classes) {
-        ClassPlan c = c0;
-        double best_ms = -1.0;
-        int best_block = 0, best_blocks = 0;
+    std::vector<BatchItem> items = B->items;  // step fields per candidate block size
+    BatchItem *d_items = nullptr;
+    BatchTile *d_tiles = nullptr;
+    double *d_part = nullptr;
+    size_t cap = 0;
+    int rc = MCUBES_OK;
+    if (hipMalloc((void **)&d_items, items.size() * sizeof(BatchItem)) != hipSuccess)
+        return fail(MCUBES_E_ALLOC, "hipMalloc (autotune)");
+    // times one candidate geometry of class c: warm-up, then the mean of two launches
+    auto time_one = [&](const ClassPlan &c, int block, int shares, double *ms_out) -> int {
+        for (int i : c.items) {
+            VsArgs tmp = items[i].args;
+            set_step(tmp, B->dim[i], (uint64_t)block);
+            items[i].step_block = tmp.step;
+            memcpy(items[i].step_digit_block, tmp.step_digit, sizeof tmp.step_digit);
+        }
+        std::vector<BatchTile> tiles;
+        split_class(B, c, shares, tiles);
+        if (tiles.size() > cap) {
+            hipFree(d_tiles);
+            hipFree(d_part);
+            d_tiles = nullptr;
+            d_part = nullptr;
+            cap = tiles.size() + tiles.size() / 4 + 64;
+            if (hipMalloc((void **)&d_tiles, cap * sizeof(BatchTile)) != hipSuccess ||
+                hipMalloc((void **)&d_part, 2 * cap * sizeof(double)) != hipSuccess)
+                return fail(MCUBES_E_ALLOC, "hipMalloc (autotune)");
+        }
+        hipError_t x = hipMemcpy(d_items, items.data(), items.size() * sizeof(BatchItem),
+                                 hipMemcpyHostToDevice);
+        if (x == hipSuccess)
+            x = hipMemcpy(d_tiles, tiles.data(), tiles.size() * sizeof(BatchTile),
+                          hipMemcpyHostToDevice);
+        const int nt = (int)tiles.size();
+        for (int r = 0; r < 3 && x == hipSuccess; ++r) {
+            if (r == 1) x = hipEventRecord(B->ev[0], B->stream);
+            if (x == hipSuccess)
+                x = c.launch[0](d_items, d_tiles, nt, B->d_grids, B->d_bins, d_part, B->d_iter,
+                                B->d_done, block, c.lds, B->stream);
+        }
+        if (x == hipSuccess) x = hipEventRecord(B->ev[1], B->stream);
+        if (x == hipSuccess) x = hipEventSynchronize(B->ev[1]);
+        float ms = 0.0f;
+        if (x == hipSuccess) x = hipEventElapsedTime(&ms, B->ev[0], B->ev[1]);
+        if (x != hipSuccess) return hip_fail(x, "autotune launch");
+        *ms_out = ms / 2.0;
+        return MCUBES_OK;
+    };
+    for (const ClassPlan &c : B->plan) {
+        double best_ms = -1.0, default_ms = 0.0;
+        int best_block = 0, best_shares = 0;
+        // the library's default geometry first
+        const int dblock = B->forced_block ? std::min(B->forced_block, c.max_block / 64 * 64)
+                                           : default_block(c);
+        const int dshares = class_shares(B, c, dblock, 0);
+        if (dshares >= 1) {
+            rc = time_one(c, dblock, dshares, &default_ms);
+            if (rc != MCUBES_OK) break;
+            best_ms = default_ms;
+            best_block = dblock;
+            best_shares = dshares;
+        }
         for (int bs : kBlocks) {
             if (bs > c.max_block || (B->forced_block && bs != B->forced_block)) continue;
             const int R = resident_blocks(B, c, bs);
             if (R < 1) continue;
-            std::vector<int> counts = {R, 2 * R, 4 * R};
+            std::vector<int64_t> counts = {2 * (int64_t)R, 4 * (int64_t)R, 8 * (int64_t)R,
+                                           16 * (int64_t)R};
             for (int cpt : kCubesPerThread) {
-                int64_t q = (c.cubes + (int64_t)bs * cpt - 1) / ((int64_t)bs * cpt);
-                if (q < 1) q = 1;
-                if (q < R) counts.push_back((int)q);
+                const int64_t q = (c.cubes + (int64_t)bs * cpt - 1) / ((int64_t)bs * cpt);
+                if (q < R) counts.push_back(q);
             }
-            for (int &q : counts) q = (int)std::min<int64_t>(q, std::min<int64_t>(c.cubes, kMaxShares));
+            for (int64_t &q : counts) q = std::max<int64_t>(1, std::min<int64_t>(q, std::min<int64_t>(c.cubes, kMaxShares)));
             std::sort(counts.begin(), counts.end());
             counts.erase(std::unique(counts.begin(), counts.end()), counts.end());
-            for (int nblk : counts) {
-                ClassCfg &cf = B->cfg[c.key];
-                cf.block = bs;
-                cf.blocks = nblk;
-                const int saved = B->forced_block;
-                B->forced_block = 0;
-                int rc = build_plan(B, active);
-                B->forced_block = saved;
-                if (rc != MCUBES_OK) return rc;
-                const ClassPlan *cp = nullptr;
-                for (const ClassPlan &x : B->plan)
-                    if (!(x.key < c.key) && !(c.key < x.key)) cp = &x;
-                if (!cp) return fail(MCUBES_E_DEVICE, "internal: class lost while tuning");
-                e = launch_class(B, *cp, false, B->stream);  // warm-up
-                if (e == hipSuccess) e = hipEventRecord(B->ev[0], B->stream);
-                for (int r = 0; r < 2 && e == hipSuccess; ++r) e = launch_class(B, *cp, false, B->stream);
-                if (e == hipSuccess) e = hipEventRecord(B->ev[1], B->stream);
-                if (e == hipSuccess) e = hipEventSynchronize(B->ev[1]);
-                float ms = 0.0f;
-                if (e == hipSuccess) e = hipEventElapsedTime(&ms, B->ev[0], B->ev[1]);
-                if (e != hipSuccess) return hip_fail(e, "autotune launch");
-                const double t = ms / 2.0;
-                if (best_ms < 0.0 || t < best_ms) {
-                    best_ms = t;
+            for (int64_t q : counts) {
+                if (bs == dblock && q == dshares) continue;
+                double ms = 0.0;
+                rc = time_one(c, bs, (int)q, &ms);
+                if (rc != MCUBES_OK) break;
+                if (best_ms < 0.0 || ms < best_ms) {
+                    best_ms = ms;
                     best_block = bs;
-                    best_blocks = nblk;
+                    best_shares = (int)q;
                 }
             }
+            if (rc != MCUBES_OK) break;
         }
-        if (best_ms < 0.0)
-            return fail(MCUBES_E_DEVICE, "no launch geometry fits class (family %d, dim %d)",
-                        c.key.family, c.key.dim);
+        if (rc != MCUBES_OK) break;
+        if (best_ms < 0.0) {
+            rc = fail(MCUBES_E_DEVICE, "no launch geometry fits class (family %d, dim %d)",
+                      c.key.family, c.key.dim);
+            break;
+        }
         ClassCfg &cf = B->cfg[c.key];
         cf.block = best_block;
-        cf.blocks = best_blocks;
+        cf.blocks = best_shares;
         cf.tuned_ms = best_ms;
+        cf.default_ms = default_ms;
     }
+    hipFree(d_items);
+    hipFree(d_tiles);
+    hipFree(d_part);
+    if (rc != MCUBES_OK) return rc;
     const int saved = B->forced_block;
     B->forced_block = 0;
-    const int rc = build_plan(B, active);
+    rc = build_plan(B, all);
     B->forced_block = saved;
     if (rc != MCUBES_OK) return rc;
-    // the tuning launches added to the bin sums and partials: start clean
+    // number of concurrent streams for the class launches: the fastest of
+    // 1, 2, 3, 4 over all classes (warm-up, then the mean of two)
+    double best_ms = -1.0;
+    int best_streams = 1;
+    for (int ns = 1; ns <= kMaxStreams; ++ns) {
+        B->streams = ns;
+        assign_branches(B);
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) {
+            if (r == 1) e = hipEventRecord(B->ev[0], B->stream);
+            if (e == hipSuccess) e = enqueue_vsample(B, false, B->stream);
+        }
+        if (e == hipSuccess) e = hipEventRecord(B->ev[1], B->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(B->ev[1]);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, B->ev[0], B->ev[1]);
+        if (e != hipSuccess) return hip_fail(e, "autotune (streams)");
+        if (best_ms < 0.0 || ms < best_ms) {
+            best_ms = ms;
+            best_streams = ns;
+        }
+    }
+    B->streams = best_streams;
+    assign_branches(B);
+    drop_graphs(B);
+    // the tuning launches added to the bin sums: start clean
     e = launch_fill(B->d_bins, B->bins_len, 0.0, B->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(B->stream);
     if (e != hipSuccess) return hip_fail(e, "autotune");
@@ -661,8 +827,7 @@ int mcubes_batch_step(mcubes_batch *B, uint32_t iteration, double *grids, double
         e = hipMemcpyAsync(B->d_grids, grids, (size_t)B->grids_len * sizeof(double),
                            hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_fill(B->d_bins, B->bins_len, 0.0, s);
-    for (const ClassPlan &c : B->plan)
-        if (e == hipSuccess) e = launch_class(B, c, false, s);
+    if (e == hipSuccess) e = enqueue_vsample(B, false, s);
     if (e == hipSuccess) e = launch_batch_reduce(B->d_items, B->n, B->d_partials, B->d_done, B->d_est, s);
     if (e == hipSuccess)
         e = launch_batch_refine(B->d_items, B->d_axes, (int)B->axes.size(), B->d_grids, B->d_bins,

@@ -54,9 +54,11 @@ int main(void) {
     F(mcubes_batch_item, ncall) F(mcubes_batch_item, params)
     printf("mcubes_batch_info size %zu\n", sizeof(mcubes_batch_info));
     F(mcubes_batch_info, grids_len) F(mcubes_batch_info, last_iterations)
+    F(mcubes_batch_info, streams)
     F(mcubes_batch_info, last_samples) F(mcubes_batch_info, last_ms)
     printf("mcubes_batch_class size %zu\n", sizeof(mcubes_batch_class));
     F(mcubes_batch_class, shares) F(mcubes_batch_class, samples) F(mcubes_batch_class, tuned_ms)
+    F(mcubes_batch_class, default_ms)
     printf("MCUBES_STATE_LEN x %d\n", MCUBES_STATE_LEN);
     return 0;
 }

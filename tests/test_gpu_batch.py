@@ -208,17 +208,21 @@ def _compare_runs(problems, runs, base, ref, what):
 def test_graph_replays_match_eager(mc):
     """The captured graph, replayed once per iteration with host
     synchronisation and flag reads between replays, against the same kernels
-    launched one by one: every iteration of every integrand (the first
+    launched one by one, on one stream and with the class launches spread over
+    three concurrent streams: every iteration of every integrand (the first
     iteration, on the uniform grid, to 1e-12; later ones to the drift bound)."""
     probs = workloads.batch_problems(n=16, seed=12, ncall_lo=5e3, ncall_hi=2e5)
     b = mc.Batch(_items(probs), seed=5)
     rc_e, eager = b.integrate(6, 0.0, use_graph=False, grids=True, traces=True)
     rc_g, graph = b.integrate(6, 0.0, use_graph=True, grids=True, traces=True)
+    b.set_streams(3)  # class launches on three concurrent streams: graph branches
+    assert b.info()["streams"] == 3
     rc_g2, graph2 = b.integrate(6, 0.0, use_graph=True, grids=True, traces=True)
-    assert rc_e == rc_g == rc_g2 == mc.MCUBES_NOT_CONVERGED
+    rc_e2, eager2 = b.integrate(6, 0.0, use_graph=False, grids=True, traces=True)
+    assert rc_e == rc_g == rc_g2 == rc_e2 == mc.MCUBES_NOT_CONVERGED
     ref = _oracle_all(probs, 6, 0.0, 5, 500)
     _compare(probs, eager, ref, "eager")
-    _compare_runs(probs, [graph, graph2], eager, ref, "graph vs eager")
+    _compare_runs(probs, [graph, graph2, eager2], eager, ref, "graph vs eager")
     for e, g in zip(eager, graph):
         assert e["trace_I"][0] == pytest.approx(g["trace_I"][0], rel=1e-15, abs=1e-300)
 
