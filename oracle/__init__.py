@@ -4,10 +4,11 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  The product path (the HIP library and
 its Python binding) never imports or calls it.
 
-The arithmetic lives in ``mcubes_oracle.c`` (plain single-threaded FP64 C,
-built by ``oracle/build.py``); this module only marshals numpy arrays.
-Integrand family ids follow the order of eqs. 1-6 of the paper plus the
-addition integrand of §5.3.
+The arithmetic lives in ``mcubes_oracle.c`` and ``flow_oracle.c`` (plain
+single-threaded FP64 C, built by ``oracle/build.py``); this module only
+marshals numpy arrays.  Integrand family ids follow the order of eqs. 1-6 of
+the paper, then the addition integrand of §5.3 and the correlated Gaussian
+mixture used with the learned proposal.
 """
 import ctypes
 import os
@@ -17,9 +18,18 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-OSCILLATORY, PRODUCT_PEAK, CORNER_PEAK, GAUSSIAN, C0, DISCONTINUOUS, ADDITION = range(7)
+OSCILLATORY, PRODUCT_PEAK, CORNER_PEAK, GAUSSIAN, C0, DISCONTINUOUS, ADDITION, MIXTURE = range(8)
 FAMILY_NAMES = ["oscillatory", "product_peak", "corner_peak", "gaussian", "c0",
-                "discontinuous", "addition"]
+                "discontinuous", "addition", "mixture"]
+
+# flow constants (flow_oracle.h)
+FLOW_D, FLOW_LAYERS, FLOW_NA, FLOW_NB, FLOW_BLOBS = 6, 4, 3, 3, 32
+FLOW_IN, FLOW_HID, FLOW_BINS = FLOW_NA * FLOW_BLOBS, 64, 16
+FLOW_RAW = 2 * FLOW_BINS + 1
+FLOW_OUT = FLOW_NB * FLOW_RAW
+FLOW_LAYER_PARAMS = (FLOW_IN * FLOW_HID + FLOW_HID + FLOW_HID * FLOW_HID + FLOW_HID
+                     + FLOW_HID * FLOW_OUT + FLOW_OUT)
+FLOW_PARAMS = FLOW_LAYERS * FLOW_LAYER_PARAMS
 
 _lib = None
 
@@ -64,6 +74,28 @@ def lib():
                                 ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, _i64p, _dp, _dp,
                                 _dp]
     L.mco_integrate.restype = ctypes.c_int
+    L.mcf_param_count.argtypes = []
+    L.mcf_param_count.restype = ctypes.c_int
+    L.mcf_masks.argtypes = [ctypes.c_int, _ip, _ip]
+    L.mcf_masks.restype = None
+    for fn in (L.mcf_spline_forward, L.mcf_spline_inverse):
+        fn.argtypes = [_dp, ctypes.c_double, _dp, _dp]
+        fn.restype = ctypes.c_int
+    L.mcf_conditioner.argtypes = [_dp, _dp, ctypes.c_int, _dp]
+    L.mcf_conditioner.restype = None
+    for fn in (L.mcf_density, L.mcf_sample):
+        fn.argtypes = [_dp, _dp, ctypes.c_int, _dp, _dp]
+        fn.restype = None
+    L.mcf_loss_grad.argtypes = [_dp, ctypes.c_int64, _dp, _dp, _dp]
+    L.mcf_loss_grad.restype = ctypes.c_double
+    L.mcf_adam.argtypes = [_dp, _dp, _dp, _dp, ctypes.c_int64, ctypes.c_int, ctypes.c_double,
+                           ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    L.mcf_adam.restype = None
+    L.mcf_proposal_range.argtypes = [_dp, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int64,
+                                     ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
+                                     ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,
+                                     ctypes.c_int64, _dp]
+    L.mcf_proposal_range.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -189,3 +221,93 @@ def integrate(family, params, dim, ncall, itmax, rel_tol, seed, nb=500, alpha=1.
             "chi2_dof": float(res[2]), "iterations": n, "dof": int(info[1]),
             "g": int(info[2]), "m": int(info[3]), "p": int(info[4]), "n": int(info[5]),
             "converged": bool(info[6]), "grid": grid, "trace_I": tI[:n], "trace_var": tV[:n]}
+
+
+# ---------------------------------------------------------------------------
+# learned proposal (flow_oracle.c)
+# ---------------------------------------------------------------------------
+def flow_masks(layer):
+    a = (ctypes.c_int * FLOW_NA)()
+    b = (ctypes.c_int * FLOW_NB)()
+    lib().mcf_masks(int(layer), a, b)
+    return list(a), list(b)
+
+
+def spline_forward(raw, u):
+    """-> (y, pdf, bin) of the piecewise-quadratic CDF with raw parameters raw[33]."""
+    raw, rp = _d(raw)
+    y, pdf = ctypes.c_double(), ctypes.c_double()
+    b = lib().mcf_spline_forward(rp, float(u), ctypes.byref(y), ctypes.byref(pdf))
+    return y.value, pdf.value, b
+
+
+def spline_inverse(raw, y):
+    """-> (u, pdf, bin): the inverse CDF."""
+    raw, rp = _d(raw)
+    u, pdf = ctypes.c_double(), ctypes.c_double()
+    b = lib().mcf_spline_inverse(rp, float(y), ctypes.byref(u), ctypes.byref(pdf))
+    return u.value, pdf.value, b
+
+
+def flow_conditioner(layer_params, ua, bf16=False):
+    lp, lpp = _d(layer_params)
+    ua, up = _d(ua)
+    out = np.zeros(FLOW_OUT)
+    lib().mcf_conditioner(lpp, up, int(bool(bf16)), out.ctypes.data_as(_dp))
+    return out
+
+
+def flow_density(theta, x, bf16=False):
+    """x -> (z, log q(x))."""
+    theta, tp = _d(theta)
+    x, xp = _d(x)
+    z = np.zeros(FLOW_D)
+    lq = ctypes.c_double()
+    lib().mcf_density(tp, xp, int(bool(bf16)), z.ctypes.data_as(_dp), ctypes.byref(lq))
+    return z, lq.value
+
+
+def flow_sample(theta, z, bf16=False):
+    """z -> (x, log q(x))."""
+    theta, tp = _d(theta)
+    z, zp = _d(z)
+    x = np.zeros(FLOW_D)
+    lq = ctypes.c_double()
+    lib().mcf_sample(tp, zp, int(bool(bf16)), x.ctypes.data_as(_dp), ctypes.byref(lq))
+    return x, lq.value
+
+
+def flow_loss_grad(theta, xs, ws):
+    """-> (loss, grad): weighted negative log-likelihood and its gradient."""
+    theta, tp = _d(theta)
+    xs, xp = _d(np.asarray(xs).reshape(-1, FLOW_D))
+    ws, wp = _d(ws)
+    grad = np.zeros(FLOW_PARAMS)
+    loss = lib().mcf_loss_grad(tp, len(ws), xp, wp, grad.ctypes.data_as(_dp))
+    return loss, grad
+
+
+def flow_adam(theta, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step; returns new (theta, m, v) arrays."""
+    theta = np.array(theta, dtype=np.float64)
+    m = np.array(m, dtype=np.float64)
+    v = np.array(v, dtype=np.float64)
+    grad, gp = _d(grad)
+    lib().mcf_adam(theta.ctypes.data_as(_dp), m.ctypes.data_as(_dp), v.ctypes.data_as(_dp), gp,
+                   len(theta), int(step), float(lr), float(beta1), float(beta2), float(eps))
+    return theta, m, v
+
+
+def flow_proposal_range(theta, family, params, g, m, p, seed, stream, iteration, c_begin, c_end,
+                        bf16=False):
+    """Sums (sum S_c, sum var_c) over cubes [c_begin, c_end) of one iteration
+    that samples through the flow."""
+    theta, tp = _d(theta)
+    params, pp = _d(params)
+    sums = np.zeros(2)
+    rc = lib().mcf_proposal_range(tp, int(bool(bf16)), int(family), pp, int(g), int(m), int(p),
+                                  int(seed), int(stream) & 0xffffffff, int(iteration),
+                                  int(c_begin), int(c_end), sums.ctypes.data_as(_dp))
+    if rc != 0:
+        raise ValueError("mcf_proposal_range failed")
+    return float(sums[0]), float(sums[1])

@@ -8,13 +8,13 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "mcubes_oracle.c")
+SRCS = [os.path.join(HERE, "mcubes_oracle.c"), os.path.join(HERE, "flow_oracle.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-std=gnu11", "-O2", "-ffp-contract=off", "-fno-fast-math",
-           "-Wall", "-Wextra", "-shared", "-fPIC", "-o", LIB, SRC, "-lm"]
+           "-Wall", "-Wextra", "-shared", "-fPIC", "-o", LIB, *SRCS, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -102,7 +102,27 @@ def addition(params, dim):
     return mp.mpf(dim) / 2
 
 
-BY_FAMILY = [oscillatory, product_peak, corner_peak, gaussian, c0, discontinuous, addition]
+def mixture(params, dim):
+    """Equal mixture of N(m_k 1, s^2 [(1 - r) I + r 1 1^T]), k = 1, 2, over the
+    unit cube (a_0 = s, a_1 = r >= 0, u_0 = m_1, u_1 = m_2).  An equicorrelated
+    Gaussian vector is m + s (sqrt(1 - r) e_j + sqrt(r) h) with independent
+    standard normals e_j, h; given h the coordinates are independent, so
+      P(box) = int phi(h) [Phi((1 - m - s sqrt(r) h) / (s sqrt(1 - r)))
+                           - Phi((-m - s sqrt(r) h) / (s sqrt(1 - r)))]^d dh."""
+    s, r = mp.mpf(float(params[0])), mp.mpf(float(params[1]))
+    total = mp.mpf(0)
+    for m in (mp.mpf(float(params[dim])), mp.mpf(float(params[dim + 1]))):
+        sd = s * mp.sqrt(1 - r)
+
+        def integrand(h, m=m, sd=sd):
+            c = m + s * mp.sqrt(r) * h
+            return mp.npdf(h) * (mp.ncdf((1 - c) / sd) - mp.ncdf(-c / sd)) ** dim
+        total += mp.quad(integrand, [-mp.inf, -10, -5, 0, 5, 10, mp.inf])
+    return total / 2
+
+
+BY_FAMILY = [oscillatory, product_peak, corner_peak, gaussian, c0, discontinuous, addition,
+             mixture]
 
 
 def integral(family, params, dim):

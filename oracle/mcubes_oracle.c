@@ -168,6 +168,32 @@ double mco_integrand(int family, int dim, const double *params, const double *x)
         for (int i = 0; i < dim; ++i) s = s + x[i];
         return s;
     }
+    case MCO_MIXTURE: {
+        /* Equal mixture of two Gaussians N(m_k 1, S), k = 1, 2, with the
+         * equicorrelated covariance S = s^2 [(1 - r) I + r 1 1^T]
+         * (a_0 = s, a_1 = r, u_0 = m_1, u_1 = m_2; not one of the paper's
+         * integrands).  S has eigenvalue s^2 (1 - r + d r) along 1 and
+         * s^2 (1 - r) across it, so
+         *   y^T S^-1 y = (|y|^2 - r/(1 - r + d r) (sum y)^2) / (s^2 (1 - r)),
+         *   det S = s^(2d) (1 - r)^(d-1) (1 - r + d r). */
+        const double s = a[0], r = a[1];
+        const double lam = 1.0 - r + (double)dim * r;
+        const double c1 = r / lam;
+        const double c2 = 1.0 / (2.0 * s * s * (1.0 - r));
+        const double norm = 0.5 / (pow(2.0 * M_PI, 0.5 * (double)dim) * pow(s, (double)dim) *
+                                   pow(1.0 - r, 0.5 * (double)(dim - 1)) * sqrt(lam));
+        double f = 0.0;
+        for (int k = 0; k < 2; ++k) {
+            double S1 = 0.0, S2 = 0.0;
+            for (int i = 0; i < dim; ++i) {
+                double t = x[i] - u[k];
+                S1 = S1 + t;
+                S2 = fma(t, t, S2);
+            }
+            f = f + exp(-(c2 * (S2 - c1 * S1 * S1)));
+        }
+        return norm * f;
+    }
     default:
         return NAN;
     }

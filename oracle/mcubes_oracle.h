@@ -18,7 +18,8 @@ enum {
     MCO_GAUSSIAN = 3,
     MCO_C0 = 4,
     MCO_DISCONTINUOUS = 5,
-    MCO_ADDITION = 6
+    MCO_ADDITION = 6,
+    MCO_MIXTURE = 7
 };
 
 void mco_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

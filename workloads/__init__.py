@@ -13,9 +13,9 @@ from typing import List
 
 import numpy as np
 
-OSCILLATORY, PRODUCT_PEAK, CORNER_PEAK, GAUSSIAN, C0, DISCONTINUOUS, ADDITION = range(7)
+OSCILLATORY, PRODUCT_PEAK, CORNER_PEAK, GAUSSIAN, C0, DISCONTINUOUS, ADDITION, MIXTURE = range(8)
 FAMILY_NAMES = ["oscillatory", "product_peak", "corner_peak", "gaussian", "c0",
-                "discontinuous", "addition"]
+                "discontinuous", "addition", "mixture"]
 
 
 @dataclass
@@ -129,3 +129,40 @@ def batch_problems(n=512, seed=BATCH_SEED, ncall_lo=1e6, ncall_hi=1e8, nbins=500
         pr.name = f"batch{i}_{pr.name}"
         out.append(pr)
     return out
+
+
+def mixture_6d(ncall=1 << 26, itmax=50, rel_tol=1e-3):
+    """6-D equal mixture of two correlated Gaussians centred at 1/3 and 2/3 on
+    the diagonal, standard deviation 0.05 and correlation 0.9 on every pair of
+    axes; 2^26 samples per iteration.  Its integral over the unit cube is 1 to
+    within 12 Phi(-20/3) ~ 1.6e-10 (the mass outside the cube)."""
+    params = [0.05, 0.9] + [0.0] * 4 + [1.0 / 3.0, 2.0 / 3.0] + [0.0] * 4
+    return Problem("mixture_6d", MIXTURE, 6, params, ncall=ncall, nbins=500, itmax=itmax,
+                   rel_tol=rel_tol, seed=0)
+
+
+def flow_init(seed=7, scale=1.0):
+    """Initial flow parameters (67212 FP64 values in the layout of the flow):
+    Glorot-uniform hidden weights (numpy PCG64, seeded) times `scale`, small
+    hidden biases, and a zero output layer, so that the initial flow is the
+    identity map with density 1."""
+    return flow_random(seed, scale=scale, out_scale=0.0)
+
+
+def flow_random(seed, scale=1.0, out_scale=0.1):
+    """Random flow parameters for tests: Glorot-uniform weights times `scale`
+    for the hidden layers and `out_scale` for the output layer, small random
+    biases."""
+    blobs, na, hid, bins, nb = 32, 3, 64, 16, 3
+    n_in, n_out = na * blobs, nb * (2 * bins + 1)
+    rng = np.random.default_rng(seed)
+    parts = []
+    for _ in range(4):
+        lim1 = scale * np.sqrt(6.0 / (n_in + hid))
+        lim2 = scale * np.sqrt(6.0 / (hid + hid))
+        lim3 = out_scale * np.sqrt(6.0 / (hid + n_out))
+        parts += [rng.uniform(-lim1, lim1, n_in * hid), rng.uniform(-0.05, 0.05, hid) * scale,
+                  rng.uniform(-lim2, lim2, hid * hid), rng.uniform(-0.05, 0.05, hid) * scale,
+                  rng.uniform(-lim3, lim3, hid * n_out),
+                  rng.uniform(-1.0, 1.0, n_out) * out_scale]
+    return np.concatenate(parts)
