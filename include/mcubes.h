@@ -45,6 +45,9 @@ extern "C" {
 
 #define MCUBES_MAX_DIM 10
 #define MCUBES_MAX_BINS 500
+/* The learned proposal: dimension and number of parameters (see below). */
+#define MCUBES_FLOW_DIM 6
+#define MCUBES_FLOW_PARAMS 67212
 /* Combined-state buffer: 8 scalars followed by (I_t, var_t) per iteration. */
 #define MCUBES_STATE_HEADER 8
 #define MCUBES_MAX_ITERATIONS 1024
@@ -68,7 +71,12 @@ typedef enum {
  *   GAUSSIAN       exp(-sum a_i^2 (x_i - u_i)^2)                    eq. 4
  *   C0             exp(-sum a_i |x_i - u_i|)                        eq. 5
  *   DISCONTINUOUS  exp(sum a_i x_i) if x_i < u_i for all i, else 0  eq. 6
- *   ADDITION       sum x_i                                          §5.3   */
+ *   ADDITION       sum x_i                                          §5.3
+ *   MIXTURE        equal mixture of N(u_0 1, S) and N(u_1 1, S),
+ *                  S = a_0^2 [(1 - a_1) I + a_1 1 1^T] (a_0 > 0,
+ *                  0 <= a_1 < 1, dim >= 2; the other a_i, u_i unused):
+ *                  a non-separable integrand (not in the paper) for the
+ *                  learned proposal                                        */
 typedef enum {
     MCUBES_OSCILLATORY = 0,
     MCUBES_PRODUCT_PEAK = 1,
@@ -76,7 +84,8 @@ typedef enum {
     MCUBES_GAUSSIAN = 3,
     MCUBES_C0 = 4,
     MCUBES_DISCONTINUOUS = 5,
-    MCUBES_ADDITION = 6
+    MCUBES_ADDITION = 6,
+    MCUBES_MIXTURE = 7
 } mcubes_family;
 
 /* Arithmetic of the map and the integrand inside V-Sample.  MCUBES_FP32 draws
@@ -84,7 +93,7 @@ typedef enum {
  * and evaluates the integrand in FP32 from an FP32 copy of the grid; the
  * Jacobian, weights, cube statistics, bin sums, reductions, refinement and
  * combination stay FP64. */
-typedef enum { MCUBES_FP64 = 0, MCUBES_FP32 = 1 } mcubes_precision;
+typedef enum { MCUBES_FP64 = 0, MCUBES_FP32 = 1, MCUBES_BF16 = 2 } mcubes_precision;
 
 typedef struct {
     int32_t nbins;       /* bins per axis, 2..500; default 500 (Alg. 2 uses 500) */
@@ -354,6 +363,127 @@ int mcubes_batch_step(mcubes_batch *batch, uint32_t iteration, double *grids, do
  * or an error (then results are not written). */
 int mcubes_batch_integrate(mcubes_batch *batch, int itmax, double rel_tol, int use_graph,
                            mcubes_result *results, double *grids_out, double *traces);
+
+/* ------------------------------------------------------------------------
+ * Learned proposal (not part of the paper): a normalizing flow used in place
+ * of the separable VEGAS map for non-separable integrands, after the design
+ * of "Neural Importance Sampling" (Müller et al., 2019).  Over (0,1)^6 the
+ * flow maps x to z through four coupling layers; layer l keeps coordinates
+ * A_l = {0,1,2}, {3,4,5}, {0,2,4}, {1,3,5} and maps every other coordinate
+ * through the CDF of a piecewise-linear density with 16 bins whose widths
+ * (softmax) and 17 vertex heights (exp, scaled to integrate to 1) are the
+ * 99 outputs of a network of u_{A_l}: one-blob encoding (32 Gaussian bumps
+ * of width 1/32 per input), two hidden layers of 64 ReLU units.  q(x) is the
+ * product of the spline densities met on the way x -> z; sampling draws z
+ * and inverts the layers.  Parameters (MCUBES_FLOW_PARAMS values) per layer,
+ * row-major with the input index first: W1[96][64], b1[64], W2[64][64],
+ * b2[64], W3[64][99], b3[99].
+ *
+ * The flow keeps FP32 master parameters, Adam moments and a gradient on the
+ * device.  Precision MCUBES_FP32 evaluates it in FP32, one thread per
+ * sample; MCUBES_BF16 (sampling only) runs the network's matrix products on
+ * the BF16 matrix cores with FP32 accumulation.
+ * ---------------------------------------------------------------------- */
+typedef struct mcubes_flow mcubes_flow;
+
+/* theta: host, MCUBES_FLOW_PARAMS values (copied).  Adam state zeroed. */
+int mcubes_flow_create(const double *theta, mcubes_flow **flow);
+void mcubes_flow_destroy(mcubes_flow *flow);
+/* theta (host) <- the current FP32 parameters. */
+int mcubes_flow_get_params(const mcubes_flow *flow, double *theta);
+/* Replaces the parameters and zeroes the Adam state. */
+int mcubes_flow_set_params(mcubes_flow *flow, const double *theta);
+
+/* d_x (n x 6, device) -> d_z (n x 6) and d_logq (n): the density direction. */
+int mcubes_flow_density(mcubes_flow *flow, int precision, const double *d_x, int64_t n,
+                        double *d_z, double *d_logq, void *stream);
+/* d_z (n x 6, device, in (0,1)) -> d_x (n x 6) and d_logq = log q(x). */
+int mcubes_flow_sample(mcubes_flow *flow, int precision, const double *d_z, int64_t n,
+                       double *d_x, double *d_logq, void *stream);
+
+/* Weighted negative log-likelihood of n samples (x_i, w_i >= 0, sum > 0):
+ * *d_loss (device, 1 double) += -sum w_i log q(x_i) / sum w_i (zero it
+ * first); the gradient with respect to the parameters is kept in the flow
+ * (for mcubes_flow_adam_step) and copied to d_grad (device,
+ * MCUBES_FLOW_PARAMS doubles) when that is not NULL.  FP32. */
+int mcubes_flow_loss_grad(mcubes_flow *flow, const double *d_x, const double *d_w, int64_t n,
+                          double *d_grad, double *d_loss, void *stream);
+/* One Adam step (bias-corrected; the flow counts the steps) with the kept gradient. */
+int mcubes_flow_adam_step(mcubes_flow *flow, double lr, double beta1, double beta2, double eps,
+                          void *stream);
+/* epochs passes of mini-batches of `batch` consecutive samples (the last one
+ * shorter), one Adam step each (beta1 0.9, beta2 0.999, eps 1e-8).
+ * losses (host, epochs doubles, may be NULL): mean batch loss per epoch. */
+int mcubes_flow_train(mcubes_flow *flow, const double *d_x, const double *d_w, int64_t n,
+                      int epochs, int64_t batch, double lr, double *losses, void *stream);
+
+/* The samples and weights w = f J of work items [w_begin, w_begin + count)
+ * of iteration `iteration` of the plain method on d_grid: work item w is
+ * cube (w mult) mod m (V-Sample's visiting order, which spreads a prefix
+ * over the whole domain; mult is coprime to the cube side), and its p
+ * samples are exactly those V-Sample draws there.  d_x: count p x dim,
+ * d_w: count p (device); rows in work-item order. */
+int mcubes_vsample_dump(const mcubes_plan *plan, uint32_t iteration, const double *d_grid,
+                        int64_t w_begin, int64_t count, double *d_x, double *d_w, void *stream);
+
+/* n unstratified samples of the flow (FP32) with weights w = f(x)/q(x) for
+ * the plan's integrand (dim 6): sample i draws z from Philox counter
+ * (i, stream_id | 0xC0000000, block, iteration) under the plan's seed.
+ * d_x: n x 6, d_w: n (device).  Training data for refining the flow on
+ * its own samples. */
+int mcubes_flow_draw(mcubes_flow *flow, const mcubes_plan *plan, uint32_t iteration, int64_t n,
+                     double *d_x, double *d_w, void *stream);
+
+/* One m-Cubes iteration with the flow as the map (plan of dim 6, p >= 2):
+ * cube c's sample k draws u from Philox with the plan's seed and stream word
+ * stream_id | 0x80000000, z_j = (c_j + u_j)/g, x = flow sample of z and
+ * w = f(x)/q(x).  d_est (device, 2 doubles) <- (I_t, var_t) as mcubes_reduce
+ * gives them (then mcubes_combine applies unchanged). */
+int mcubes_flow_vsample(mcubes_flow *flow, int precision, const mcubes_plan *plan,
+                        uint32_t iteration, double *d_est, void *stream);
+
+/* The whole learned-proposal pipeline for one integrand of dim 6:
+ *   1. warmup_iters plain m-Cubes iterations (grid refined every time);
+ *   2. the samples and weights of train_items work items of the last of them
+ *      (mcubes_vsample_dump) train the flow for `epochs` epochs;
+ *   3. `rounds` times: round_samples samples of the flow itself with weights
+ *      f/q (mcubes_flow_draw) train it for round_epochs epochs;
+ *   4. flow-mapped iterations (mcubes_flow_vsample, in `precision`) combined
+ *      by inverse-variance weighting until error <= rel_tol |estimate| or
+ *      itmax of them.
+ * Plain m-Cubes stays the judge: if the first flow iteration's variance is
+ * not below the last plain iteration's, the flow is dropped and the
+ * remaining iterations run plain (report->used_flow = 0).  `flow` is trained
+ * in place (start from an identity flow for a fresh run).  out receives the
+ * combined result of the iterations that decide it (flow, or plain on
+ * fallback).  Synchronous; allocates its buffers. */
+typedef struct {
+    int32_t warmup_iters;  /* default 8 */
+    int32_t precision;     /* proposal iterations: MCUBES_BF16 (default) or MCUBES_FP32 */
+    int64_t train_items;   /* default 2^18 (each gives p samples) */
+    int32_t epochs;        /* default 6 */
+    int32_t rounds;        /* default 2 */
+    int64_t round_samples; /* default 2^19 */
+    int32_t round_epochs;  /* default 2 */
+    int32_t reserved;
+    int64_t batch;         /* default 16384 */
+    double lr;             /* default 1e-3 */
+    double round_lr;       /* default 5e-4 */
+} mcubes_flow_options;
+
+typedef struct {
+    double warmup_ms, train_ms, flow_ms, total_ms; /* wall time of the phases (HIP events) */
+    double plain_estimate, plain_error, plain_chi2_dof; /* combined warm-up iterations */
+    double last_plain_var, first_flow_var; /* the judge's comparison */
+    double final_loss;     /* mean batch loss of the last training epoch */
+    int32_t flow_iterations, used_flow;
+} mcubes_flow_report;
+
+void mcubes_default_flow_options(mcubes_flow_options *opt);
+int mcubes_flow_integrate(mcubes_flow *flow, int family, const double *params, int64_t ncall,
+                          int itmax, double rel_tol, uint64_t seed, const mcubes_options *opt,
+                          const mcubes_flow_options *fopt, mcubes_result *out,
+                          mcubes_flow_report *report);
 
 #ifdef __cplusplus
 }

@@ -23,8 +23,9 @@ MCUBES_OK, MCUBES_NOT_CONVERGED = 0, 1
 MCUBES_E_ARG, MCUBES_E_INTEGRAND, MCUBES_E_NONFINITE, MCUBES_E_DEVICE, MCUBES_E_ALLOC = (
     -1, -2, -3, -4, -5)
 (MCUBES_OSCILLATORY, MCUBES_PRODUCT_PEAK, MCUBES_CORNER_PEAK, MCUBES_GAUSSIAN, MCUBES_C0,
- MCUBES_DISCONTINUOUS, MCUBES_ADDITION) = range(7)
-MCUBES_FP64, MCUBES_FP32 = 0, 1
+ MCUBES_DISCONTINUOUS, MCUBES_ADDITION, MCUBES_MIXTURE) = range(8)
+MCUBES_FP64, MCUBES_FP32, MCUBES_BF16 = 0, 1, 2
+MCUBES_FLOW_DIM, MCUBES_FLOW_PARAMS = 6, 67212
 (MCUBES_MB_INTEGRAND, MCUBES_MB_PHILOX, MCUBES_MB_EXP64, MCUBES_MB_COS64, MCUBES_MB_POW64,
  MCUBES_MB_EXP32, MCUBES_MB_COS32, MCUBES_MB_POW32) = range(8)
 
@@ -61,6 +62,23 @@ class mcubes_plan_info(ctypes.Structure):
                 ("samples_per_iter", ctypes.c_int64), ("grid_len", ctypes.c_int64),
                 ("bins_len", ctypes.c_int64), ("partials_len", ctypes.c_int64),
                 ("state_len", ctypes.c_int64)]
+
+
+class mcubes_flow_options(ctypes.Structure):
+    _fields_ = [("warmup_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("train_items", ctypes.c_int64), ("epochs", ctypes.c_int32),
+                ("rounds", ctypes.c_int32), ("round_samples", ctypes.c_int64),
+                ("round_epochs", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("batch", ctypes.c_int64), ("lr", ctypes.c_double), ("round_lr", ctypes.c_double)]
+
+
+class mcubes_flow_report(ctypes.Structure):
+    _fields_ = [("warmup_ms", ctypes.c_double), ("train_ms", ctypes.c_double),
+                ("flow_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("plain_estimate", ctypes.c_double), ("plain_error", ctypes.c_double),
+                ("plain_chi2_dof", ctypes.c_double), ("last_plain_var", ctypes.c_double),
+                ("first_flow_var", ctypes.c_double), ("final_loss", ctypes.c_double),
+                ("flow_iterations", ctypes.c_int32), ("used_flow", ctypes.c_int32)]
 
 
 class mcubes_batch_item(ctypes.Structure):
@@ -129,6 +147,28 @@ _SIGNATURES = {
     "mcubes_batch_autotune": (ctypes.c_int, [_vp]),
     "mcubes_batch_set_streams": (ctypes.c_int, [_vp, ctypes.c_int]),
     "mcubes_batch_step": (ctypes.c_int, [_vp, ctypes.c_uint32, _dp, _dp]),
+    "mcubes_flow_create": (ctypes.c_int, [_dp, ctypes.POINTER(_vp)]),
+    "mcubes_flow_destroy": (None, [_vp]),
+    "mcubes_flow_get_params": (ctypes.c_int, [_vp, _dp]),
+    "mcubes_flow_set_params": (ctypes.c_int, [_vp, _dp]),
+    "mcubes_flow_density": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int64, _vp, _vp, _vp]),
+    "mcubes_flow_sample": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int64, _vp, _vp, _vp]),
+    "mcubes_flow_loss_grad": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp, _vp]),
+    "mcubes_flow_adam_step": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_double, _vp]),
+    "mcubes_flow_train": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int,
+                                         ctypes.c_int64, ctypes.c_double, _dp, _vp]),
+    "mcubes_vsample_dump": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, ctypes.c_int64,
+                                           ctypes.c_int64, _vp, _vp, _vp]),
+    "mcubes_flow_vsample": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_uint32, _vp, _vp]),
+    "mcubes_flow_draw": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, ctypes.c_int64, _vp, _vp, _vp]),
+    "mcubes_default_flow_options": (None, [ctypes.POINTER(mcubes_flow_options)]),
+    "mcubes_flow_integrate": (ctypes.c_int, [_vp, ctypes.c_int, _dp, ctypes.c_int64, ctypes.c_int,
+                                             ctypes.c_double, ctypes.c_uint64,
+                                             ctypes.POINTER(mcubes_options),
+                                             ctypes.POINTER(mcubes_flow_options),
+                                             ctypes.POINTER(mcubes_result),
+                                             ctypes.POINTER(mcubes_flow_report)]),
     "mcubes_batch_integrate": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                               ctypes.POINTER(mcubes_result), _dp, _dp]),
 }
@@ -449,3 +489,95 @@ class Batch:
                 r["trace_var"] = [row[2 * t + 1] for t in range(it)]
             out.append(r)
         return rc, out
+
+
+class Flow:
+    """Owns an mcubes_flow* (the learned proposal); destroyed with the object.
+    theta: MCUBES_FLOW_PARAMS initial parameters (host)."""
+
+    def __init__(self, theta):
+        arr = (ctypes.c_double * MCUBES_FLOW_PARAMS)(*[float(v) for v in theta])
+        h = _vp()
+        _check(lib().mcubes_flow_create(arr, ctypes.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.mcubes_flow_destroy(self.handle)
+            self.handle = None
+
+    def params(self):
+        buf = (ctypes.c_double * MCUBES_FLOW_PARAMS)()
+        _check(lib().mcubes_flow_get_params(self.handle, buf))
+        return list(buf)
+
+    def set_params(self, theta):
+        arr = (ctypes.c_double * MCUBES_FLOW_PARAMS)(*[float(v) for v in theta])
+        _check(lib().mcubes_flow_set_params(self.handle, arr))
+
+    def density(self, d_x, n, d_z, d_logq, precision=MCUBES_FP32, stream=None):
+        _check(lib().mcubes_flow_density(self.handle, int(precision), _dev(d_x, 6 * n, "x"),
+                                         int(n), _dev(d_z, 6 * n, "z"),
+                                         _dev(d_logq, n, "logq"), _stream(stream)))
+
+    def sample(self, d_z, n, d_x, d_logq, precision=MCUBES_FP32, stream=None):
+        _check(lib().mcubes_flow_sample(self.handle, int(precision), _dev(d_z, 6 * n, "z"),
+                                        int(n), _dev(d_x, 6 * n, "x"),
+                                        _dev(d_logq, n, "logq"), _stream(stream)))
+
+    def loss_grad(self, d_x, d_w, n, d_grad, d_loss, stream=None):
+        _check(lib().mcubes_flow_loss_grad(self.handle, _dev(d_x, 6 * n, "x"),
+                                           _dev(d_w, n, "w"), int(n),
+                                           _dev(d_grad, MCUBES_FLOW_PARAMS, "grad")
+                                           if d_grad is not None else None,
+                                           _dev(d_loss, 1, "loss"), _stream(stream)))
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check(lib().mcubes_flow_adam_step(self.handle, float(lr), float(beta1), float(beta2),
+                                           float(eps), _stream(stream)))
+
+    def train(self, d_x, d_w, n, epochs, batch, lr, stream=None):
+        losses = (ctypes.c_double * max(int(epochs), 1))()
+        _check(lib().mcubes_flow_train(self.handle, _dev(d_x, 6 * n, "x"), _dev(d_w, n, "w"),
+                                       int(n), int(epochs), int(batch), float(lr), losses,
+                                       _stream(stream)))
+        return list(losses)[:int(epochs)]
+
+    def draw(self, plan, iteration, n, d_x, d_w, stream=None):
+        _check(lib().mcubes_flow_draw(self.handle, plan.handle, int(iteration), int(n),
+                                      _dev(d_x, 6 * n, "x"), _dev(d_w, n, "w"),
+                                      _stream(stream)))
+
+    def integrate(self, family, params, ncall, itmax, rel_tol, seed, options=None, **flow_opts):
+        """The whole learned-proposal pipeline (mcubes_flow_integrate) ->
+        (result dict, report dict)."""
+        keep, pp = _params(params, MCUBES_FLOW_DIM)
+        fo = mcubes_flow_options()
+        lib().mcubes_default_flow_options(ctypes.byref(fo))
+        for k, v in flow_opts.items():
+            setattr(fo, k, v)
+        opt = options if options is not None else mcubes_default_options()
+        res = mcubes_result()
+        rep = mcubes_flow_report()
+        rc = lib().mcubes_flow_integrate(self.handle, int(family), pp, int(ncall), int(itmax),
+                                         float(rel_tol), int(seed) & (2**64 - 1),
+                                         ctypes.byref(opt), ctypes.byref(fo), ctypes.byref(res),
+                                         ctypes.byref(rep))
+        _check(rc, allow=(MCUBES_OK, MCUBES_NOT_CONVERGED))
+        out = {f: getattr(res, f) for f, _ in mcubes_result._fields_}
+        out["converged"] = bool(out["converged"])
+        return out, {f: getattr(rep, f) for f, _ in mcubes_flow_report._fields_}
+
+    def vsample(self, plan, iteration, d_est, precision=MCUBES_FP32, stream=None):
+        _check(lib().mcubes_flow_vsample(self.handle, int(precision), plan.handle,
+                                         int(iteration), _dev(d_est, 2, "est"),
+                                         _stream(stream)))
+
+
+def mcubes_vsample_dump(plan, iteration, d_grid, w_begin, count, d_x, d_w, stream=None):
+    i = plan.info
+    rows = count * i["samples_per_cube"]
+    _check(lib().mcubes_vsample_dump(plan.handle, int(iteration),
+                                     _dev(d_grid, i["grid_len"], "grid"), int(w_begin),
+                                     int(count), _dev(d_x, rows * i["dim"], "x"),
+                                     _dev(d_w, rows, "w"), _stream(stream)))

@@ -86,6 +86,7 @@ struct mcubes_batch {
     hipGraphExec_t exec[2] = {};  // [frozen]
     // concurrent class launches: branch 0 runs on `stream`, branch k on side[k-1]
     int streams = kMaxStreams;
+    int branches = 1;  // streams in use: min(streams, classes)
     hipStream_t side[kMaxStreams - 1] = {};
     hipEvent_t fork = nullptr, join[kMaxStreams - 1] = {};
 
@@ -246,7 +247,9 @@ void assign_branches(mcubes_batch *B) {
                                            const std::pair<double, int> &b) {
         return a.first > b.first || (a.first == b.first && a.second < b.second);
     });
-    std::vector<double> load(B->streams, 0.0);
+    // never more branches than classes: a captured branch without work is not wanted
+    B->branches = std::max(1, std::min(B->streams, (int)B->plan.size()));
+    std::vector<double> load(B->branches, 0.0);
     for (const auto &ck : cost) {
         const int br = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         B->plan[ck.second].branch = br;
@@ -348,7 +351,7 @@ hipError_t launch_class(const mcubes_batch *B, const ClassPlan &c, bool frozen, 
 // s and joined back into s.
 hipError_t enqueue_vsample(const mcubes_batch *B, bool frozen, hipStream_t s) {
     hipError_t e = hipSuccess;
-    const int side = B->streams - 1;
+    const int side = B->branches - 1;
     if (side > 0) e = hipEventRecord(B->fork, s);
     for (int k = 0; k < side && e == hipSuccess; ++k) e = hipStreamWaitEvent(B->side[k], B->fork, 0);
     for (const ClassPlan &c : B->plan)

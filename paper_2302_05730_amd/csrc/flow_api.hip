@@ -1,0 +1,497 @@
+// Host side of the learned proposal (declared in include/mcubes.h): the flow
+// object (FP32 master parameters, BF16 copy, Adam moments, gradient,
+// training scratch), training, and the flow-mapped iteration.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "flow_impl.h"
+
+using namespace mcubes;
+
+struct mcubes_flow {
+    float *d_theta = nullptr, *d_m = nullptr, *d_v = nullptr, *d_grad = nullptr;
+    float *d_thetaT = nullptr;         // transposed weight matrices (backward pass)
+    void *d_frags = nullptr;           // BF16 weight fragments for the matrix-core path
+    float *d_fbias = nullptr;          // biases in accumulator order
+    bool packed = false;               // fragments up to date with d_theta
+    double *d_aux = nullptr;           // [0] sum of weights, [1] loss
+    double *d_part = nullptr;          // per-block partials of the flow-mapped iteration
+    float *d_scratch = nullptr;
+    int64_t scratch_n = 0;             // samples the scratch buffer holds
+    int step = 0;                      // Adam steps taken
+    int cus = 0;
+};
+
+namespace {
+
+constexpr int64_t kMaxSamples = (int64_t)1 << 31;
+constexpr int kVsBlocks = 2048;  // workgroups of the flow-mapped iteration (grid-stride)
+
+void release(mcubes_flow *F) {
+    if (!F) return;
+    hipFree(F->d_theta);
+    hipFree(F->d_m);
+    hipFree(F->d_v);
+    hipFree(F->d_grad);
+    hipFree(F->d_thetaT);
+    hipFree(F->d_frags);
+    hipFree(F->d_fbias);
+    hipFree(F->d_aux);
+    hipFree(F->d_part);
+    hipFree(F->d_scratch);
+    delete F;
+}
+
+int upload(mcubes_flow *F, const double *theta) {
+    std::vector<float> h(flow::PARAMS);
+    for (int i = 0; i < flow::PARAMS; ++i) {
+        if (!isfinite(theta[i])) return fail(MCUBES_E_ARG, "flow parameter %d is not finite", i);
+        h[i] = (float)theta[i];
+    }
+    hipError_t e = hipMemcpy(F->d_theta, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(F->d_m, 0, h.size() * sizeof(float));
+    if (e == hipSuccess) e = hipMemset(F->d_v, 0, h.size() * sizeof(float));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "flow parameter upload");
+    F->step = 0;
+    F->packed = false;
+    return MCUBES_OK;
+}
+
+// BF16 fragments of the current parameters (repacked after any change).
+hipError_t ensure_packed(mcubes_flow *F, hipStream_t s) {
+    if (F->packed) return hipSuccess;
+    const hipError_t e = launch_flow_pack_bf16(F->d_theta, F->d_frags, F->d_fbias, s);
+    if (e == hipSuccess) F->packed = true;
+    return e;
+}
+
+int check_n(int64_t n) {
+    if (n < 0 || n > kMaxSamples) return fail(MCUBES_E_ARG, "n must be in [0, 2^31]");
+    return MCUBES_OK;
+}
+
+int ensure_scratch(mcubes_flow *F, int64_t n) {
+    if (n <= F->scratch_n) return MCUBES_OK;
+    hipFree(F->d_scratch);
+    F->d_scratch = nullptr;
+    F->scratch_n = 0;
+    const size_t bytes = (size_t)flow_scratch_floats(n) * sizeof(float);
+    const hipError_t e = hipMalloc((void **)&F->d_scratch, bytes);
+    if (e != hipSuccess) return fail(MCUBES_E_ALLOC, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    F->scratch_n = n;
+    return MCUBES_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mcubes_flow_create(const double *theta, mcubes_flow **out) {
+    if (!theta || !out) return fail(MCUBES_E_ARG, "NULL argument");
+    for (int i = 0; i < flow::PARAMS; ++i)
+        if (!isfinite(theta[i])) return fail(MCUBES_E_ARG, "flow parameter %d is not finite", i);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    mcubes_flow *F = new (std::nothrow) mcubes_flow();
+    if (!F) return fail(MCUBES_E_ALLOC, "out of host memory");
+    e = hipDeviceGetAttribute(&F->cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const size_t pb = (size_t)flow::PARAMS * sizeof(float);
+    if (e == hipSuccess) e = hipMalloc((void **)&F->d_theta, pb);
+    if (e == hipSuccess) e = hipMalloc((void **)&F->d_m, pb);
+    if (e == hipSuccess) e = hipMalloc((void **)&F->d_v, pb);
+    if (e == hipSuccess) e = hipMalloc((void **)&F->d_grad, pb);
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&F->d_thetaT, (size_t)flow_transposed_floats() * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&F->d_frags, (size_t)flow_bf16_frag_bytes());
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&F->d_fbias, (size_t)flow_bf16_bias_floats() * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void **)&F->d_aux, 2 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&F->d_part, 2 * kVsBlocks * sizeof(double));
+    if (e != hipSuccess) {
+        release(F);
+        return fail(MCUBES_E_ALLOC, "flow allocation: %s", hipGetErrorString(e));
+    }
+    const int rc = upload(F, theta);
+    if (rc != MCUBES_OK) {
+        release(F);
+        return rc;
+    }
+    *out = F;
+    return MCUBES_OK;
+}
+
+void mcubes_flow_destroy(mcubes_flow *F) { release(F); }
+
+int mcubes_flow_get_params(const mcubes_flow *F, double *theta) {
+    if (!F || !theta) return fail(MCUBES_E_ARG, "NULL argument");
+    std::vector<float> h(flow::PARAMS);
+    const hipError_t e =
+        hipMemcpy(h.data(), F->d_theta, h.size() * sizeof(float), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "flow parameter download");
+    for (int i = 0; i < flow::PARAMS; ++i) theta[i] = (double)h[i];
+    return MCUBES_OK;
+}
+
+int mcubes_flow_set_params(mcubes_flow *F, const double *theta) {
+    if (!F || !theta) return fail(MCUBES_E_ARG, "NULL argument");
+    return upload(F, theta);
+}
+
+int mcubes_flow_density(mcubes_flow *F, int precision, const double *d_x, int64_t n, double *d_z,
+                        double *d_logq, void *stream) {
+    if (!F || (n > 0 && (!d_x || !d_z || !d_logq))) return fail(MCUBES_E_ARG, "NULL argument");
+    int rc = check_n(n);
+    if (rc != MCUBES_OK) return rc;
+    if (precision != MCUBES_FP32)
+        return fail(MCUBES_E_ARG, "the density direction is available in MCUBES_FP32 only");
+    const hipError_t e = launch_flow_density(F->d_theta, d_x, n, d_z, d_logq, as_stream(stream));
+    return e == hipSuccess ? MCUBES_OK : hip_fail(e, "flow density launch");
+}
+
+int mcubes_flow_sample(mcubes_flow *F, int precision, const double *d_z, int64_t n, double *d_x,
+                       double *d_logq, void *stream) {
+    if (!F || (n > 0 && (!d_z || !d_x || !d_logq))) return fail(MCUBES_E_ARG, "NULL argument");
+    int rc = check_n(n);
+    if (rc != MCUBES_OK) return rc;
+    if (precision != MCUBES_FP32 && precision != MCUBES_BF16)
+        return fail(MCUBES_E_ARG, "precision must be MCUBES_FP32 or MCUBES_BF16");
+    hipStream_t s = as_stream(stream);
+    hipError_t e;
+    if (precision == MCUBES_BF16) {
+        e = ensure_packed(F, s);
+        if (e == hipSuccess) e = launch_flow_sample_bf16(F->d_frags, F->d_fbias, d_z, n, d_x, d_logq, s);
+    } else {
+        e = launch_flow_sample(F->d_theta, d_z, n, d_x, d_logq, s);
+    }
+    return e == hipSuccess ? MCUBES_OK : hip_fail(e, "flow sample launch");
+}
+
+int mcubes_flow_loss_grad(mcubes_flow *F, const double *d_x, const double *d_w, int64_t n,
+                          double *d_grad, double *d_loss, void *stream) {
+    if (!F || !d_x || !d_w || !d_loss) return fail(MCUBES_E_ARG, "NULL argument");
+    if (n < 1 || n > kMaxSamples) return fail(MCUBES_E_ARG, "n must be in [1, 2^31]");
+    int rc = ensure_scratch(F, n);
+    if (rc != MCUBES_OK) return rc;
+    hipStream_t s = as_stream(stream);
+    hipError_t e = launch_flow_train(F->d_theta, F->d_thetaT, d_x, d_w, n, F->d_aux, F->d_scratch, F->d_grad,
+                                     d_loss, s);
+    if (e == hipSuccess && d_grad) {
+        // widen the kept FP32 gradient for the caller
+        std::vector<float> h(flow::PARAMS);
+        e = hipMemcpyAsync(h.data(), F->d_grad, h.size() * sizeof(float), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e == hipSuccess) {
+            std::vector<double> g(h.begin(), h.end());
+            e = hipMemcpyAsync(d_grad, g.data(), g.size() * sizeof(double), hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+        }
+    }
+    return e == hipSuccess ? MCUBES_OK : hip_fail(e, "flow gradient");
+}
+
+int mcubes_flow_adam_step(mcubes_flow *F, double lr, double beta1, double beta2, double eps,
+                          void *stream) {
+    if (!F) return fail(MCUBES_E_ARG, "NULL argument");
+    if (!(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) ||
+        !(eps > 0.0))
+        return fail(MCUBES_E_ARG, "Adam needs lr > 0, 0 <= beta < 1, eps > 0");
+    F->step += 1;
+    F->packed = false;
+    const double c1 = 1.0 - pow(beta1, (double)F->step), c2 = 1.0 - pow(beta2, (double)F->step);
+    const hipError_t e = launch_flow_adam(F->d_theta, F->d_m, F->d_v, F->d_grad, (float)lr,
+                                          (float)beta1, (float)beta2, (float)eps, (float)c1,
+                                          (float)c2, as_stream(stream));
+    return e == hipSuccess ? MCUBES_OK : hip_fail(e, "Adam launch");
+}
+
+int mcubes_flow_train(mcubes_flow *F, const double *d_x, const double *d_w, int64_t n, int epochs,
+                      int64_t batch, double lr, double *losses, void *stream) {
+    if (!F || !d_x || !d_w) return fail(MCUBES_E_ARG, "NULL argument");
+    if (n < 1 || n > kMaxSamples) return fail(MCUBES_E_ARG, "n must be in [1, 2^31]");
+    if (epochs < 0 || batch < 1) return fail(MCUBES_E_ARG, "epochs >= 0 and batch >= 1 required");
+    if (batch > n) batch = n;
+    int rc = ensure_scratch(F, batch);
+    if (rc != MCUBES_OK) return rc;
+    hipStream_t s = as_stream(stream);
+    double *d_loss = F->d_aux + 1;
+    F->packed = false;
+    for (int ep = 0; ep < epochs; ++ep) {
+        hipError_t e = hipMemsetAsync(d_loss, 0, sizeof(double), s);
+        int nbatch = 0;
+        for (int64_t b0 = 0; b0 < n && e == hipSuccess; b0 += batch) {
+            const int64_t nb = n - b0 < batch ? n - b0 : batch;
+            e = launch_flow_train(F->d_theta, F->d_thetaT, d_x + b0 * flow::D, d_w + b0, nb, F->d_aux,
+                                  F->d_scratch, F->d_grad, d_loss, s);
+            if (e == hipSuccess) {
+                F->step += 1;
+                const double c1 = 1.0 - pow(0.9, (double)F->step);
+                const double c2 = 1.0 - pow(0.999, (double)F->step);
+                e = launch_flow_adam(F->d_theta, F->d_m, F->d_v, F->d_grad, (float)lr, 0.9f,
+                                     0.999f, 1e-8f, (float)c1, (float)c2, s);
+            }
+            ++nbatch;
+        }
+        if (e == hipSuccess && losses) {
+            double h = 0.0;
+            e = hipMemcpyAsync(&h, d_loss, sizeof(double), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            losses[ep] = h / (double)nbatch;
+        }
+        if (e != hipSuccess) return hip_fail(e, "flow training");
+    }
+    return MCUBES_OK;
+}
+
+int mcubes_vsample_dump(const mcubes_plan *P, uint32_t iteration, const double *d_grid,
+                        int64_t w_begin, int64_t count, double *d_x, double *d_w, void *stream) {
+    if (!P || !d_grid || (count > 0 && (!d_x || !d_w))) return fail(MCUBES_E_ARG, "NULL argument");
+    if (w_begin < 0 || count < 0 || w_begin + count > P->m)
+        return fail(MCUBES_E_ARG, "work items [%lld, %lld) outside [0, %lld)", (long long)w_begin,
+                    (long long)(w_begin + count), (long long)P->m);
+    VsArgs A = P->args;
+    A.iteration = iteration;
+    const hipError_t e = launch_vsample_dump(P->family, P->dim, A, d_grid, (uint32_t)w_begin,
+                                             (uint32_t)count, d_x, d_w, as_stream(stream));
+    return e == hipSuccess ? MCUBES_OK : hip_fail(e, "sample export launch");
+}
+
+int mcubes_flow_draw(mcubes_flow *F, const mcubes_plan *P, uint32_t iteration, int64_t n,
+                     double *d_x, double *d_w, void *stream) {
+    if (!F || !P || (n > 0 && (!d_x || !d_w))) return fail(MCUBES_E_ARG, "NULL argument");
+    if (P->dim != flow::D) return fail(MCUBES_E_ARG, "the flow needs a plan of dim %d", flow::D);
+    if (n < 0 || n > 0xFFFFFFFFll) return fail(MCUBES_E_ARG, "n must be in [0, 2^32)");
+    VsArgs A = P->args;
+    A.iteration = iteration;
+    const uint32_t stream_word = A.stream_id | 0xC0000000u;
+    const hipError_t e = launch_flow_draw(P->family, F->d_theta, A, stream_word, (uint32_t)n, d_x,
+                                          d_w, as_stream(stream));
+    return e == hipSuccess ? MCUBES_OK : hip_fail(e, "flow draw launch");
+}
+
+int mcubes_flow_vsample(mcubes_flow *F, int precision, const mcubes_plan *P, uint32_t iteration,
+                        double *d_est, void *stream) {
+    if (!F || !P || !d_est) return fail(MCUBES_E_ARG, "NULL argument");
+    if (P->dim != flow::D) return fail(MCUBES_E_ARG, "the flow needs a plan of dim %d", flow::D);
+    if (precision != MCUBES_FP32 && precision != MCUBES_BF16)
+        return fail(MCUBES_E_ARG, "precision must be MCUBES_FP32 or MCUBES_BF16");
+    if (precision == MCUBES_BF16 && 64 % P->p != 0)
+        return fail(MCUBES_E_ARG, "the BF16 flow iteration needs p dividing 64, got %lld",
+                    (long long)P->p);
+    VsArgs A = P->args;
+    A.iteration = iteration;
+    const uint32_t stream_word = A.stream_id | 0x80000000u;
+    hipStream_t s = as_stream(stream);
+    hipError_t e;
+    int blocks;
+    if (precision == MCUBES_BF16) {
+        // 256 samples per workgroup pass (four waves of 64)
+        const int64_t groups = (P->m * P->p + 255) / 256;
+        blocks = groups < kVsBlocks ? (int)groups : kVsBlocks;
+        e = ensure_packed(F, s);
+        if (e == hipSuccess)
+            e = launch_flow_vsample_bf16(P->family, F->d_frags, F->d_fbias, A, stream_word,
+                                         F->d_part, blocks, s);
+    } else {
+        blocks = (int)((P->m + 255) / 256);
+        if (blocks > kVsBlocks) blocks = kVsBlocks;
+        e = launch_flow_vsample(P->family, F->d_theta, A, stream_word, F->d_part, blocks, s);
+    }
+    const double n = (double)P->m * (double)P->p;
+    const double denom = (double)P->p * (double)P->m * (double)P->m;
+    if (e == hipSuccess) e = launch_reduce(F->d_part, blocks, n, denom, d_est, s);
+    return e == hipSuccess ? MCUBES_OK : hip_fail(e, "flow V-Sample launch");
+}
+
+void mcubes_default_flow_options(mcubes_flow_options *o) {
+    if (!o) return;
+    memset(o, 0, sizeof *o);
+    o->warmup_iters = 8;
+    o->precision = MCUBES_BF16;
+    o->train_items = (int64_t)1 << 18;
+    o->epochs = 6;
+    o->rounds = 2;
+    o->round_samples = (int64_t)1 << 19;
+    o->round_epochs = 2;
+    o->batch = 16384;
+    o->lr = 1e-3;
+    o->round_lr = 5e-4;
+}
+
+int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int64_t ncall,
+                          int itmax, double rel_tol, uint64_t seed, const mcubes_options *opt_in,
+                          const mcubes_flow_options *fopt_in, mcubes_result *out,
+                          mcubes_flow_report *rep) {
+    if (!F || !out) return fail(MCUBES_E_ARG, "NULL argument");
+    if (itmax < 1 || itmax > MCUBES_MAX_ITERATIONS)
+        return fail(MCUBES_E_ARG, "itmax must be in [1, %d]", MCUBES_MAX_ITERATIONS);
+    if (!(rel_tol >= 0.0) || !isfinite(rel_tol)) return fail(MCUBES_E_ARG, "rel_tol must be finite and >= 0");
+    mcubes_flow_options fo;
+    mcubes_default_flow_options(&fo);
+    if (fopt_in) fo = *fopt_in;
+    if (fo.warmup_iters < 1 || fo.warmup_iters + itmax > MCUBES_MAX_ITERATIONS || fo.epochs < 0 ||
+        fo.rounds < 0 || fo.round_epochs < 0 || fo.batch < 1 || fo.train_items < 1 ||
+        fo.round_samples < 1 || fo.round_samples > ((int64_t)1 << 31) || !(fo.lr > 0.0) ||
+        !(fo.round_lr > 0.0) || (fo.precision != MCUBES_FP32 && fo.precision != MCUBES_BF16))
+        return fail(MCUBES_E_ARG, "invalid flow options");
+    mcubes_options opt;
+    mcubes_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    opt.precision = MCUBES_FP64;
+    mcubes_plan *P = nullptr;
+    int rc = mcubes_plan_create(family, params, flow::D, ncall, seed, &opt, &P);
+    if (rc != MCUBES_OK) return rc;
+    hipStream_t s = as_stream(opt.stream);
+    const int64_t ng = (int64_t)P->dim * (P->nb + 1), nbn = (int64_t)P->dim * P->nb;
+    const int64_t items = fo.train_items < P->m ? fo.train_items : P->m;
+    const int64_t rows = items * P->p;
+    const int64_t drows = rows > fo.round_samples ? rows : fo.round_samples;
+    const int64_t total = 2 * ng + nbn + 2 * (int64_t)P->blocks + 2 + 2 * MCUBES_STATE_LEN +
+                          7 * drows;
+    double *buf = nullptr;
+    hipEvent_t ev[4] = {};
+    double head[MCUBES_STATE_HEADER];
+    mcubes_flow_report R;
+    memset(&R, 0, sizeof R);
+    int done = 0, used = 1, plain_t = fo.warmup_iters;
+    float ms = 0.0f;
+    hipError_t e = hipMalloc(&buf, (size_t)total * sizeof(double));
+    if (e != hipSuccess) {
+        mcubes_plan_destroy(P);
+        return fail(MCUBES_E_ALLOC, "hipMalloc: %s", hipGetErrorString(e));
+    }
+    double *grid[2] = {buf, buf + ng};
+    double *bins = buf + 2 * ng;
+    double *partials = bins + nbn;
+    double *est = partials + 2 * (int64_t)P->blocks;
+    double *st_plain = est + 2, *st_flow = st_plain + MCUBES_STATE_LEN;
+    double *dx = st_flow + MCUBES_STATE_LEN, *dw = dx + 6 * drows;
+    double *state = st_flow;
+
+#define FI_CHECK(expr, what)                 \
+    do {                                     \
+        e = (expr);                          \
+        if (e != hipSuccess) {               \
+            rc = hip_fail(e, what);          \
+            goto cleanup;                    \
+        }                                    \
+    } while (0)
+#define FI_CALL(expr)                        \
+    do {                                     \
+        rc = (expr);                         \
+        if (rc != MCUBES_OK) goto cleanup;   \
+    } while (0)
+
+    for (auto &x : ev) FI_CHECK(hipEventCreate(&x), "hipEventCreate");
+    FI_CHECK(hipEventRecord(ev[0], s), "hipEventRecord");
+    // 1. plain warm-up iterations
+    FI_CHECK(launch_init_grid(grid[0], P->dim, P->nb, s), "init_grid launch");
+    FI_CHECK(launch_fill(st_plain, 2 * MCUBES_STATE_LEN, 0.0, s), "fill launch");
+    for (int t = 0; t < fo.warmup_iters; ++t)
+        FI_CALL(mcubes_iteration(P, (uint32_t)t, grid[t & 1], grid[(t + 1) & 1], bins, partials, est,
+                                 st_plain, 0.0, opt.stream));
+    FI_CHECK(hipMemcpyAsync(&R.last_plain_var, est + 1, sizeof(double), hipMemcpyDeviceToHost, s),
+             "hipMemcpyAsync");
+    FI_CHECK(hipMemcpyAsync(head, st_plain, sizeof head, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    FI_CHECK(hipEventRecord(ev[1], s), "hipEventRecord");
+    // 2-3. training on the last warm-up iteration's samples, then on the flow's own
+    FI_CALL(mcubes_vsample_dump(P, (uint32_t)(fo.warmup_iters - 1), grid[(fo.warmup_iters - 1) & 1],
+                                0, items, dx, dw, opt.stream));
+    {
+        double losses[1024];
+        const int ep = fo.epochs < 1024 ? fo.epochs : 1024;
+        if (ep > 0) {
+            FI_CALL(mcubes_flow_train(F, dx, dw, rows, ep, fo.batch, fo.lr, losses, opt.stream));
+            R.final_loss = losses[ep - 1];
+        }
+        const int rep_ep = fo.round_epochs < 1024 ? fo.round_epochs : 1024;
+        for (int r = 0; r < fo.rounds; ++r) {
+            FI_CALL(mcubes_flow_draw(F, P, (uint32_t)(1000 + r), fo.round_samples, dx, dw, opt.stream));
+            if (rep_ep > 0) {
+                FI_CALL(mcubes_flow_train(F, dx, dw, fo.round_samples, rep_ep, fo.batch, fo.round_lr,
+                                          losses, opt.stream));
+                R.final_loss = losses[rep_ep - 1];
+            }
+        }
+    }
+    FI_CHECK(hipEventRecord(ev[2], s), "hipEventRecord");
+    R.plain_estimate = head[0];
+    R.plain_error = head[1];
+    R.plain_chi2_dof = head[2];
+    // 4. flow-mapped iterations, judged against the plain method
+    for (int t = 0; t < itmax; ++t) {
+        const uint32_t it = (uint32_t)(fo.warmup_iters + t);
+        if (used) {
+            FI_CALL(mcubes_flow_vsample(F, fo.precision, P, it, est, opt.stream));
+            FI_CALL(mcubes_combine(P, (uint32_t)t, est, st_flow, rel_tol, opt.stream));
+        } else {
+            // plain iterations continue from the warm-up's grid and state
+            FI_CALL(mcubes_iteration(P, (uint32_t)plain_t, grid[plain_t & 1],
+                                     grid[(plain_t + 1) & 1], bins, partials, est, st_plain,
+                                     rel_tol, opt.stream));
+            ++plain_t;
+        }
+        FI_CHECK(hipMemcpyAsync(head, used ? st_flow : st_plain, sizeof head,
+                                hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+        double ev_var = 0.0;
+        FI_CHECK(hipMemcpyAsync(&ev_var, est + 1, sizeof ev_var, hipMemcpyDeviceToHost, s),
+                 "hipMemcpyAsync");
+        FI_CHECK(hipStreamSynchronize(s), "hipStreamSynchronize");
+        done = t + 1;
+        if (used && t == 0) {
+            R.first_flow_var = ev_var;
+            if (!(ev_var < R.last_plain_var)) {
+                used = 0;  // the flow lost: continue with plain iterations
+                state = st_plain;
+                continue;
+            }
+        }
+        if (head[6] != 0.0) {
+            rc = fail(MCUBES_E_NONFINITE, "iteration %d produced a non-finite estimate", t);
+            goto cleanup;
+        }
+        if (head[5] != 0.0) break;
+    }
+    FI_CHECK(hipEventRecord(ev[3], s), "hipEventRecord");
+    FI_CHECK(hipEventSynchronize(ev[3]), "hipEventSynchronize");
+    FI_CHECK(hipEventElapsedTime(&ms, ev[0], ev[1]), "hipEventElapsedTime");
+    R.warmup_ms = ms;
+    FI_CHECK(hipEventElapsedTime(&ms, ev[1], ev[2]), "hipEventElapsedTime");
+    R.train_ms = ms;
+    FI_CHECK(hipEventElapsedTime(&ms, ev[2], ev[3]), "hipEventElapsedTime");
+    R.flow_ms = ms;
+    FI_CHECK(hipEventElapsedTime(&ms, ev[0], ev[3]), "hipEventElapsedTime");
+    R.total_ms = ms;
+    FI_CHECK(hipMemcpy(head, state, sizeof head, hipMemcpyDeviceToHost), "hipMemcpy");
+    R.flow_iterations = used ? done : 1;
+    R.used_flow = used;
+    out->estimate = head[0];
+    out->error = head[1];
+    out->chi2_dof = head[2];
+    out->dof = (int32_t)head[3];
+    out->iterations = (int32_t)head[4];
+    out->converged = head[5] != 0.0;
+    out->cube_side = P->g;
+    out->ncubes = P->m;
+    out->samples_per_cube = P->p;
+    out->samples_per_iter = P->n;
+    out->kernel_ms = R.flow_ms;
+    rc = out->converged ? MCUBES_OK : MCUBES_NOT_CONVERGED;
+    out->status = rc;
+    if (rep) *rep = R;
+
+cleanup:
+#undef FI_CHECK
+#undef FI_CALL
+    for (auto &x : ev)
+        if (x) hipEventDestroy(x);
+    hipFree(buf);
+    mcubes_plan_destroy(P);
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,356 @@
+// Flow sampling on the BF16 matrix cores (gfx950 v_mfma_f32_32x32x16_bf16,
+// FP32 accumulation): the proposal's hot loop.
+//
+// A wave carries 64 samples, one per lane for the per-sample work (Philox,
+// spline inversion, integrand), and runs each conditioner as three chained
+// matrix products in transposed form, out^T = W^T in^T: features are the
+// matrix rows (M), the 64 samples two blocks of 32 columns (N).  With that
+// orientation the accumulator of one product (lane l holds column l % 32 and
+// rows 8 (r/4) + 4 (l/32) + r%4 of a 32-row tile, r = 0..15) is, after bias,
+// ReLU and rounding to BF16, already the B operand of the next product (lane
+// l holds K values 8 (l/32) .. +7 of column l % 32) provided the K order of a
+// step is the one the accumulator registers hold: the weight fragments are
+// packed with that order, so activations never leave the registers.  The
+// one-blob inputs of the first product are computed directly in operand
+// order.  At the end, one v_permlane32_swap per accumulator register gives
+// every lane all 99 outputs of its own sample.
+//
+// Rounding: weights and the inputs of every product are BF16 (round to
+// nearest even), biases and accumulation FP32, the splines FP32, the
+// integrand and weights FP64.
+#include "flow_impl.h"
+#include "vsample_impl.h"
+
+namespace mcubes {
+
+namespace {
+
+using namespace flow;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// fragments per layer: first product 2 row tiles x 6 K steps, second 2 x 4,
+// third 4 x 4 (99 outputs padded to 128)
+constexpr int G1T = 2, G1K = 6, G2T = 2, G2K = 4, G3T = 4, G3K = 4;
+constexpr int OFF_G1 = 0, OFF_G2 = OFF_G1 + G1T * G1K, OFF_G3 = OFF_G2 + G2T * G2K;
+constexpr int FRAGS = OFF_G3 + G3T * G3K;  // 36
+// biases per layer in accumulator order: [tile][lane half][register]
+constexpr int BOFF_1 = 0, BOFF_2 = BOFF_1 + G1T * 32, BOFF_3 = BOFF_2 + G2T * 32;
+constexpr int BIAS = BOFF_3 + G3T * 32;  // 256
+
+// feature held by accumulator register r of lane half h in row tile t
+__host__ __device__ constexpr int acc_feature(int t, int r, int h) {
+    return 32 * t + 8 * (r / 4) + 4 * h + (r % 4);
+}
+
+__device__ __forceinline__ uint16_t bf16_bits(float f) {
+    uint32_t b = __float_as_uint(f);
+    b += 0x7fffu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+
+__device__ __forceinline__ bf16x8 pack8(const float v[8]) {
+    bf16x8 r;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) r[i] = __builtin_bit_cast(__bf16, bf16_bits(v[i]));
+    return r;
+}
+
+// One thread per (layer, fragment, lane): the 8 BF16 weights lane `lane`
+// feeds to the matrix core, and the biases in accumulator order.
+__global__ void pack_kernel(const float *__restrict__ theta, bf16x8 *__restrict__ frags,
+                            float *__restrict__ bias) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid < L * BIAS) {
+        const int l = gid / BIAS, q = gid % BIAS;
+        const float *P = theta + l * LP;
+        int off, n, t;
+        if (q < BOFF_2) {
+            off = OFF_B1; n = HID; t = q / 32;
+        } else if (q < BOFF_3) {
+            off = OFF_B2; n = HID; t = (q - BOFF_2) / 32;
+        } else {
+            off = OFF_B3; n = OUT; t = (q - BOFF_3) / 32;
+        }
+        const int w = q % 32, h = w / 16, r = w % 16;
+        const int f = acc_feature(t, r, h);
+        bias[gid] = f < n ? P[off + f] : 0.0f;
+    }
+    if (gid >= L * FRAGS * 64) return;
+    const int lane = gid % 64, fr = (gid / 64) % FRAGS, l = gid / (64 * FRAGS);
+    const float *P = theta + l * LP;
+    const int row = lane % 32, h = lane / 32;
+    float v[8];
+    if (fr < OFF_G2) {  // first product: natural K order over the 96 one-blob inputs
+        const int t = fr / G1K, ks = fr % G1K;
+        for (int e = 0; e < 8; ++e) v[e] = P[OFF_W1 + (16 * ks + 8 * h + e) * HID + 32 * t + row];
+    } else {  // second and third: K order of the previous accumulator registers
+        const bool third = fr >= OFF_G3;
+        const int q = fr - (third ? OFF_G3 : OFF_G2);
+        const int t = q / 4, ks = q % 4;
+        const int o = 32 * t + row;
+        for (int e = 0; e < 8; ++e) {
+            const int k = acc_feature(ks / 2, 8 * (ks % 2) + e, h);
+            v[e] = third ? (o < OUT ? P[OFF_W3 + k * OUT + o] : 0.0f) : P[OFF_W2 + k * HID + o];
+        }
+    }
+    frags[gid] = pack8(v);
+}
+
+// 64 samples through the inverse flow: lane s holds sample s in u[] and
+// returns log q.  All 64 lanes must be active.
+__device__ __forceinline__ float sample_wave(const bf16x8 *__restrict__ frags,
+                                             const float *__restrict__ bias, float u[D]) {
+    const int lane = threadIdx.x & 63, h = lane >> 5, col = lane & 31;
+    float lq = 0.0f;
+#pragma unroll 1
+    for (int l = L - 1; l >= 0; --l) {
+        const bf16x8 *F = frags + (size_t)l * FRAGS * 64 + lane;
+        const float *Bs = bias + l * BIAS + h * 16;
+        f32x16 out[2][G3T];  // [sample block][row tile]
+#pragma unroll
+        for (int sb = 0; sb < 2; ++sb) {
+            // conditioning inputs of this lane's column sample
+            float ua[NA];
+#pragma unroll
+            for (int a = 0; a < NA; ++a) ua[a] = __shfl(getu(u, a_idx(l, a)), 32 * sb + col);
+            // first product: one-blob inputs computed in operand order
+            f32x16 acc1[G1T];
+#pragma unroll
+            for (int t = 0; t < G1T; ++t) acc1[t] = f32x16{};
+#pragma unroll
+            for (int ks = 0; ks < G1K; ++ks) {
+                float e[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) e[i] = blob(ua[ks >> 1], 16 * (ks & 1) + 8 * h + i);
+                const bf16x8 bop = pack8(e);
+#pragma unroll
+                for (int t = 0; t < G1T; ++t)
+                    acc1[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F[(OFF_G1 + t * G1K + ks) * 64],
+                                                                      bop, acc1[t], 0, 0, 0);
+            }
+            // h1 = relu(acc + b1) as the next operand
+            bf16x8 h1[G2K];
+#pragma unroll
+            for (int ks = 0; ks < G2K; ++ks) {
+                float v[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int r = 8 * (ks % 2) + i;
+                    v[i] = fmaxf(acc1[ks / 2][r] + Bs[BOFF_1 + (ks / 2) * 32 + r], 0.0f);
+                }
+                h1[ks] = pack8(v);
+            }
+            f32x16 acc2[G2T];
+#pragma unroll
+            for (int t = 0; t < G2T; ++t) acc2[t] = f32x16{};
+#pragma unroll
+            for (int ks = 0; ks < G2K; ++ks)
+#pragma unroll
+                for (int t = 0; t < G2T; ++t)
+                    acc2[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F[(OFF_G2 + t * G2K + ks) * 64],
+                                                                      h1[ks], acc2[t], 0, 0, 0);
+            bf16x8 h2[G3K];
+#pragma unroll
+            for (int ks = 0; ks < G3K; ++ks) {
+                float v[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int r = 8 * (ks % 2) + i;
+                    v[i] = fmaxf(acc2[ks / 2][r] + Bs[BOFF_2 + (ks / 2) * 32 + r], 0.0f);
+                }
+                h2[ks] = pack8(v);
+            }
+#pragma unroll
+            for (int t = 0; t < G3T; ++t) out[sb][t] = f32x16{};
+#pragma unroll
+            for (int ks = 0; ks < G3K; ++ks)
+#pragma unroll
+                for (int t = 0; t < G3T; ++t)
+                    out[sb][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        F[(OFF_G3 + t * G3K + ks) * 64], h2[ks], out[sb][t], 0, 0, 0);
+        }
+        // hand every lane its own sample: lanes 32..63 of block 0 <-> lanes
+        // 0..31 of block 1; then lane s holds the features of lane half 0 in
+        // own[0] and of lane half 1 in own[1]
+        f32x16 own[2][G3T];
+#pragma unroll
+        for (int t = 0; t < G3T; ++t)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const auto sw = __builtin_amdgcn_permlane32_swap(
+                    __float_as_uint(out[0][t][r]), __float_as_uint(out[1][t][r]), false, false);
+                own[0][t][r] = __uint_as_float(sw[0]) + bias[l * BIAS + BOFF_3 + t * 32 + r];
+                own[1][t][r] = __uint_as_float(sw[1]) + bias[l * BIAS + BOFF_3 + t * 32 + 16 + r];
+            }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            float raw[RAW];
+#pragma unroll
+            for (int k = 0; k < RAW; ++k) {
+                const int f = b * RAW + k, t = f / 32, w = f % 32;
+                const int hh = (w / 4) % 2, r = 4 * (w / 8) + w % 4;
+                raw[k] = own[hh][t][r];
+            }
+            Spline s;
+            spline_setup(raw, s);
+            const int j = b_idx(l, b);
+            float v, pdf;
+            spline_inverse(s, getu(u, j), v, pdf);
+            setu(u, j, v);
+            lq += logf(pdf);
+        }
+    }
+    return lq;
+}
+
+// z (n x 6) -> x, log q, 64 samples per wave; lanes past n work on a copy of
+// the last sample and store nothing.
+__global__ __launch_bounds__(256) void sample_bf16_kernel(const bf16x8 *__restrict__ frags,
+                                                          const float *__restrict__ bias,
+                                                          const double *__restrict__ z, int64_t n,
+                                                          double *__restrict__ x,
+                                                          double *__restrict__ logq) {
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int64_t wid = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    for (int64_t base = wid * 64; base < n; base += waves * 64) {
+        const int64_t s = base + lane < n ? base + lane : n - 1;
+        float u[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) u[j] = (float)z[s * D + j];
+        const float lq = sample_wave(frags, bias, u);
+        if (base + lane < n) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) x[s * D + j] = (double)u[j];
+            logq[s] = (double)lq;
+        }
+    }
+}
+
+// The flow-mapped iteration on the matrix cores: 64 consecutive samples per
+// wave, sample q = cube q / p, index q % p (p divides 64, so a cube's
+// samples share a wave); per-cube statistics by butterfly sums over the p
+// lanes of a cube.
+template <int F>
+__global__ __launch_bounds__(256) void flow_vsample_bf16_kernel(const bf16x8 *__restrict__ frags,
+                                                                const float *__restrict__ bias,
+                                                                const VsArgs A,
+                                                                uint32_t stream_word,
+                                                                double *__restrict__ partials) {
+    constexpr int NBLK = (D + 3) / 4;
+    const uint64_t N = (uint64_t)A.m * A.p;
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    const uint64_t wid = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int p = (int)A.p;
+    double tS = 0.0, tV = 0.0;
+    for (uint64_t base = wid * 64; base < N; base += waves * 64) {
+        const uint64_t q = base + lane;
+        const bool live = q < N;
+        const uint32_t c = live ? (uint32_t)(q / p) : 0u;
+        const uint32_t k = live ? (uint32_t)(q % p) : 0u;
+        float u[D];
+        uint32_t rest = c;
+#pragma unroll
+        for (int b = 0; b < NBLK; ++b) {
+            uint32_t r[4];
+            philox10(c, stream_word, k * NBLK + b, A.iteration, A.key0, A.key1, r);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int j = 4 * b + i;
+                if (j < D) {
+                    const double dig = (double)(rest % A.g);
+                    rest /= A.g;
+                    const double uu = __fma_rn((double)r[i], 0x1p-32, 0x1p-33);
+                    u[j] = (float)((dig + uu) / (double)A.g);
+                }
+            }
+        }
+        const float lq = sample_wave(frags, bias, u);
+        Acc acc = Family<F, D>::begin(A.phase);
+#pragma unroll
+        for (int j = 0; j < D; ++j) Family<F, D>::axis(acc, A.ca[j], A.cu[j], (double)u[j]);
+        const double w = Family<F, D>::end(acc, A) / exp((double)lq);
+        // per-cube sums over the p lanes of the cube, shifted by its first sample
+        const int first = lane - (lane % p);
+        const double w0 = __shfl(w, first);
+        const double dlt = w - w0;
+        double S = w, D1 = dlt, D2 = dlt * dlt;
+        for (int off = 1; off < p; off <<= 1) {
+            S += __shfl_xor(S, off);
+            D1 += __shfl_xor(D1, off);
+            D2 += __shfl_xor(D2, off);
+        }
+        if (live && lane == first) {
+            tS += S;
+            tV += (D2 - D1 * D1 * A.inv_p) * A.inv_pm1;
+        }
+    }
+    __shared__ double red[2][4];
+    tS = wave_sum(tS);
+    tV = wave_sum(tV);
+    if (lane == 0) {
+        red[0][threadIdx.x >> 6] = tS;
+        red[1][threadIdx.x >> 6] = tV;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0, v = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            s += red[0][w];
+            v += red[1][w];
+        }
+        partials[2 * blockIdx.x] = s;
+        partials[2 * blockIdx.x + 1] = v;
+    }
+}
+
+template <int F>
+hipError_t launch_bf16_f(const void *frags, const float *bias, const VsArgs &A,
+                         uint32_t stream_word, double *partials, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL((flow_vsample_bf16_kernel<F>), dim3(blocks), dim3(256), 0, s,
+                       (const bf16x8 *)frags, bias, A, stream_word, partials);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t flow_bf16_frag_bytes() { return (int64_t)L * FRAGS * 64 * sizeof(bf16x8); }
+int64_t flow_bf16_bias_floats() { return (int64_t)L * BIAS; }
+
+hipError_t launch_flow_pack_bf16(const float *theta, void *frags, float *bias, hipStream_t s) {
+    const int n = L * FRAGS * 64;
+    hipLaunchKernelGGL(pack_kernel, dim3((n + 255) / 256), dim3(256), 0, s, theta,
+                       (bf16x8 *)frags, bias);
+    return hipGetLastError();
+}
+
+hipError_t launch_flow_sample_bf16(const void *frags, const float *bias, const double *z,
+                                   int64_t n, double *x, double *logq, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(sample_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                       (const bf16x8 *)frags, bias, z, n, x, logq);
+    return hipGetLastError();
+}
+
+hipError_t launch_flow_vsample_bf16(int family, const void *frags, const float *bias,
+                                    const VsArgs &A, uint32_t stream_word, double *partials,
+                                    int blocks, hipStream_t s) {
+    switch (family) {
+    case MCUBES_OSCILLATORY: return launch_bf16_f<MCUBES_OSCILLATORY>(frags, bias, A, stream_word, partials, blocks, s);
+    case MCUBES_PRODUCT_PEAK: return launch_bf16_f<MCUBES_PRODUCT_PEAK>(frags, bias, A, stream_word, partials, blocks, s);
+    case MCUBES_CORNER_PEAK: return launch_bf16_f<MCUBES_CORNER_PEAK>(frags, bias, A, stream_word, partials, blocks, s);
+    case MCUBES_GAUSSIAN: return launch_bf16_f<MCUBES_GAUSSIAN>(frags, bias, A, stream_word, partials, blocks, s);
+    case MCUBES_C0: return launch_bf16_f<MCUBES_C0>(frags, bias, A, stream_word, partials, blocks, s);
+    case MCUBES_DISCONTINUOUS: return launch_bf16_f<MCUBES_DISCONTINUOUS>(frags, bias, A, stream_word, partials, blocks, s);
+    case MCUBES_ADDITION: return launch_bf16_f<MCUBES_ADDITION>(frags, bias, A, stream_word, partials, blocks, s);
+    case MCUBES_MIXTURE: return launch_bf16_f<MCUBES_MIXTURE>(frags, bias, A, stream_word, partials, blocks, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mcubes

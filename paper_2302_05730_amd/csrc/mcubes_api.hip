@@ -11,18 +11,6 @@
 
 using namespace mcubes;
 
-struct mcubes_plan {
-    int family, dim, nb, precision;
-    int block, blocks;
-    size_t lds;
-    int adapt_iters, skip;
-    double alpha;
-    int64_t g, m, p, n;
-    VsArgs args;
-    VsLaunchFn launch[2];  // [0] without bin sums, [1] with
-    const void *func;
-};
-
 namespace {
 thread_local std::string g_error;
 }  // namespace
@@ -52,6 +40,7 @@ const VsKernel *family_table(int family) {
     case MCUBES_C0: return kVsC0();
     case MCUBES_DISCONTINUOUS: return kVsDiscontinuous();
     case MCUBES_ADDITION: return kVsAddition();
+    case MCUBES_MIXTURE: return kVsMixture();
     default: return nullptr;
     }
 }
@@ -103,6 +92,12 @@ int validate_params(int family, const double *params, int dim) {
     if (family == MCUBES_PRODUCT_PEAK)
         for (int i = 0; i < dim; ++i)
             if (params[i] == 0.0) return fail(MCUBES_E_INTEGRAND, "product peak needs a_%d != 0", i);
+    if (family == MCUBES_MIXTURE) {
+        if (dim < 2) return fail(MCUBES_E_INTEGRAND, "the mixture needs dim >= 2");
+        if (!(params[0] > 0.0)) return fail(MCUBES_E_INTEGRAND, "mixture: a_0 = s must be > 0");
+        if (!(params[1] >= 0.0 && params[1] < 1.0))
+            return fail(MCUBES_E_INTEGRAND, "mixture: a_1 = r must be in [0, 1)");
+    }
     return MCUBES_OK;
 }
 
@@ -112,6 +107,19 @@ void fold_params(int family, const double *params, int dim, VsArgs &A) {
     A.phase = 0.0;
     if (family == MCUBES_ADDITION) return;
     const double *a = params, *u = params + dim;
+    if (family == MCUBES_MIXTURE) {
+        const double sg = a[0], r = a[1];
+        const double lam = 1.0 - r + (double)dim * r;
+        A.mix_c1 = r / lam;
+        A.mix_c2 = 1.0 / (2.0 * sg * sg * (1.0 - r));
+        A.mix_norm = 0.5 / (pow(2.0 * M_PI, 0.5 * (double)dim) * pow(sg, (double)dim) *
+                            pow(1.0 - r, 0.5 * (double)(dim - 1)) * sqrt(lam));
+        for (int i = 0; i < dim; ++i) {
+            A.ca[i] = u[0];
+            A.cu[i] = u[1];
+        }
+        return;
+    }
     for (int i = 0; i < dim; ++i) {
         switch (family) {
         case MCUBES_PRODUCT_PEAK: A.ca[i] = 1.0 / (a[i] * a[i]); break;

@@ -10,7 +10,7 @@ namespace mcubes {
 
 constexpr int kMaxDim = MCUBES_MAX_DIM;
 constexpr int kMaxBins = MCUBES_MAX_BINS;
-constexpr int kFamilies = 7;
+constexpr int kFamilies = 8;
 constexpr int kMaxBlock = 1024;
 
 // Uniform arguments of one V-Sample launch (kernel-argument segment, read
@@ -21,10 +21,12 @@ constexpr int kMaxBlock = 1024;
 //   Gaussian       ca = a a,      cu = u
 //   C0             ca = a,        cu = u
 //   discontinuous  ca = a,        cu = u
+//   mixture        ca = m_1,      cu = m_2 (every axis), mix_* below
 struct VsArgs {
     double ca[kMaxDim];
     double cu[kMaxDim];
     double phase;
+    double mix_c1, mix_c2, mix_norm;  // mixture: r/(1-r+dr), 1/(2 s^2 (1-r)), normalisation / 2
     double zscale;      // fl(nb/g) * 2^-32: bin coordinate per unit of (c_j 2^32 + r + 1/2)
     double nbd;         // fl(nb^d) by repeated multiplication
     double inv_p;       // fl(1/p)
@@ -84,6 +86,7 @@ const VsKernel *kVsGaussian();
 const VsKernel *kVsC0();
 const VsKernel *kVsDiscontinuous();
 const VsKernel *kVsAddition();
+const VsKernel *kVsMixture();
 
 // Small kernels (support.hip).
 hipError_t launch_fill(double *d, int64_t n, double value, hipStream_t stream);
@@ -128,9 +131,56 @@ void make_args(int family, const double *params, int dim, int64_t g, int64_t m, 
 void set_step(VsArgs &A, int dim, uint64_t threads);
 hipStream_t as_stream(void *s);
 
+// Flow kernels (flow.hip).
+hipError_t launch_flow_density(const float *theta, const double *x, int64_t n, double *z,
+                               double *logq, hipStream_t s);
+hipError_t launch_flow_sample(const float *theta, const double *z, int64_t n, double *x,
+                              double *logq, hipStream_t s);
+int64_t flow_scratch_floats(int64_t n);
+int64_t flow_transposed_floats();
+// thetaT: flow_transposed_floats() floats, rewritten from theta on each call
+hipError_t launch_flow_train(const float *theta, float *thetaT, const double *x, const double *w,
+                             int64_t n, double *wsum, float *scratch, float *grad, double *loss,
+                             hipStream_t s);
+hipError_t launch_flow_adam(float *theta, float *m, float *v, const float *grad, float lr,
+                            float beta1, float beta2, float eps, float c1, float c2,
+                            hipStream_t s);
+hipError_t launch_flow_vsample(int family, const float *theta, const VsArgs &A,
+                               uint32_t stream_word, double *partials, int blocks,
+                               hipStream_t s);
+hipError_t launch_vsample_dump(int family, int dim, const VsArgs &A, const double *grid,
+                               uint32_t w0, uint32_t count, double *xs, double *ws,
+                               hipStream_t s);
+hipError_t launch_flow_draw(int family, const float *theta, const VsArgs &A,
+                            uint32_t stream_word, uint32_t n, double *xs, double *ws,
+                            hipStream_t s);
+
+// BF16 matrix-core flow sampling (flow_bf16.hip).
+int64_t flow_bf16_frag_bytes();
+int64_t flow_bf16_bias_floats();
+hipError_t launch_flow_pack_bf16(const float *theta, void *frags, float *bias, hipStream_t s);
+hipError_t launch_flow_sample_bf16(const void *frags, const float *bias, const double *z,
+                                   int64_t n, double *x, double *logq, hipStream_t s);
+hipError_t launch_flow_vsample_bf16(int family, const void *frags, const float *bias,
+                                    const VsArgs &A, uint32_t stream_word, double *partials,
+                                    int blocks, hipStream_t s);
+
 // Microbenchmarks (microbench.hip).
 hipError_t launch_microbench(int kind, int family, int dim, const VsArgs &A, const double *pts,
                              int64_t npts, int64_t calls, int blocks, int block, double *out,
                              hipStream_t stream);
 
 }  // namespace mcubes
+
+// A validated problem with its stratification and V-Sample launch geometry.
+struct mcubes_plan {
+    int family, dim, nb, precision;
+    int block, blocks;
+    size_t lds;
+    int adapt_iters, skip;
+    double alpha;
+    int64_t g, m, p, n;
+    mcubes::VsArgs args;
+    mcubes::VsLaunchFn launch[2];  // [0] without bin sums, [1] with
+    const void *func;
+};

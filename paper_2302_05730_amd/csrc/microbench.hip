@@ -32,7 +32,7 @@ __global__ __launch_bounds__(256) void mb_integrand_kernel(VsArgs A, const doubl
         Acc acc = Family<F, D>::begin(A.phase);
 #pragma unroll
         for (int j = 0; j < D; ++j) Family<F, D>::axis(acc, ca[j], cu[j], x[j]);
-        sum += Family<F, D>::end(acc);
+        sum += Family<F, D>::end(acc, A);
         q = (q + 1 == npts) ? 0 : q + 1;
     }
     out[tid] = sum;
@@ -114,6 +114,8 @@ hipError_t launch_microbench(int kind, int family, int dim, const VsArgs &A, con
             return launch_integrand_f<MCUBES_DISCONTINUOUS>(dim, A, pts, npts, calls, blocks, block, out, s);
         case MCUBES_ADDITION:
             return launch_integrand_f<MCUBES_ADDITION>(dim, A, pts, npts, calls, blocks, block, out, s);
+        case MCUBES_MIXTURE:
+            return launch_integrand_f<MCUBES_MIXTURE>(dim, A, pts, npts, calls, blocks, block, out, s);
         default: return hipErrorInvalidValue;
         }
     }

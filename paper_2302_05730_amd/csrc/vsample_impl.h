@@ -66,6 +66,7 @@ __device__ __forceinline__ void philox10(uint32_t x0, uint32_t x1, uint32_t x2, 
 struct Acc {
     double s;
     bool inside;
+    double s2, t1, t2;  // further sums (mixture family; unused fields cost nothing)
 };
 
 template <int F, int D>
@@ -77,7 +78,7 @@ struct Family<MCUBES_OSCILLATORY, D> {  // cos(2 pi u_0 + sum a_i x_i)
     static __device__ __forceinline__ void axis(Acc &a, double ca, double, double x) {
         a.s = __fma_rn(ca, x, a.s);
     }
-    static __device__ __forceinline__ double end(const Acc &a) { return cos(a.s); }
+    static __device__ __forceinline__ double end(const Acc &a, const VsArgs &) { return cos(a.s); }
 };
 
 template <int D>
@@ -87,7 +88,7 @@ struct Family<MCUBES_PRODUCT_PEAK, D> {  // prod (a_i^-2 + (x_i - u_i)^2)^-1
         const double t = x - cu;
         a.s = a.s * __fma_rn(t, t, ca);
     }
-    static __device__ __forceinline__ double end(const Acc &a) { return 1.0 / a.s; }
+    static __device__ __forceinline__ double end(const Acc &a, const VsArgs &) { return 1.0 / a.s; }
 };
 
 template <int D>
@@ -96,7 +97,7 @@ struct Family<MCUBES_CORNER_PEAK, D> {  // (1 + sum a_i x_i)^-(d+1)
     static __device__ __forceinline__ void axis(Acc &a, double ca, double, double x) {
         a.s = __fma_rn(ca, x, a.s);
     }
-    static __device__ __forceinline__ double end(const Acc &a) {
+    static __device__ __forceinline__ double end(const Acc &a, const VsArgs &) {
         double pw = a.s;
 #pragma unroll
         for (int k = 0; k < D; ++k) pw = pw * a.s;
@@ -111,7 +112,7 @@ struct Family<MCUBES_GAUSSIAN, D> {  // exp(-sum a_i^2 (x_i - u_i)^2)
         const double t = x - cu;
         a.s = __fma_rn(ca, t * t, a.s);
     }
-    static __device__ __forceinline__ double end(const Acc &a) { return exp(-a.s); }
+    static __device__ __forceinline__ double end(const Acc &a, const VsArgs &) { return exp(-a.s); }
 };
 
 template <int D>
@@ -120,7 +121,7 @@ struct Family<MCUBES_C0, D> {  // exp(-sum a_i |x_i - u_i|)
     static __device__ __forceinline__ void axis(Acc &a, double ca, double cu, double x) {
         a.s = __fma_rn(ca, fabs(x - cu), a.s);
     }
-    static __device__ __forceinline__ double end(const Acc &a) { return exp(-a.s); }
+    static __device__ __forceinline__ double end(const Acc &a, const VsArgs &) { return exp(-a.s); }
 };
 
 template <int D>
@@ -130,14 +131,35 @@ struct Family<MCUBES_DISCONTINUOUS, D> {  // exp(sum a_i x_i) if x_i < u_i for a
         a.inside = a.inside && (x < cu);
         a.s = __fma_rn(ca, x, a.s);
     }
-    static __device__ __forceinline__ double end(const Acc &a) { return a.inside ? exp(a.s) : 0.0; }
+    static __device__ __forceinline__ double end(const Acc &a, const VsArgs &) { return a.inside ? exp(a.s) : 0.0; }
 };
 
 template <int D>
 struct Family<MCUBES_ADDITION, D> {  // sum x_i
     static __device__ __forceinline__ Acc begin(double) { return {0.0, true}; }
     static __device__ __forceinline__ void axis(Acc &a, double, double, double x) { a.s = a.s + x; }
-    static __device__ __forceinline__ double end(const Acc &a) { return a.s; }
+    static __device__ __forceinline__ double end(const Acc &a, const VsArgs &) { return a.s; }
+};
+
+// Equal mixture of two equicorrelated Gaussians centred at m_1 1 and m_2 1
+// (ca = m_1, cu = m_2 on every axis): with S1_k = sum (x - m_k) and
+// S2_k = sum (x - m_k)^2, f = norm (exp(-c2 (S2_1 - c1 S1_1^2)) +
+// exp(-c2 (S2_2 - c1 S1_2^2))), c1 = r / (1 - r + d r), c2 = 1 / (2 s^2 (1 - r)).
+template <int D>
+struct Family<MCUBES_MIXTURE, D> {
+    static __device__ __forceinline__ Acc begin(double) { return {0.0, true, 0.0, 0.0, 0.0}; }
+    static __device__ __forceinline__ void axis(Acc &a, double ca, double cu, double x) {
+        const double t1 = x - ca, t2 = x - cu;
+        a.s = a.s + t1;
+        a.s2 = __fma_rn(t1, t1, a.s2);
+        a.t1 = a.t1 + t2;
+        a.t2 = __fma_rn(t2, t2, a.t2);
+    }
+    static __device__ __forceinline__ double end(const Acc &a, const VsArgs &A) {
+        const double q1 = A.mix_c2 * (a.s2 - A.mix_c1 * a.s * a.s);
+        const double q2 = A.mix_c2 * (a.t2 - A.mix_c1 * a.t1 * a.t1);
+        return A.mix_norm * (exp(-q1) + exp(-q2));
+    }
 };
 
 // FP32 forms of the families (precision option): same operations in the
@@ -145,6 +167,7 @@ struct Family<MCUBES_ADDITION, D> {  // sum x_i
 struct Acc32 {
     float s;
     bool inside;
+    float s2, t1, t2;
 };
 
 template <int F, int D>
@@ -156,7 +179,7 @@ struct Family32<MCUBES_OSCILLATORY, D> {
     static __device__ __forceinline__ void axis(Acc32 &a, float ca, float, float x) {
         a.s = __fmaf_rn(ca, x, a.s);
     }
-    static __device__ __forceinline__ float end(const Acc32 &a) { return cosf(a.s); }
+    static __device__ __forceinline__ float end(const Acc32 &a, const VsArgs &) { return cosf(a.s); }
 };
 
 template <int D>
@@ -166,7 +189,7 @@ struct Family32<MCUBES_PRODUCT_PEAK, D> {
         const float t = x - cu;
         a.s = a.s * __fmaf_rn(t, t, ca);
     }
-    static __device__ __forceinline__ float end(const Acc32 &a) { return 1.0f / a.s; }
+    static __device__ __forceinline__ float end(const Acc32 &a, const VsArgs &) { return 1.0f / a.s; }
 };
 
 template <int D>
@@ -175,7 +198,7 @@ struct Family32<MCUBES_CORNER_PEAK, D> {
     static __device__ __forceinline__ void axis(Acc32 &a, float ca, float, float x) {
         a.s = __fmaf_rn(ca, x, a.s);
     }
-    static __device__ __forceinline__ float end(const Acc32 &a) {
+    static __device__ __forceinline__ float end(const Acc32 &a, const VsArgs &) {
         float pw = a.s;
 #pragma unroll
         for (int k = 0; k < D; ++k) pw = pw * a.s;
@@ -190,7 +213,7 @@ struct Family32<MCUBES_GAUSSIAN, D> {
         const float t = x - cu;
         a.s = __fmaf_rn(ca, t * t, a.s);
     }
-    static __device__ __forceinline__ float end(const Acc32 &a) { return expf(-a.s); }
+    static __device__ __forceinline__ float end(const Acc32 &a, const VsArgs &) { return expf(-a.s); }
 };
 
 template <int D>
@@ -199,7 +222,7 @@ struct Family32<MCUBES_C0, D> {
     static __device__ __forceinline__ void axis(Acc32 &a, float ca, float cu, float x) {
         a.s = __fmaf_rn(ca, fabsf(x - cu), a.s);
     }
-    static __device__ __forceinline__ float end(const Acc32 &a) { return expf(-a.s); }
+    static __device__ __forceinline__ float end(const Acc32 &a, const VsArgs &) { return expf(-a.s); }
 };
 
 template <int D>
@@ -209,8 +232,26 @@ struct Family32<MCUBES_DISCONTINUOUS, D> {
         a.inside = a.inside && (x < cu);
         a.s = __fmaf_rn(ca, x, a.s);
     }
-    static __device__ __forceinline__ float end(const Acc32 &a) {
+    static __device__ __forceinline__ float end(const Acc32 &a, const VsArgs &) {
         return a.inside ? expf(a.s) : 0.0f;
+    }
+};
+
+template <int D>
+struct Family32<MCUBES_MIXTURE, D> {
+    static __device__ __forceinline__ Acc32 begin(float) { return {0.0f, true, 0.0f, 0.0f, 0.0f}; }
+    static __device__ __forceinline__ void axis(Acc32 &a, float ca, float cu, float x) {
+        const float t1 = x - ca, t2 = x - cu;
+        a.s = a.s + t1;
+        a.s2 = __fmaf_rn(t1, t1, a.s2);
+        a.t1 = a.t1 + t2;
+        a.t2 = __fmaf_rn(t2, t2, a.t2);
+    }
+    static __device__ __forceinline__ float end(const Acc32 &a, const VsArgs &A) {
+        const float c1 = (float)A.mix_c1, c2 = (float)A.mix_c2;
+        const float q1 = c2 * (a.s2 - c1 * a.s * a.s);
+        const float q2 = c2 * (a.t2 - c1 * a.t1 * a.t1);
+        return (float)A.mix_norm * (expf(-q1) + expf(-q2));
     }
 };
 
@@ -218,7 +259,7 @@ template <int D>
 struct Family32<MCUBES_ADDITION, D> {
     static __device__ __forceinline__ Acc32 begin(float) { return {0.0f, true}; }
     static __device__ __forceinline__ void axis(Acc32 &a, float, float, float x) { a.s = a.s + x; }
-    static __device__ __forceinline__ float end(const Acc32 &a) { return a.s; }
+    static __device__ __forceinline__ float end(const Acc32 &a, const VsArgs &) { return a.s; }
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -302,7 +343,7 @@ __device__ __forceinline__ double draw(const VsArgs &A, uint32_t iteration, cons
         }
     }
     const double J = A.nbd * prod;
-    return Family<F, D>::end(acc) * J;
+    return Family<F, D>::end(acc, A) * J;
 }
 
 // FP32 form of one sample: the bin coordinates, bin indices and in-bin
@@ -355,7 +396,7 @@ __device__ __forceinline__ double draw32(const VsArgs &A, uint32_t iteration, co
             }
         }
     }
-    return (double)Family32<F, D>::end(acc) * (A.nbd * prod);
+    return (double)Family32<F, D>::end(acc, A) * (A.nbd * prod);
 }
 
 // Largest block of a V-Sample instantiation.  The LDS tables allow one block

@@ -59,6 +59,10 @@ int main(void) {
     printf("mcubes_batch_class size %zu\n", sizeof(mcubes_batch_class));
     F(mcubes_batch_class, shares) F(mcubes_batch_class, samples) F(mcubes_batch_class, tuned_ms)
     F(mcubes_batch_class, default_ms)
+    printf("mcubes_flow_options size %zu\n", sizeof(mcubes_flow_options));
+    F(mcubes_flow_options, train_items) F(mcubes_flow_options, batch) F(mcubes_flow_options, round_lr)
+    printf("mcubes_flow_report size %zu\n", sizeof(mcubes_flow_report));
+    F(mcubes_flow_report, final_loss) F(mcubes_flow_report, used_flow)
     printf("MCUBES_STATE_LEN x %d\n", MCUBES_STATE_LEN);
     return 0;
 }
@@ -100,7 +104,11 @@ def _create(family=3, params=None, dim=2, ncall=1000, **opt):
     (dict(dim=0), mc.MCUBES_E_ARG),
     (dict(dim=11), mc.MCUBES_E_ARG),
     (dict(ncall=1), mc.MCUBES_E_ARG),
-    (dict(family=7), mc.MCUBES_E_INTEGRAND),
+    (dict(family=8), mc.MCUBES_E_INTEGRAND),
+    (dict(family=7, params=[0.0, 0.5, 0.3, 0.6]), mc.MCUBES_E_INTEGRAND),
+    (dict(family=7, params=[0.1, 1.0, 0.3, 0.6]), mc.MCUBES_E_INTEGRAND),
+    (dict(family=7, params=[0.1, -0.2, 0.3, 0.6]), mc.MCUBES_E_INTEGRAND),
+    (dict(family=7, dim=1, params=[0.1, 0.3]), mc.MCUBES_E_INTEGRAND),
     (dict(family=-1), mc.MCUBES_E_INTEGRAND),
     (dict(params=[float("nan"), 1.0, 1.0, 1.0]), mc.MCUBES_E_INTEGRAND),
     (dict(params=[1.0, float("inf"), 1.0, 1.0]), mc.MCUBES_E_INTEGRAND),

@@ -78,6 +78,7 @@ CASES = [
     (4, 3, 300, 150_000), (4, 8, 120, 300_000),
     (5, 2, 500, 120_000), (5, 5, 50, 200_000), (5, 10, 10, 100_000),
     (6, 1, 3, 1000), (6, 5, 500, 300_000), (6, 8, 500, 600_000), (6, 10, 500, 400_000),
+    (7, 2, 50, 100_001), (7, 6, 500, 500_000), (7, 10, 211, 300_000),
 ]
 
 

@@ -98,6 +98,11 @@ def random_problem(rng, family, dim, ncall, nbins):
     dimension so that the integral stays representable)."""
     if family == ADDITION:
         params = [0.0] * (2 * dim)
+    elif family == MIXTURE:
+        s, r = rng.uniform(0.05, 0.3), rng.uniform(0.0, 0.95)
+        m1, m2 = rng.uniform(0.2, 0.5), rng.uniform(0.5, 0.8)
+        params = [float(s), float(r)] + [0.0] * (dim - 2) + [float(m1), float(m2)] + \
+            [0.0] * (dim - 2)
     elif family == DISCONTINUOUS:
         params = genz_params(rng, dim, 1.0, 8.0, 0.3, 1.2)
     elif family == CORNER_PEAK:
