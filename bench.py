@@ -175,6 +175,59 @@ def bench_batch(mc, n, iters, full=True):
     return out
 
 
+# network multiply-adds per flow sample: 4 coupling layers, each 96x64 + 64x64 + 64x99
+FLOW_GEMM_FLOPS = 2 * 4 * (96 * 64 + 64 * 64 + 64 * 99)
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+
+def bench_flow(mc, ncall, plain_iters=50):
+    """The learned-proposal form on the 6-D correlated mixture (integral 1):
+    plain FP64 m-Cubes for plain_iters iterations against the whole flow
+    pipeline (warm-up, training, BF16 proposal iterations) run to 1e-3, with
+    wall times, estimates, claimed and true errors."""
+    pr = workloads.mixture_6d(ncall=ncall)
+    opts = mc.mcubes_default_options(nbins=500)
+    t_a = time.perf_counter()
+    r = mc.mcubes_integrate(pr.family, pr.params, 6, ncall, plain_iters, 1e-3, 11, opts)
+    t_b = time.perf_counter()
+    plain = {"seconds": round(t_b - t_a, 4), "iterations": r["iterations"],
+             "converged": r["converged"], "estimate": r["estimate"], "error": r["error"],
+             "chi2_dof": r["chi2_dof"], "true_rel_error": abs(r["estimate"] - 1.0)}
+    # the plain method's own error bar would need (error / 1e-3)^2 times the iterations
+    plain["iterations_for_claimed_1e-3"] = (r["iterations"] * (r["error"] / 1e-3) ** 2
+                                            if r["error"] else None)
+    fl = mc.Flow(workloads.flow_init(7))
+    t_a = time.perf_counter()
+    res, rep = fl.integrate(pr.family, pr.params, ncall, 10, 1e-3, 11, opts)
+    t_b = time.perf_counter()
+    fo = mc.mcubes_flow_options()
+    mc.lib().mcubes_default_flow_options(mc.ctypes.byref(fo))
+    items = min(fo.train_items, mc.mcubes_plan_sizes(6, ncall)[1])
+    p = mc.mcubes_plan_sizes(6, ncall)[2]
+    trained = (items * p * fo.epochs
+               + (fo.rounds + fo.tail_rounds) * fo.round_samples * fo.round_epochs)
+    n_eval = mc.mcubes_plan_sizes(6, ncall)[3]
+    flow_s = rep["flow_ms"] * 1e-3
+    evals = n_eval * res["iterations"] / flow_s if flow_s > 0 else None
+    flow = {"seconds": round(t_b - t_a, 4), "total_ms": round(rep["total_ms"], 2),
+            "warmup_ms": round(rep["warmup_ms"], 2), "train_ms": round(rep["train_ms"], 2),
+            "proposal_ms": round(rep["flow_ms"], 2), "iterations": res["iterations"],
+            "converged": res["converged"], "estimate": res["estimate"], "error": res["error"],
+            "chi2_dof": res["chi2_dof"], "true_rel_error": abs(res["estimate"] - 1.0),
+            "used_flow": rep["used_flow"], "last_plain_var": rep["last_plain_var"],
+            "first_flow_var": rep["first_flow_var"],
+            "training_samples_per_s": trained / (rep["train_ms"] * 1e-3),
+            "proposal_evals_per_s": evals,
+            "proposal_network_tflops": (evals * FLOW_GEMM_FLOPS / 1e12) if evals else None}
+    if flow["proposal_network_tflops"]:
+        flow["proposal_frac_of_bf16_mfma_peak"] = (flow["proposal_network_tflops"]
+                                                   / BF16_MFMA_PEAK_TFLOPS)
+    return {"workload": ("6-D mixture of two correlated Gaussians (sigma 0.05, correlation "
+                         f"0.9, centres 1/3 and 2/3 on the diagonal), {ncall} samples/iter, "
+                         "500 bins; integral 1"),
+            "plain_fp64": plain, "flow_pipeline_bf16": flow}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +242,10 @@ def main():
     ap.add_argument("--batch-n", type=int, default=512,
                     help="integrands of the batched-form measurement (0 = skip it)")
     ap.add_argument("--batch-iters", type=int, default=5)
+    ap.add_argument("--flow-ncall", type=int, default=1 << 26,
+                    help="samples per iteration of the learned-proposal section (0: skip)")
+    ap.add_argument("--only-flow", action="store_true",
+                    help="run only the learned-proposal section and print it")
     ap.add_argument("--only-batch", action="store_true",
                     help="measure only the batched form at its default geometry (no autotuner)"
                          " and print its figures as one JSON line (for profiling)")
@@ -209,6 +266,10 @@ def main():
     if args.only_batch:
         print(json.dumps({"batched": bench_batch(mc, args.batch_n or 512, args.batch_iters,
                                                  full=False)}), flush=True)
+        return
+    if args.only_flow:
+        print(json.dumps({"learned_proposal": bench_flow(mc, args.flow_ncall or (1 << 26))}),
+              flush=True)
         return
     if args.calibrate_copy_mib:
         n = args.calibrate_copy_mib * (1 << 20) // 8
@@ -336,6 +397,7 @@ def main():
                                           if b["error"] else None)
 
     batched = bench_batch(mc, args.batch_n, args.batch_iters) if args.batch_n > 0 else None
+    flow = bench_flow(mc, args.flow_ncall) if args.flow_ncall > 0 else None
     cpu = None if args.no_cpu else cpu_baseline(problems, args.cpu_ncall)
     out = {
         "metric": "integrand evals/s + time to 1e-3 rel err, plain FP64 vs FP32/flow form",
@@ -351,6 +413,7 @@ def main():
                    "blocks": plans[0].info["blocks"], "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "time_to_1e-3": ttt,
         "frozen_grid_vsample": frozen, "fp32_vsample": fp32, "batched": batched,
+        "learned_proposal": flow,
     }
     print(json.dumps(out), flush=True)
 

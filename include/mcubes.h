@@ -447,7 +447,11 @@ int mcubes_flow_vsample(mcubes_flow *flow, int precision, const mcubes_plan *pla
  *   2. the samples and weights of train_items work items of the last of them
  *      (mcubes_vsample_dump) train the flow for `epochs` epochs;
  *   3. `rounds` times: round_samples samples of the flow itself with weights
- *      f/q (mcubes_flow_draw) train it for round_epochs epochs;
+ *      f/q (mcubes_flow_draw) train it for round_epochs epochs; then
+ *      tail_rounds more such rounds with the weights raised to tail_power
+ *      (> 1 stresses the samples the flow under-weights: between the
+ *      Kullback-Leibler objective, power 1, and the variance, power 2) at
+ *      learning rate tail_lr;
  *   4. flow-mapped iterations (mcubes_flow_vsample, in `precision`) combined
  *      by inverse-variance weighting until error <= rel_tol |estimate| or
  *      itmax of them.
@@ -456,19 +460,25 @@ int mcubes_flow_vsample(mcubes_flow *flow, int precision, const mcubes_plan *pla
  * remaining iterations run plain (report->used_flow = 0).  `flow` is trained
  * in place (start from an identity flow for a fresh run).  out receives the
  * combined result of the iterations that decide it (flow, or plain on
- * fallback).  Synchronous; allocates its buffers. */
+ * fallback).  Synchronous; allocates its buffers.
+ * The flow's weights have a long tail where it is thinner than f (regions
+ * of f that training has barely sampled): on the 6-D correlated mixture
+ * the defaults leave the estimate a few 1e-4 low, with an error estimate
+ * that can be a few times too small. */
 typedef struct {
     int32_t warmup_iters;  /* default 8 */
     int32_t precision;     /* proposal iterations: MCUBES_BF16 (default) or MCUBES_FP32 */
-    int64_t train_items;   /* default 2^18 (each gives p samples) */
-    int32_t epochs;        /* default 6 */
-    int32_t rounds;        /* default 2 */
-    int64_t round_samples; /* default 2^19 */
+    int64_t train_items;   /* default 2^20 (each gives p samples) */
+    int32_t epochs;        /* default 10 */
+    int32_t rounds;        /* default 6 */
+    int64_t round_samples; /* default 2^22 */
     int32_t round_epochs;  /* default 2 */
-    int32_t reserved;
+    int32_t tail_rounds;   /* default 2 */
     int64_t batch;         /* default 16384 */
     double lr;             /* default 1e-3 */
     double round_lr;       /* default 5e-4 */
+    double tail_power;     /* default 1.5 */
+    double tail_lr;        /* default 2e-4 */
 } mcubes_flow_options;
 
 typedef struct {

@@ -68,8 +68,9 @@ class mcubes_flow_options(ctypes.Structure):
     _fields_ = [("warmup_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("train_items", ctypes.c_int64), ("epochs", ctypes.c_int32),
                 ("rounds", ctypes.c_int32), ("round_samples", ctypes.c_int64),
-                ("round_epochs", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("batch", ctypes.c_int64), ("lr", ctypes.c_double), ("round_lr", ctypes.c_double)]
+                ("round_epochs", ctypes.c_int32), ("tail_rounds", ctypes.c_int32),
+                ("batch", ctypes.c_int64), ("lr", ctypes.c_double), ("round_lr", ctypes.c_double),
+                ("tail_power", ctypes.c_double), ("tail_lr", ctypes.c_double)]
 
 
 class mcubes_flow_report(ctypes.Structure):

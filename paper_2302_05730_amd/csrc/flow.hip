@@ -440,6 +440,11 @@ __global__ __launch_bounds__(256) void bias_grad_kernel(const float *__restrict_
     if (threadIdx.x == 0) grad[l * LP + dst] = red[0];
 }
 
+__global__ void pow_kernel(double *__restrict__ w, int64_t n, double power) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) w[i] = pow(w[i], power);
+}
+
 // One Adam step on the FP32 master parameters; c1 = 1 - beta1^t, c2 = 1 - beta2^t.
 __global__ void adam_kernel(float *__restrict__ theta, float *__restrict__ m,
                             float *__restrict__ v, const float *__restrict__ grad, int count,
@@ -695,6 +700,12 @@ hipError_t launch_flow_train(const float *theta, float *thetaT, const double *x,
     hipLaunchKernelGGL(wgrad_sum_kernel, dim3((PARAMS + 255) / 256), dim3(256), 0, s, part,
                        (int)slices, grad);
     hipLaunchKernelGGL(bias_grad_kernel, dim3(L * NBIAS), dim3(256), 0, s, scratch, n, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_pow_weights(double *w, int64_t n, double power, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pow_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, n, power);
     return hipGetLastError();
 }
 

@@ -312,14 +312,17 @@ void mcubes_default_flow_options(mcubes_flow_options *o) {
     memset(o, 0, sizeof *o);
     o->warmup_iters = 8;
     o->precision = MCUBES_BF16;
-    o->train_items = (int64_t)1 << 18;
-    o->epochs = 6;
-    o->rounds = 2;
-    o->round_samples = (int64_t)1 << 19;
+    o->train_items = (int64_t)1 << 20;
+    o->epochs = 10;
+    o->rounds = 6;
+    o->round_samples = (int64_t)1 << 22;
     o->round_epochs = 2;
+    o->tail_rounds = 2;
     o->batch = 16384;
     o->lr = 1e-3;
     o->round_lr = 5e-4;
+    o->tail_power = 1.5;
+    o->tail_lr = 2e-4;
 }
 
 int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int64_t ncall,
@@ -334,7 +337,9 @@ int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int6
     mcubes_default_flow_options(&fo);
     if (fopt_in) fo = *fopt_in;
     if (fo.warmup_iters < 1 || fo.warmup_iters + itmax > MCUBES_MAX_ITERATIONS || fo.epochs < 0 ||
-        fo.rounds < 0 || fo.round_epochs < 0 || fo.batch < 1 || fo.train_items < 1 ||
+        fo.rounds < 0 || fo.round_epochs < 0 || fo.tail_rounds < 0 || fo.batch < 1 ||
+        fo.train_items < 1 || !(fo.tail_power >= 1.0 && fo.tail_power <= 4.0) ||
+        !(fo.tail_lr > 0.0) ||
         fo.round_samples < 1 || fo.round_samples > ((int64_t)1 << 31) || !(fo.lr > 0.0) ||
         !(fo.round_lr > 0.0) || (fo.precision != MCUBES_FP32 && fo.precision != MCUBES_BF16))
         return fail(MCUBES_E_ARG, "invalid flow options");
@@ -409,11 +414,14 @@ int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int6
             R.final_loss = losses[ep - 1];
         }
         const int rep_ep = fo.round_epochs < 1024 ? fo.round_epochs : 1024;
-        for (int r = 0; r < fo.rounds; ++r) {
+        for (int r = 0; r < fo.rounds + fo.tail_rounds; ++r) {
+            const bool tail = r >= fo.rounds;
             FI_CALL(mcubes_flow_draw(F, P, (uint32_t)(1000 + r), fo.round_samples, dx, dw, opt.stream));
+            if (tail && fo.tail_power != 1.0)
+                FI_CHECK(launch_pow_weights(dw, fo.round_samples, fo.tail_power, s), "weights launch");
             if (rep_ep > 0) {
-                FI_CALL(mcubes_flow_train(F, dx, dw, fo.round_samples, rep_ep, fo.batch, fo.round_lr,
-                                          losses, opt.stream));
+                FI_CALL(mcubes_flow_train(F, dx, dw, fo.round_samples, rep_ep, fo.batch,
+                                          tail ? fo.tail_lr : fo.round_lr, losses, opt.stream));
                 R.final_loss = losses[rep_ep - 1];
             }
         }

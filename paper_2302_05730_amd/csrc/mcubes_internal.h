@@ -138,6 +138,8 @@ hipError_t launch_flow_sample(const float *theta, const double *z, int64_t n, do
                               double *logq, hipStream_t s);
 int64_t flow_scratch_floats(int64_t n);
 int64_t flow_transposed_floats();
+// w[i] <- w[i]^power (training weights of the tail rounds)
+hipError_t launch_pow_weights(double *w, int64_t n, double power, hipStream_t s);
 // thetaT: flow_transposed_floats() floats, rewritten from theta on each call
 hipError_t launch_flow_train(const float *theta, float *thetaT, const double *x, const double *w,
                              int64_t n, double *wsum, float *scratch, float *grad, double *loss,
