@@ -50,13 +50,16 @@ def flops_per_sample(family, d, p):
 
 
 def source_digest():
-    """SHA-256 over the HIP sources of the library (identifies the kernel build
-    that a stored counter profile belongs to)."""
+    """SHA-256 over the sources that define the single-integrand V-Sample
+    kernel and its launch (identifies the kernel build that a stored counter
+    profile belongs to): the kernel template, its per-family instantiations,
+    the shared declarations and the host code that sizes the launch."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2302_05730_amd", "csrc")
     h = hashlib.sha256()
     for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
+        if (name in ("vsample_impl.h", "mcubes_internal.h", "mcubes_api.hip")
+                or (name.startswith("vsample_f") and name.endswith(".hip"))):
             with open(os.path.join(csrc, name), "rb") as fh:
                 h.update(name.encode() + b"\0" + fh.read())
     return h.hexdigest()
