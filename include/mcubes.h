@@ -405,17 +405,24 @@ int mcubes_flow_sample(mcubes_flow *flow, int precision, const double *d_z, int6
  * *d_loss (device, 1 double) += -sum w_i log q(x_i) / sum w_i (zero it
  * first); the gradient with respect to the parameters is kept in the flow
  * (for mcubes_flow_adam_step) and copied to d_grad (device,
- * MCUBES_FLOW_PARAMS doubles) when that is not NULL.  FP32. */
-int mcubes_flow_loss_grad(mcubes_flow *flow, const double *d_x, const double *d_w, int64_t n,
-                          double *d_grad, double *d_loss, void *stream);
+ * MCUBES_FLOW_PARAMS doubles) when that is not NULL.
+ * precision: MCUBES_FP32 runs every product of the forward and backward
+ * pass in FP32 on the vector units; MCUBES_BF16 runs the nine products per
+ * layer on the matrix cores (BF16 weights and product inputs, FP32
+ * accumulation; splines FP32), which makes the gradient approximate.  The
+ * weight gradients (sums over the samples) are FP32 in both. */
+int mcubes_flow_loss_grad(mcubes_flow *flow, int precision, const double *d_x, const double *d_w,
+                          int64_t n, double *d_grad, double *d_loss, void *stream);
 /* One Adam step (bias-corrected; the flow counts the steps) with the kept gradient. */
 int mcubes_flow_adam_step(mcubes_flow *flow, double lr, double beta1, double beta2, double eps,
                           void *stream);
 /* epochs passes of mini-batches of `batch` consecutive samples (the last one
  * shorter), one Adam step each (beta1 0.9, beta2 0.999, eps 1e-8).
- * losses (host, epochs doubles, may be NULL): mean batch loss per epoch. */
-int mcubes_flow_train(mcubes_flow *flow, const double *d_x, const double *d_w, int64_t n,
-                      int epochs, int64_t batch, double lr, double *losses, void *stream);
+ * losses (host, epochs doubles, may be NULL): mean batch loss per epoch.
+ * precision as for mcubes_flow_loss_grad. */
+int mcubes_flow_train(mcubes_flow *flow, int precision, const double *d_x, const double *d_w,
+                      int64_t n, int epochs, int64_t batch, double lr, double *losses,
+                      void *stream);
 
 /* The samples and weights w = f J of work items [w_begin, w_begin + count)
  * of iteration `iteration` of the plain method on d_grid: work item w is
@@ -474,11 +481,13 @@ typedef struct {
     int64_t round_samples; /* default 2^22 */
     int32_t round_epochs;  /* default 2 */
     int32_t tail_rounds;   /* default 2 */
-    int64_t batch;         /* default 16384 */
-    double lr;             /* default 1e-3 */
-    double round_lr;       /* default 5e-4 */
+    int64_t batch;         /* default 32768 */
+    double lr;             /* default 2e-3 */
+    double round_lr;       /* default 1e-3 */
     double tail_power;     /* default 1.5 */
-    double tail_lr;        /* default 2e-4 */
+    double tail_lr;        /* default 4e-4 */
+    int32_t train_precision; /* training products: MCUBES_BF16 (default) or MCUBES_FP32 */
+    int32_t reserved;
 } mcubes_flow_options;
 
 typedef struct {

@@ -70,7 +70,8 @@ class mcubes_flow_options(ctypes.Structure):
                 ("rounds", ctypes.c_int32), ("round_samples", ctypes.c_int64),
                 ("round_epochs", ctypes.c_int32), ("tail_rounds", ctypes.c_int32),
                 ("batch", ctypes.c_int64), ("lr", ctypes.c_double), ("round_lr", ctypes.c_double),
-                ("tail_power", ctypes.c_double), ("tail_lr", ctypes.c_double)]
+                ("tail_power", ctypes.c_double), ("tail_lr", ctypes.c_double),
+                ("train_precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class mcubes_flow_report(ctypes.Structure):
@@ -154,11 +155,12 @@ _SIGNATURES = {
     "mcubes_flow_set_params": (ctypes.c_int, [_vp, _dp]),
     "mcubes_flow_density": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int64, _vp, _vp, _vp]),
     "mcubes_flow_sample": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int64, _vp, _vp, _vp]),
-    "mcubes_flow_loss_grad": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp, _vp]),
+    "mcubes_flow_loss_grad": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int64, _vp,
+                                             _vp, _vp]),
     "mcubes_flow_adam_step": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_double, ctypes.c_double, _vp]),
-    "mcubes_flow_train": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int,
-                                         ctypes.c_int64, ctypes.c_double, _dp, _vp]),
+    "mcubes_flow_train": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int64,
+                                         ctypes.c_int, ctypes.c_int64, ctypes.c_double, _dp, _vp]),
     "mcubes_vsample_dump": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, ctypes.c_int64,
                                            ctypes.c_int64, _vp, _vp, _vp]),
     "mcubes_flow_vsample": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_uint32, _vp, _vp]),
@@ -526,8 +528,8 @@ class Flow:
                                         int(n), _dev(d_x, 6 * n, "x"),
                                         _dev(d_logq, n, "logq"), _stream(stream)))
 
-    def loss_grad(self, d_x, d_w, n, d_grad, d_loss, stream=None):
-        _check(lib().mcubes_flow_loss_grad(self.handle, _dev(d_x, 6 * n, "x"),
+    def loss_grad(self, d_x, d_w, n, d_grad, d_loss, stream=None, precision=MCUBES_FP32):
+        _check(lib().mcubes_flow_loss_grad(self.handle, int(precision), _dev(d_x, 6 * n, "x"),
                                            _dev(d_w, n, "w"), int(n),
                                            _dev(d_grad, MCUBES_FLOW_PARAMS, "grad")
                                            if d_grad is not None else None,
@@ -537,11 +539,11 @@ class Flow:
         _check(lib().mcubes_flow_adam_step(self.handle, float(lr), float(beta1), float(beta2),
                                            float(eps), _stream(stream)))
 
-    def train(self, d_x, d_w, n, epochs, batch, lr, stream=None):
+    def train(self, d_x, d_w, n, epochs, batch, lr, stream=None, precision=MCUBES_BF16):
         losses = (ctypes.c_double * max(int(epochs), 1))()
-        _check(lib().mcubes_flow_train(self.handle, _dev(d_x, 6 * n, "x"), _dev(d_w, n, "w"),
-                                       int(n), int(epochs), int(batch), float(lr), losses,
-                                       _stream(stream)))
+        _check(lib().mcubes_flow_train(self.handle, int(precision), _dev(d_x, 6 * n, "x"),
+                                       _dev(d_w, n, "w"), int(n), int(epochs), int(batch),
+                                       float(lr), losses, _stream(stream)))
         return list(losses)[:int(epochs)]
 
     def draw(self, plan, iteration, n, d_x, d_w, stream=None):

@@ -12,12 +12,6 @@ namespace {
 
 using namespace flow;
 
-// Scratch fields of one sample and layer (FP32, field-major, sample
-// contiguous): the layer's input u (6), h1, h2, the output-layer deltas
-// (99) and the deltas after the two ReLUs (64 each).
-constexpr int FS_U = 0, FS_H1 = FS_U + D, FS_H2 = FS_H1 + HID, FS_DOUT = FS_H2 + HID;
-constexpr int FS_D2 = FS_DOUT + OUT, FS_D1 = FS_D2 + HID, FS = FS_D1 + HID;
-
 // Cooperative form: a workgroup of CW waves takes CS = 64 samples (lane =
 // sample).  Each matrix product is split over the waves by output feature,
 // so the weights a wave reads are the same for all its lanes (scalar loads)
@@ -260,15 +254,15 @@ __global__ void transpose_kernel(const float *__restrict__ theta, float *__restr
     thetaT[i] = v;
 }
 
-// sum of the n weights (one block, fixed order)
-__global__ __launch_bounds__(256) void wsum_kernel(const double *__restrict__ w, int64_t n,
-                                                   double *__restrict__ out) {
-    __shared__ double red[256];
+// sum of the n weights (one block of 1024 threads, fixed order)
+__global__ __launch_bounds__(1024) void wsum_kernel(const double *__restrict__ w, int64_t n,
+                                                    double *__restrict__ out) {
+    __shared__ double red[1024];
     double a = 0.0;
-    for (int64_t s = threadIdx.x; s < n; s += 256) a += w[s];
+    for (int64_t s = threadIdx.x; s < n; s += 1024) a += w[s];
     red[threadIdx.x] = a;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
+    for (int h = 512; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
         __syncthreads();
     }
@@ -278,7 +272,7 @@ __global__ __launch_bounds__(256) void wsum_kernel(const double *__restrict__ w,
 // Forward and backward pass of the weighted negative log-likelihood: loss
 // contribution c log q(x) of each sample, c = -w / sum w.  The weight
 // gradients are formed afterwards from the scratch fields.
-__global__ __launch_bounds__(CT) void train_kernel(const float *__restrict__ theta,
+__global__ __launch_bounds__(CT, 4) void train_kernel(const float *__restrict__ theta,
                                                    const float *__restrict__ thetaT,
                                                    const double *__restrict__ x,
                                                    const double *__restrict__ w, int64_t n,
@@ -679,15 +673,23 @@ int64_t flow_scratch_floats(int64_t n) { return (int64_t)L * FS * n + (int64_t)k
 
 int64_t flow_transposed_floats() { return (int64_t)L * LPT; }
 
-hipError_t launch_flow_train(const float *theta, float *thetaT, const double *x, const double *w,
-                             int64_t n, double *wsum, float *scratch, float *grad, double *loss,
-                             hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(wsum_kernel, dim3(1), dim3(256), 0, s, w, n, wsum);
+hipError_t launch_flow_wsum(const double *w, int64_t n, double *wsum, hipStream_t s) {
+    hipLaunchKernelGGL(wsum_kernel, dim3(1), dim3(1024), 0, s, w, n, wsum);
+    return hipGetLastError();
+}
+
+hipError_t launch_flow_train_fp32(const float *theta, float *thetaT, const double *x,
+                                  const double *w, int64_t n, const double *wsum, float *scratch,
+                                  double *loss, hipStream_t s) {
     hipLaunchKernelGGL(transpose_kernel, dim3((L * LPT + 255) / 256), dim3(256), 0, s, theta,
                        thetaT);
     hipLaunchKernelGGL(train_kernel, dim3((unsigned)((n + CS - 1) / CS)), dim3(CT), 0, s, theta,
                        thetaT, x, w, n, wsum, scratch, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_flow_wgrad(const float *scratch_in, int64_t n, float *grad, hipStream_t s) {
+    float *scratch = const_cast<float *>(scratch_in);
     // slices of at least 512 samples, at most kMaxSlices of them
     int64_t slices = (n + 511) / 512;
     if (slices > kMaxSlices) slices = kMaxSlices;

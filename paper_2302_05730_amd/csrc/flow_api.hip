@@ -15,6 +15,7 @@ struct mcubes_flow {
     float *d_theta = nullptr, *d_m = nullptr, *d_v = nullptr, *d_grad = nullptr;
     float *d_thetaT = nullptr;         // transposed weight matrices (backward pass)
     void *d_frags = nullptr;           // BF16 weight fragments for the matrix-core path
+    void *d_bfrags = nullptr;          // BF16 fragments of the backward products
     float *d_fbias = nullptr;          // biases in accumulator order
     bool packed = false;               // fragments up to date with d_theta
     double *d_aux = nullptr;           // [0] sum of weights, [1] loss
@@ -38,6 +39,7 @@ void release(mcubes_flow *F) {
     hipFree(F->d_grad);
     hipFree(F->d_thetaT);
     hipFree(F->d_frags);
+    hipFree(F->d_bfrags);
     hipFree(F->d_fbias);
     hipFree(F->d_aux);
     hipFree(F->d_part);
@@ -86,6 +88,27 @@ int ensure_scratch(mcubes_flow *F, int64_t n) {
     return MCUBES_OK;
 }
 
+// One step's forward/backward pass and weight gradients (loss += its value).
+hipError_t train_step(mcubes_flow *F, int precision, const double *d_x, const double *d_w,
+                      int64_t n, double *d_loss, hipStream_t s) {
+    hipError_t e = launch_flow_wsum(d_w, n, F->d_aux, s);
+    if (e != hipSuccess) return e;
+    if (precision == MCUBES_BF16)
+        e = launch_flow_train_bf16(F->d_theta, F->d_frags, F->d_bfrags, F->d_fbias, d_x, d_w, n,
+                                   F->d_aux, F->d_scratch, d_loss, F->cus, s);
+    else
+        e = launch_flow_train_fp32(F->d_theta, F->d_thetaT, d_x, d_w, n, F->d_aux, F->d_scratch,
+                                   d_loss, s);
+    if (e != hipSuccess) return e;
+    return launch_flow_wgrad(F->d_scratch, n, F->d_grad, s);
+}
+
+int check_train_precision(int precision) {
+    if (precision != MCUBES_FP32 && precision != MCUBES_BF16)
+        return fail(MCUBES_E_ARG, "precision must be MCUBES_FP32 or MCUBES_BF16");
+    return MCUBES_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -108,6 +131,7 @@ int mcubes_flow_create(const double *theta, mcubes_flow **out) {
     if (e == hipSuccess)
         e = hipMalloc((void **)&F->d_thetaT, (size_t)flow_transposed_floats() * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&F->d_frags, (size_t)flow_bf16_frag_bytes());
+    if (e == hipSuccess) e = hipMalloc(&F->d_bfrags, (size_t)flow_bf16_bwd_frag_bytes());
     if (e == hipSuccess)
         e = hipMalloc((void **)&F->d_fbias, (size_t)flow_bf16_bias_floats() * sizeof(float));
     if (e == hipSuccess) e = hipMalloc((void **)&F->d_aux, 2 * sizeof(double));
@@ -171,15 +195,16 @@ int mcubes_flow_sample(mcubes_flow *F, int precision, const double *d_z, int64_t
     return e == hipSuccess ? MCUBES_OK : hip_fail(e, "flow sample launch");
 }
 
-int mcubes_flow_loss_grad(mcubes_flow *F, const double *d_x, const double *d_w, int64_t n,
-                          double *d_grad, double *d_loss, void *stream) {
+int mcubes_flow_loss_grad(mcubes_flow *F, int precision, const double *d_x, const double *d_w,
+                          int64_t n, double *d_grad, double *d_loss, void *stream) {
     if (!F || !d_x || !d_w || !d_loss) return fail(MCUBES_E_ARG, "NULL argument");
     if (n < 1 || n > kMaxSamples) return fail(MCUBES_E_ARG, "n must be in [1, 2^31]");
-    int rc = ensure_scratch(F, n);
+    int rc = check_train_precision(precision);
+    if (rc != MCUBES_OK) return rc;
+    rc = ensure_scratch(F, n);
     if (rc != MCUBES_OK) return rc;
     hipStream_t s = as_stream(stream);
-    hipError_t e = launch_flow_train(F->d_theta, F->d_thetaT, d_x, d_w, n, F->d_aux, F->d_scratch, F->d_grad,
-                                     d_loss, s);
+    hipError_t e = train_step(F, precision, d_x, d_w, n, d_loss, s);
     if (e == hipSuccess && d_grad) {
         // widen the kept FP32 gradient for the caller
         std::vector<float> h(flow::PARAMS);
@@ -209,13 +234,16 @@ int mcubes_flow_adam_step(mcubes_flow *F, double lr, double beta1, double beta2,
     return e == hipSuccess ? MCUBES_OK : hip_fail(e, "Adam launch");
 }
 
-int mcubes_flow_train(mcubes_flow *F, const double *d_x, const double *d_w, int64_t n, int epochs,
-                      int64_t batch, double lr, double *losses, void *stream) {
+int mcubes_flow_train(mcubes_flow *F, int precision, const double *d_x, const double *d_w,
+                      int64_t n, int epochs, int64_t batch, double lr, double *losses,
+                      void *stream) {
     if (!F || !d_x || !d_w) return fail(MCUBES_E_ARG, "NULL argument");
     if (n < 1 || n > kMaxSamples) return fail(MCUBES_E_ARG, "n must be in [1, 2^31]");
     if (epochs < 0 || batch < 1) return fail(MCUBES_E_ARG, "epochs >= 0 and batch >= 1 required");
+    int rc = check_train_precision(precision);
+    if (rc != MCUBES_OK) return rc;
     if (batch > n) batch = n;
-    int rc = ensure_scratch(F, batch);
+    rc = ensure_scratch(F, batch);
     if (rc != MCUBES_OK) return rc;
     hipStream_t s = as_stream(stream);
     double *d_loss = F->d_aux + 1;
@@ -225,8 +253,7 @@ int mcubes_flow_train(mcubes_flow *F, const double *d_x, const double *d_w, int6
         int nbatch = 0;
         for (int64_t b0 = 0; b0 < n && e == hipSuccess; b0 += batch) {
             const int64_t nb = n - b0 < batch ? n - b0 : batch;
-            e = launch_flow_train(F->d_theta, F->d_thetaT, d_x + b0 * flow::D, d_w + b0, nb, F->d_aux,
-                                  F->d_scratch, F->d_grad, d_loss, s);
+            e = train_step(F, precision, d_x + b0 * flow::D, d_w + b0, nb, d_loss, s);
             if (e == hipSuccess) {
                 F->step += 1;
                 const double c1 = 1.0 - pow(0.9, (double)F->step);
@@ -318,11 +345,12 @@ void mcubes_default_flow_options(mcubes_flow_options *o) {
     o->round_samples = (int64_t)1 << 22;
     o->round_epochs = 2;
     o->tail_rounds = 2;
-    o->batch = 16384;
-    o->lr = 1e-3;
-    o->round_lr = 5e-4;
+    o->batch = 32768;
+    o->lr = 2e-3;
+    o->round_lr = 1e-3;
     o->tail_power = 1.5;
-    o->tail_lr = 2e-4;
+    o->tail_lr = 4e-4;
+    o->train_precision = MCUBES_BF16;
 }
 
 int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int64_t ncall,
@@ -340,6 +368,7 @@ int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int6
         fo.rounds < 0 || fo.round_epochs < 0 || fo.tail_rounds < 0 || fo.batch < 1 ||
         fo.train_items < 1 || !(fo.tail_power >= 1.0 && fo.tail_power <= 4.0) ||
         !(fo.tail_lr > 0.0) ||
+        (fo.train_precision != MCUBES_FP32 && fo.train_precision != MCUBES_BF16) ||
         fo.round_samples < 1 || fo.round_samples > ((int64_t)1 << 31) || !(fo.lr > 0.0) ||
         !(fo.round_lr > 0.0) || (fo.precision != MCUBES_FP32 && fo.precision != MCUBES_BF16))
         return fail(MCUBES_E_ARG, "invalid flow options");
@@ -410,7 +439,8 @@ int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int6
         double losses[1024];
         const int ep = fo.epochs < 1024 ? fo.epochs : 1024;
         if (ep > 0) {
-            FI_CALL(mcubes_flow_train(F, dx, dw, rows, ep, fo.batch, fo.lr, losses, opt.stream));
+            FI_CALL(mcubes_flow_train(F, fo.train_precision, dx, dw, rows, ep, fo.batch, fo.lr,
+                                      losses, opt.stream));
             R.final_loss = losses[ep - 1];
         }
         const int rep_ep = fo.round_epochs < 1024 ? fo.round_epochs : 1024;
@@ -420,8 +450,9 @@ int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int6
             if (tail && fo.tail_power != 1.0)
                 FI_CHECK(launch_pow_weights(dw, fo.round_samples, fo.tail_power, s), "weights launch");
             if (rep_ep > 0) {
-                FI_CALL(mcubes_flow_train(F, dx, dw, fo.round_samples, rep_ep, fo.batch,
-                                          tail ? fo.tail_lr : fo.round_lr, losses, opt.stream));
+                FI_CALL(mcubes_flow_train(F, fo.train_precision, dx, dw, fo.round_samples, rep_ep,
+                                          fo.batch, tail ? fo.tail_lr : fo.round_lr, losses,
+                                          opt.stream));
                 R.final_loss = losses[rep_ep - 1];
             }
         }

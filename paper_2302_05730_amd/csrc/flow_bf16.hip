@@ -172,18 +172,18 @@ __device__ __forceinline__ float sample_wave(const bf16x8 *__restrict__ frags,
                         F[(OFF_G3 + t * G3K + ks) * 64], h2[ks], out[sb][t], 0, 0, 0);
         }
         // hand every lane its own sample: lanes 32..63 of block 0 <-> lanes
-        // 0..31 of block 1; then lane s holds the features of lane half 0 in
-        // own[0] and of lane half 1 in own[1]
-        f32x16 own[2][G3T];
+        // 0..31 of block 1; then (in place) lane s holds the features of lane
+        // half 0 in out[0] and of lane half 1 in out[1]
 #pragma unroll
         for (int t = 0; t < G3T; ++t)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const auto sw = __builtin_amdgcn_permlane32_swap(
                     __float_as_uint(out[0][t][r]), __float_as_uint(out[1][t][r]), false, false);
-                own[0][t][r] = __uint_as_float(sw[0]) + bias[l * BIAS + BOFF_3 + t * 32 + r];
-                own[1][t][r] = __uint_as_float(sw[1]) + bias[l * BIAS + BOFF_3 + t * 32 + 16 + r];
+                out[0][t][r] = __uint_as_float(sw[0]) + bias[l * BIAS + BOFF_3 + t * 32 + r];
+                out[1][t][r] = __uint_as_float(sw[1]) + bias[l * BIAS + BOFF_3 + t * 32 + 16 + r];
             }
+        f32x16(&own)[2][G3T] = out;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             float raw[RAW];
@@ -307,6 +307,318 @@ __global__ __launch_bounds__(256) void flow_vsample_bf16_kernel(const bf16x8 *__
     }
 }
 
+// ---------------------------------------------------------------------
+// Training on the matrix cores.  The backward pass runs the three products
+// through the transposed weights in the same orientation (features = rows,
+// samples = columns): dh2 = W3 draw, dh1 = W2 d2, de = W1 d1.  Their weight
+// fragments: through W3, 2 row tiles (hidden units) x 7 K steps over the 99
+// spline parameters (natural order, padded to 112); through W2, 2 x 4; and
+// through W1, 3 row tiles (one-blob inputs) x 4; the last two in the K order
+// of the accumulator registers, like the forward products.
+constexpr int B3T = 2, B3K = 7, B2T = 2, B2K = 4, B1T = 3, B1K = 4;
+constexpr int OFF_B3F = 0, OFF_B2F = OFF_B3F + B3T * B3K, OFF_B1F = OFF_B2F + B2T * B2K;
+constexpr int BFRAGS = OFF_B1F + B1T * B1K;  // 34
+
+__global__ void pack_bwd_kernel(const float *__restrict__ theta, bf16x8 *__restrict__ frags) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= L * BFRAGS * 64) return;
+    const int lane = gid % 64, fr = (gid / 64) % BFRAGS, l = gid / (64 * BFRAGS);
+    const float *P = theta + l * LP;
+    const int row = lane % 32, h = lane / 32;
+    float v[8];
+    if (fr < OFF_B2F) {
+        const int t = fr / B3K, ks = fr % B3K, i = 32 * t + row;
+        for (int e = 0; e < 8; ++e) {
+            const int k = 16 * ks + 8 * h + e;
+            v[e] = k < OUT ? P[OFF_W3 + i * OUT + k] : 0.0f;
+        }
+    } else if (fr < OFF_B1F) {
+        const int q = fr - OFF_B2F, t = q / B2K, ks = q % B2K, i = 32 * t + row;
+        for (int e = 0; e < 8; ++e)
+            v[e] = P[OFF_W2 + i * HID + acc_feature(ks / 2, 8 * (ks % 2) + e, h)];
+    } else {
+        const int q = fr - OFF_B1F, t = q / B1K, ks = q % B1K, r = 32 * t + row;
+        for (int e = 0; e < 8; ++e)
+            v[e] = P[OFF_W1 + r * HID + acc_feature(ks / 2, 8 * (ks % 2) + e, h)];
+    }
+    frags[gid] = pack8(v);
+}
+
+// lane < 32 gets (a of lane, a of lane + 32), lane >= 32 (b of lane - 32,
+// b of lane), per 32-bit word
+__device__ __forceinline__ void swap_halves(const bf16x8 &a, const bf16x8 &b, bf16x8 &lo,
+                                            bf16x8 &hi) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 ua = __builtin_bit_cast(u32x4, a), ub = __builtin_bit_cast(u32x4, b);
+    u32x4 r0, r1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const auto sw = __builtin_amdgcn_permlane32_swap(ua[i], ub[i], false, false);
+        r0[i] = sw[0];
+        r1[i] = sw[1];
+    }
+    lo = __builtin_bit_cast(bf16x8, r0);
+    hi = __builtin_bit_cast(bf16x8, r1);
+}
+
+// Forward and backward pass of the weighted negative log-likelihood, 64
+// samples per wave (lane = sample for the per-sample work), the nine
+// products per layer on the matrix cores.  Writes the same scratch fields
+// as the FP32 form (activations and deltas FP32, taken from the FP32
+// accumulators) for the weight-gradient kernels; loss += sum c log q with
+// c = -w / sum w.  Lanes past n work on a copy of the last sample with
+// c = 0 and store nothing.
+__global__ __launch_bounds__(64) void train_bf16_kernel(
+    const bf16x8 *__restrict__ frags, const bf16x8 *__restrict__ bfrags,
+    const float *__restrict__ bias, const double *__restrict__ x, const double *__restrict__ w,
+    int64_t n, const double *__restrict__ wsum, float *__restrict__ scratch,
+    double *__restrict__ loss) {
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int64_t wid = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, h = lane >> 5, col = lane & 31;
+    double lsum = 0.0;
+    for (int64_t base = wid * 64; base < n; base += waves * 64) {
+        const bool live = base + lane < n;
+        const int64_t s = live ? base + lane : n - 1;
+        // the sample of column col in block sb, and whether it is real
+        int64_t cs[2];
+        bool clive[2];
+#pragma unroll
+        for (int sb = 0; sb < 2; ++sb) {
+            clive[sb] = base + 32 * sb + col < n;
+            cs[sb] = clive[sb] ? base + 32 * sb + col : n - 1;
+        }
+        float u[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) u[j] = (float)x[s * D + j];
+        const float c = live ? (float)(-w[s] / *wsum) : 0.0f;
+        float lq = 0.0f;
+        // ---- forward, x -> z
+#pragma unroll 1
+        for (int l = 0; l < L; ++l) {
+            float *sc = scratch + (int64_t)l * FS * n;
+            if (live) {
+#pragma unroll
+                for (int j = 0; j < D; ++j) sc[(FS_U + j) * n + s] = u[j];
+            }
+            const bf16x8 *Fr = frags + (size_t)l * FRAGS * 64 + lane;
+            const float *Bs = bias + l * BIAS + h * 16;
+            f32x16 out[2][G3T];
+#pragma unroll
+            for (int sb = 0; sb < 2; ++sb) {
+                float ua[NA];
+#pragma unroll
+                for (int a = 0; a < NA; ++a) ua[a] = __shfl(getu(u, a_idx(l, a)), 32 * sb + col);
+                f32x16 acc1[G1T];
+#pragma unroll
+                for (int t = 0; t < G1T; ++t) acc1[t] = f32x16{};
+#pragma unroll
+                for (int ks = 0; ks < G1K; ++ks) {
+                    float e[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) e[i] = blob(ua[ks >> 1], 16 * (ks & 1) + 8 * h + i);
+                    const bf16x8 bop = pack8(e);
+#pragma unroll
+                    for (int t = 0; t < G1T; ++t)
+                        acc1[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            Fr[(OFF_G1 + t * G1K + ks) * 64], bop, acc1[t], 0, 0, 0);
+                }
+                bf16x8 h1[G2K];
+#pragma unroll
+                for (int ks = 0; ks < G2K; ++ks) {
+                    float v[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        const int r = 8 * (ks % 2) + i;
+                        v[i] = fmaxf(acc1[ks / 2][r] + Bs[BOFF_1 + (ks / 2) * 32 + r], 0.0f);
+                        if (clive[sb]) sc[(FS_H1 + acc_feature(ks / 2, r, h)) * n + cs[sb]] = v[i];
+                    }
+                    h1[ks] = pack8(v);
+                }
+                f32x16 acc2[G2T];
+#pragma unroll
+                for (int t = 0; t < G2T; ++t) acc2[t] = f32x16{};
+#pragma unroll
+                for (int ks = 0; ks < G2K; ++ks)
+#pragma unroll
+                    for (int t = 0; t < G2T; ++t)
+                        acc2[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            Fr[(OFF_G2 + t * G2K + ks) * 64], h1[ks], acc2[t], 0, 0, 0);
+                bf16x8 h2[G3K];
+#pragma unroll
+                for (int ks = 0; ks < G3K; ++ks) {
+                    float v[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        const int r = 8 * (ks % 2) + i;
+                        v[i] = fmaxf(acc2[ks / 2][r] + Bs[BOFF_2 + (ks / 2) * 32 + r], 0.0f);
+                        if (clive[sb]) sc[(FS_H2 + acc_feature(ks / 2, r, h)) * n + cs[sb]] = v[i];
+                    }
+                    h2[ks] = pack8(v);
+                }
+#pragma unroll
+                for (int t = 0; t < G3T; ++t) out[sb][t] = f32x16{};
+#pragma unroll
+                for (int ks = 0; ks < G3K; ++ks)
+#pragma unroll
+                    for (int t = 0; t < G3T; ++t)
+                        out[sb][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            Fr[(OFF_G3 + t * G3K + ks) * 64], h2[ks], out[sb][t], 0, 0, 0);
+            }
+#pragma unroll
+            for (int t = 0; t < G3T; ++t)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const auto sw = __builtin_amdgcn_permlane32_swap(
+                        __float_as_uint(out[0][t][r]), __float_as_uint(out[1][t][r]), false, false);
+                    out[0][t][r] = __uint_as_float(sw[0]) + bias[l * BIAS + BOFF_3 + t * 32 + r];
+                    out[1][t][r] = __uint_as_float(sw[1]) + bias[l * BIAS + BOFF_3 + t * 32 + 16 + r];
+                }
+            f32x16(&own)[2][G3T] = out;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                float raw[RAW];
+#pragma unroll
+                for (int k = 0; k < RAW; ++k) {
+                    const int f = b * RAW + k, t = f / 32, ww = f % 32;
+                    raw[k] = own[(ww / 4) % 2][t][4 * (ww / 8) + ww % 4];
+                    if (live) sc[(FS_DOUT + f) * n + s] = raw[k];
+                }
+                Spline sp;
+                spline_setup(raw, sp);
+                const int j = b_idx(l, b);
+                float v, pdf;
+                spline_forward(sp, getu(u, j), v, pdf);
+                setu(u, j, v);
+                lq += logf(pdf);
+            }
+        }
+        lsum += live ? (double)c * (double)lq : 0.0;
+        // ---- backward; g = dL/du at the output of the current layer
+        float g[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) g[j] = 0.0f;
+#pragma unroll 1
+        for (int l = L - 1; l >= 0; --l) {
+            float *sc = scratch + (int64_t)l * FS * n;
+            float uin[D], gprev[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                uin[j] = sc[(FS_U + j) * n + s];
+                gprev[j] = g[j];
+            }
+            // spline deltas of the own sample, natural order padded to 112
+            float gr[16 * B3K];
+#pragma unroll
+            for (int k = NB * RAW; k < 16 * B3K; ++k) gr[k] = 0.0f;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                float raw[RAW];
+#pragma unroll
+                for (int k = 0; k < RAW; ++k) raw[k] = sc[(FS_DOUT + b * RAW + k) * n + s];
+                Spline sp;
+                spline_setup(raw, sp);
+                const int j = b_idx(l, b);
+                const float ub = getu(uin, j);
+                float y, pdf, gu, graw[RAW];
+                spline_forward(sp, ub, y, pdf);
+                spline_backward(sp, ub, getu(g, j), c / pdf, graw, gu);
+                setu(gprev, j, gu);
+#pragma unroll
+                for (int k = 0; k < RAW; ++k) {
+                    gr[b * RAW + k] = graw[k];
+                    if (live) sc[(FS_DOUT + b * RAW + k) * n + s] = graw[k];
+                }
+            }
+            // operands of the two sample blocks
+            bf16x8 X[2][B3K];
+#pragma unroll
+            for (int ks = 0; ks < B3K; ++ks)
+                swap_halves(pack8(&gr[16 * ks]), pack8(&gr[16 * ks + 8]), X[0][ks], X[1][ks]);
+            const bf16x8 *Br = bfrags + (size_t)l * BFRAGS * 64 + lane;
+            float tot[NA];
+#pragma unroll
+            for (int sb = 0; sb < 2; ++sb) {
+                // through W3 and the second ReLU
+                f32x16 a3[B3T];
+#pragma unroll
+                for (int t = 0; t < B3T; ++t) a3[t] = f32x16{};
+#pragma unroll
+                for (int ks = 0; ks < B3K; ++ks)
+#pragma unroll
+                    for (int t = 0; t < B3T; ++t)
+                        a3[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            Br[(OFF_B3F + t * B3K + ks) * 64], X[sb][ks], a3[t], 0, 0, 0);
+                bf16x8 Y[B2K];
+#pragma unroll
+                for (int ks = 0; ks < B2K; ++ks) {
+                    float v[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        const int r = 8 * (ks % 2) + i, f = acc_feature(ks / 2, r, h);
+                        const float hv = sc[(FS_H2 + f) * n + cs[sb]];
+                        v[i] = hv > 0.0f ? a3[ks / 2][r] : 0.0f;
+                        if (clive[sb]) sc[(FS_D2 + f) * n + cs[sb]] = v[i];
+                    }
+                    Y[ks] = pack8(v);
+                }
+                // through W2 and the first ReLU
+                f32x16 a2[B2T];
+#pragma unroll
+                for (int t = 0; t < B2T; ++t) a2[t] = f32x16{};
+#pragma unroll
+                for (int ks = 0; ks < B2K; ++ks)
+#pragma unroll
+                    for (int t = 0; t < B2T; ++t)
+                        a2[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            Br[(OFF_B2F + t * B2K + ks) * 64], Y[ks], a2[t], 0, 0, 0);
+                bf16x8 Z[B1K];
+#pragma unroll
+                for (int ks = 0; ks < B1K; ++ks) {
+                    float v[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        const int r = 8 * (ks % 2) + i, f = acc_feature(ks / 2, r, h);
+                        const float hv = sc[(FS_H1 + f) * n + cs[sb]];
+                        v[i] = hv > 0.0f ? a2[ks / 2][r] : 0.0f;
+                        if (clive[sb]) sc[(FS_D1 + f) * n + cs[sb]] = v[i];
+                    }
+                    Z[ks] = pack8(v);
+                }
+                // through W1 to the one-blob inputs, then through the encoding:
+                // row tile t holds the 32 bumps of conditioning coordinate t
+#pragma unroll
+                for (int t = 0; t < B1T; ++t) {
+                    f32x16 a1 = f32x16{};
+#pragma unroll
+                    for (int ks = 0; ks < B1K; ++ks)
+                        a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            Br[(OFF_B1F + t * B1K + ks) * 64], Z[ks], a1, 0, 0, 0);
+                    const float ux = __shfl(getu(uin, a_idx(l, t)), 32 * sb + col);
+                    float part = 0.0f;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int k = acc_feature(0, r, h);
+                        const float tt = (ux - ((float)k + 0.5f) * (1.0f / BLOBS)) * (float)BLOBS;
+                        part = __fmaf_rn(a1[r], -expf(-0.5f * tt * tt) * tt * (float)BLOBS, part);
+                    }
+                    part += __shfl_xor(part, 32);
+                    if (sb == h) tot[t] = part;
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < NA; ++a) {
+                const int j = a_idx(l, a);
+                setu(gprev, j, getu(gprev, j) + tot[a]);
+            }
+#pragma unroll
+            for (int j = 0; j < D; ++j) g[j] = gprev[j];
+        }
+    }
+    const double v = wave_sum(lsum);
+    if (lane == 0) unsafeAtomicAdd(loss, v);
+}
+
 template <int F>
 hipError_t launch_bf16_f(const void *frags, const float *bias, const VsArgs &A,
                          uint32_t stream_word, double *partials, int blocks, hipStream_t s) {
@@ -324,6 +636,27 @@ hipError_t launch_flow_pack_bf16(const float *theta, void *frags, float *bias, h
     const int n = L * FRAGS * 64;
     hipLaunchKernelGGL(pack_kernel, dim3((n + 255) / 256), dim3(256), 0, s, theta,
                        (bf16x8 *)frags, bias);
+    return hipGetLastError();
+}
+
+int64_t flow_bf16_bwd_frag_bytes() { return (int64_t)L * BFRAGS * 64 * sizeof(bf16x8); }
+
+hipError_t launch_flow_train_bf16(const float *theta, void *frags, void *bfrags, float *bias,
+                                  const double *x, const double *w, int64_t n, const double *wsum,
+                                  float *scratch, double *loss, int cus, hipStream_t s) {
+    const int nf = L * FRAGS * 64, nb = L * BFRAGS * 64;
+    hipLaunchKernelGGL(pack_kernel, dim3((nf + 255) / 256), dim3(256), 0, s, theta,
+                       (bf16x8 *)frags, bias);
+    hipLaunchKernelGGL(pack_bwd_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, theta,
+                       (bf16x8 *)bfrags);
+    // one single-wave workgroup per 64 samples (spread over every CU), at
+    // most 8 per CU
+    int64_t blocks = (n + 63) / 64;
+    const int64_t cap = 8 * (int64_t)(cus > 0 ? cus : 256);
+    if (blocks > cap) blocks = cap;
+    hipLaunchKernelGGL(train_bf16_kernel, dim3((unsigned)blocks), dim3(64), 0, s,
+                       (const bf16x8 *)frags, (const bf16x8 *)bfrags, bias, x, w, n, wsum, scratch,
+                       loss);
     return hipGetLastError();
 }
 

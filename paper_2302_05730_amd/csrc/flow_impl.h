@@ -31,6 +31,13 @@ constexpr int LP = OFF_B3 + OUT;  // parameters per layer
 constexpr int PARAMS = L * LP;
 static_assert(PARAMS == MCUBES_FLOW_PARAMS, "flow parameter count");
 
+// Per-sample training scratch, FP32, one block of FS fields per layer, each
+// field n floats (sample contiguous): the layer's input u (6), h1 and h2
+// (64 each), the 99 spline parameters (replaced by their deltas in the
+// backward pass) and the deltas after the second and the first ReLU.
+constexpr int FS_U = 0, FS_H1 = FS_U + D, FS_H2 = FS_H1 + HID, FS_DOUT = FS_H2 + HID;
+constexpr int FS_D2 = FS_DOUT + OUT, FS_D1 = FS_D2 + HID, FS = FS_D1 + HID;
+
 // coordinate t of A_l and of B_l
 __device__ __forceinline__ int a_idx(int l, int t) {
     return l == 0 ? t : (l == 1 ? 3 + t : (l == 2 ? 2 * t : 2 * t + 1));

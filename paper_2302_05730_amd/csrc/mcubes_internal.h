@@ -140,10 +140,20 @@ int64_t flow_scratch_floats(int64_t n);
 int64_t flow_transposed_floats();
 // w[i] <- w[i]^power (training weights of the tail rounds)
 hipError_t launch_pow_weights(double *w, int64_t n, double power, hipStream_t s);
-// thetaT: flow_transposed_floats() floats, rewritten from theta on each call
-hipError_t launch_flow_train(const float *theta, float *thetaT, const double *x, const double *w,
-                             int64_t n, double *wsum, float *scratch, float *grad, double *loss,
-                             hipStream_t s);
+// One training step's passes: wsum <- sum of the n weights; the forward and
+// backward pass of the weighted NLL (loss += its value, per-sample fields in
+// scratch; FP32 form: thetaT, flow_transposed_floats() floats, is rewritten
+// from theta; BF16 form: the forward and backward fragments are repacked
+// from theta); then the weight gradients from the scratch fields.
+hipError_t launch_flow_wsum(const double *w, int64_t n, double *wsum, hipStream_t s);
+hipError_t launch_flow_train_fp32(const float *theta, float *thetaT, const double *x,
+                                  const double *w, int64_t n, const double *wsum, float *scratch,
+                                  double *loss, hipStream_t s);
+hipError_t launch_flow_train_bf16(const float *theta, void *frags, void *bfrags, float *bias,
+                                  const double *x, const double *w, int64_t n, const double *wsum,
+                                  float *scratch, double *loss, int cus, hipStream_t s);
+hipError_t launch_flow_wgrad(const float *scratch, int64_t n, float *grad, hipStream_t s);
+int64_t flow_bf16_bwd_frag_bytes();
 hipError_t launch_flow_adam(float *theta, float *m, float *v, const float *grad, float lr,
                             float beta1, float beta2, float eps, float c1, float c2,
                             hipStream_t s);
