@@ -316,11 +316,11 @@ __global__ __launch_bounds__(CT, 4) void train_kernel(const float *__restrict__ 
 // and deltas staged in LDS sample-major 32 samples at a time; the batch is
 // cut into slices of ks samples (blockIdx.y) whose partial sums land in
 // part[slice][parameter] and are added in slice order afterwards, so the
-// result does not depend on scheduling.
+// result does not depend on scheduling.  The tiles whose rows start at 0
+// also sum their delta columns over the slice: the bias gradients.
 constexpr int WT = 64, WKC = 32, WPAD = WT + 4;
 constexpr int TILES_L = 5;  // W1 rows 0-63 | W1 rows 64-95 | W2 | W3 cols 0-63 | W3 cols 64-98
 constexpr int kMaxSlices = 64;
-constexpr int NBIAS = HID + HID + OUT;
 
 __global__ __launch_bounds__(256) void wgrad_kernel(const float *__restrict__ scratch, int64_t n,
                                                     int64_t ks, float *__restrict__ part) {
@@ -340,7 +340,8 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const float *__restrict__ sc
     const float *sc = scratch + (int64_t)l * FS * n;
     const int bfield = mat == 0 ? FS_D1 : (mat == 1 ? FS_D2 : FS_DOUT);
     const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
-    float acc[4][4];
+    const bool bias_tile = r0 == 0 && ty == 0;  // 16 threads, 4 columns each
+    float acc[4][4], bsum[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -377,9 +378,24 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const float *__restrict__ sc
 #pragma unroll
                 for (int j = 0; j < 4; ++j) acc[i][j] = __fmaf_rn(av[i], bv[j], acc[i][j]);
         }
+        if (bias_tile) {
+            for (int ss = 0; ss < WKC; ++ss) {
+                const float4 b = *reinterpret_cast<const float4 *>(&Bs[ss][4 * tx]);
+                bsum[0] += b.x;
+                bsum[1] += b.y;
+                bsum[2] += b.z;
+                bsum[3] += b.w;
+            }
+        }
         __syncthreads();
     }
     float *G = part + (int64_t)blockIdx.y * PARAMS + l * LP;
+    if (bias_tile) {
+        const int boff = mat == 0 ? OFF_B1 : (mat == 1 ? OFF_B2 : OFF_B3);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (4 * tx + j < cols) G[boff + c0 + 4 * tx + j] = bsum[j];
+    }
     const int off = mat == 0 ? OFF_W1 : (mat == 1 ? OFF_W2 : OFF_W3);
     const int ld = mat == 2 ? OUT : HID;
 #pragma unroll
@@ -394,44 +410,14 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const float *__restrict__ sc
     }
 }
 
-__device__ __forceinline__ bool is_bias(int i) {
-    const int o = i % LP;
-    return (o >= OFF_B1 && o < OFF_W2) || (o >= OFF_B2 && o < OFF_W3) || o >= OFF_B3;
-}
-
-// grad[i] = sum over the slices, in slice order, for the weight entries
+// grad[i] = sum over the slices, in slice order
 __global__ void wgrad_sum_kernel(const float *__restrict__ part, int slices,
                                  float *__restrict__ grad) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= PARAMS || is_bias(i)) return;
+    if (i >= PARAMS) return;
     float a = 0.0f;
     for (int k = 0; k < slices; ++k) a += part[(int64_t)k * PARAMS + i];
     grad[i] = a;
-}
-
-// bias gradients: the sum over the batch of one delta field per workgroup
-__global__ __launch_bounds__(256) void bias_grad_kernel(const float *__restrict__ scratch,
-                                                        int64_t n, float *__restrict__ grad) {
-    __shared__ float red[256];
-    const int l = blockIdx.x / NBIAS, c = blockIdx.x % NBIAS;
-    int field, dst;
-    if (c < HID) {
-        field = FS_D1 + c; dst = OFF_B1 + c;
-    } else if (c < 2 * HID) {
-        field = FS_D2 + c - HID; dst = OFF_B2 + c - HID;
-    } else {
-        field = FS_DOUT + c - 2 * HID; dst = OFF_B3 + c - 2 * HID;
-    }
-    const float *row = scratch + ((int64_t)l * FS + field) * n;
-    float a = 0.0f;
-    for (int64_t s = threadIdx.x; s < n; s += 256) a += row[s];
-    red[threadIdx.x] = a;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) grad[l * LP + dst] = red[0];
 }
 
 __global__ void pow_kernel(double *__restrict__ w, int64_t n, double power) {
@@ -701,7 +687,6 @@ hipError_t launch_flow_wgrad(const float *scratch_in, int64_t n, float *grad, hi
                        n, ks, part);
     hipLaunchKernelGGL(wgrad_sum_kernel, dim3((PARAMS + 255) / 256), dim3(256), 0, s, part,
                        (int)slices, grad);
-    hipLaunchKernelGGL(bias_grad_kernel, dim3(L * NBIAS), dim3(256), 0, s, scratch, n, grad);
     return hipGetLastError();
 }
 

@@ -1,5 +1,6 @@
-// Flow sampling on the BF16 matrix cores (gfx950 v_mfma_f32_32x32x16_bf16,
-// FP32 accumulation): the proposal's hot loop.
+// The flow on the BF16 matrix cores (gfx950 v_mfma_f32_32x32x16_bf16, FP32
+// accumulation): sampling, the flow-mapped iteration (the proposal's hot
+// loop) and the forward and backward pass of training.
 //
 // A wave carries 64 samples, one per lane for the per-sample work (Philox,
 // spline inversion, integrand), and runs each conditioner as three chained
