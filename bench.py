@@ -195,7 +195,8 @@ def bench_flow(mc, ncall, plain_iters=50):
     t_b = time.perf_counter()
     plain = {"seconds": round(t_b - t_a, 4), "iterations": r["iterations"],
              "converged": r["converged"], "estimate": r["estimate"], "error": r["error"],
-             "chi2_dof": r["chi2_dof"], "true_rel_error": abs(r["estimate"] - 1.0)}
+             "chi2_dof": r["chi2_dof"], "true_rel_error": abs(r["estimate"] - 1.0),
+             "error_in_sigma": abs(r["estimate"] - 1.0) / r["error"] if r["error"] else None}
     # the plain method's own error bar would need (error / 1e-3)^2 times the iterations
     plain["iterations_for_claimed_1e-3"] = (r["iterations"] * (r["error"] / 1e-3) ** 2
                                             if r["error"] else None)
@@ -217,6 +218,8 @@ def bench_flow(mc, ncall, plain_iters=50):
             "proposal_ms": round(rep["flow_ms"], 2), "iterations": res["iterations"],
             "converged": res["converged"], "estimate": res["estimate"], "error": res["error"],
             "chi2_dof": res["chi2_dof"], "true_rel_error": abs(res["estimate"] - 1.0),
+            "error_in_sigma": (abs(res["estimate"] - 1.0) / res["error"]
+                               if res["error"] else None),
             "used_flow": rep["used_flow"], "last_plain_var": rep["last_plain_var"],
             "first_flow_var": rep["first_flow_var"],
             "training_samples_per_s": trained / (rep["train_ms"] * 1e-3),

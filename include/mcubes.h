@@ -250,9 +250,8 @@ int mcubes_microbench(int kind, int family, const double *params, int dim,
  * iteration counter, all reading the iteration number and the per-integrand
  * "done" flags from device memory; the sequence is captured once in a HIP
  * graph and replayed.  An integrand that converges (or produces a
- * non-finite estimate) is marked done on the device and no longer sampled;
- * when enough of the planned work has finished the library re-splits the
- * remaining work and captures a new graph.
+ * non-finite estimate) is marked done on the device and no longer sampled
+ * (its tiles return at once); the plan stays fixed for the whole call.
  *
  * The batch owns its device memory (grids, bins, states: about
  * 8 * (2 * sum dim_i * (nbins + 1) + n * MCUBES_STATE_LEN) bytes plus the
@@ -285,7 +284,7 @@ typedef struct {
     int64_t device_bytes;   /* device memory held by the batch */
     /* the last mcubes_batch_integrate call: */
     int32_t last_iterations;  /* iterations run (the most any integrand ran) */
-    int32_t last_replans;     /* times the work was re-split */
+    int32_t last_replans;     /* always 0: the work is not re-split during a call */
     int64_t last_samples;     /* samples evaluated, all integrands */
     double last_ms;           /* wall time of its iteration loop (HIP events) */
 } mcubes_batch_info;
@@ -410,7 +409,8 @@ int mcubes_flow_sample(mcubes_flow *flow, int precision, const double *d_z, int6
  * pass in FP32 on the vector units; MCUBES_BF16 runs the nine products per
  * layer on the matrix cores (BF16 weights and product inputs, FP32
  * accumulation; splines FP32), which makes the gradient approximate.  The
- * weight gradients (sums over the samples) are FP32 in both. */
+ * weight gradients (sums over the samples) are FP32 in both.  Enqueued on
+ * `stream`; nothing is read back. */
 int mcubes_flow_loss_grad(mcubes_flow *flow, int precision, const double *d_x, const double *d_w,
                           int64_t n, double *d_grad, double *d_loss, void *stream);
 /* One Adam step (bias-corrected; the flow counts the steps) with the kept gradient. */

@@ -99,7 +99,7 @@ namespace {
 
 void drop_graphs(mcubes_batch *B) {
     for (auto &e : B->exec) {
-        if (e) hipGraphExecDestroy(e);
+        if (e) (void)hipGraphExecDestroy(e);
         e = nullptr;
     }
 }
@@ -108,24 +108,24 @@ void release(mcubes_batch *B) {
     if (!B) return;
     drop_graphs(B);
     for (auto &e : B->ev)
-        if (e) hipEventDestroy(e);
+        if (e) (void)hipEventDestroy(e);
     for (auto &e : B->join)
-        if (e) hipEventDestroy(e);
-    if (B->fork) hipEventDestroy(B->fork);
+        if (e) (void)hipEventDestroy(e);
+    if (B->fork) (void)hipEventDestroy(B->fork);
     for (auto &q : B->side)
-        if (q) hipStreamDestroy(q);
-    if (B->stream) hipStreamDestroy(B->stream);
-    hipFree(B->d_items);
-    hipFree(B->d_grids);
-    hipFree(B->d_bins);
-    hipFree(B->d_est);
-    hipFree(B->d_states);
-    hipFree(B->d_done);
-    hipFree(B->d_iter);
-    hipFree(B->d_axes);
-    hipFree(B->d_tiles);
-    hipFree(B->d_partials);
-    if (B->h_done) hipHostFree(B->h_done);
+        if (q) (void)hipStreamDestroy(q);
+    if (B->stream) (void)hipStreamDestroy(B->stream);
+    (void)hipFree(B->d_items);
+    (void)hipFree(B->d_grids);
+    (void)hipFree(B->d_bins);
+    (void)hipFree(B->d_est);
+    (void)hipFree(B->d_states);
+    (void)hipFree(B->d_done);
+    (void)hipFree(B->d_iter);
+    (void)hipFree(B->d_axes);
+    (void)hipFree(B->d_tiles);
+    (void)hipFree(B->d_partials);
+    if (B->h_done) (void)hipHostFree(B->h_done);
     delete B;
 }
 
@@ -312,8 +312,8 @@ int build_plan(mcubes_batch *B, const std::vector<char> &active) {
         it.part_end = tiles[t].partial + 1;
     }
     if (tiles.size() > B->cap_tiles) {
-        hipFree(B->d_tiles);
-        hipFree(B->d_partials);
+        (void)hipFree(B->d_tiles);
+        (void)hipFree(B->d_partials);
         B->d_tiles = nullptr;
         B->d_partials = nullptr;
         const size_t cap = tiles.size() + tiles.size() / 4 + 64;
@@ -385,12 +385,12 @@ int capture(mcubes_batch *B, bool frozen, double rel_tol) {
     const hipError_t el = enqueue_iteration(B, frozen, rel_tol, B->stream);
     e = hipStreamEndCapture(B->stream, &graph);
     if (el != hipSuccess) {
-        if (graph) hipGraphDestroy(graph);
+        if (graph) (void)hipGraphDestroy(graph);
         return hip_fail(el, "batch iteration launch (capture)");
     }
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
     e = hipGraphInstantiate(&B->exec[frozen ? 1 : 0], graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);
     if (e != hipSuccess) {
         B->exec[frozen ? 1 : 0] = nullptr;
         return hip_fail(e, "hipGraphInstantiate");
@@ -559,7 +559,12 @@ int mcubes_batch_create(const mcubes_batch_item *items, int n, uint64_t seed,
 }
 
 void mcubes_batch_destroy(mcubes_batch *B) {
-    if (B && B->stream) hipStreamSynchronize(B->stream);
+    if (B) {
+        // nothing of this batch may still run when its memory goes
+        if (B->stream) (void)hipStreamSynchronize(B->stream);
+        for (auto &q : B->side)
+            if (q) (void)hipStreamSynchronize(q);
+    }
     release(B);
 }
 
@@ -674,8 +679,8 @@ int mcubes_batch_autotune(mcubes_batch *B) {
         std::vector<BatchTile> tiles;
         split_class(B, c, shares, tiles);
         if (tiles.size() > cap) {
-            hipFree(d_tiles);
-            hipFree(d_part);
+            (void)hipFree(d_tiles);
+            (void)hipFree(d_part);
             d_tiles = nullptr;
             d_part = nullptr;
             cap = tiles.size() + tiles.size() / 4 + 64;
@@ -755,9 +760,9 @@ int mcubes_batch_autotune(mcubes_batch *B) {
         cf.tuned_ms = best_ms;
         cf.default_ms = default_ms;
     }
-    hipFree(d_items);
-    hipFree(d_tiles);
-    hipFree(d_part);
+    (void)hipFree(d_items);
+    (void)hipFree(d_tiles);
+    (void)hipFree(d_part);
     if (rc != MCUBES_OK) return rc;
     const int saved = B->forced_block;
     B->forced_block = 0;
@@ -871,7 +876,8 @@ int mcubes_batch_integrate(mcubes_batch *B, int itmax, double rel_tol, int use_g
     if (e == hipSuccess)
         e = launch_batch_reset(B->d_states, (int64_t)n * MCUBES_STATE_LEN, B->d_done, n, B->d_iter, s);
     if (e != hipSuccess) return hip_fail(e, "batch reset");
-    int replans = 0, iterations = 0;
+    const int replans = 0;
+    int iterations = 0;
     int64_t samples = 0, running = 0;
     for (int i = 0; i < n; ++i) running += B->m[i] * B->p[i];
     e = hipEventRecord(B->ev[0], s);
@@ -896,18 +902,12 @@ int mcubes_batch_integrate(mcubes_batch *B, int itmax, double rel_tol, int use_g
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "batch flags");
         if (B->h_done[n] == 0u) break;
-        // re-split the remaining work once a noticeable share has finished
+        // the tiles of finished integrands return at once; the plan (and the
+        // captured graph) stays as it is for the whole call
         int64_t left = 0;
-        for (int i = 0; i < n; ++i) {
-            active[i] = B->h_done[i] == 0u;
-            if (active[i]) left += B->m[i] * B->p[i];
-        }
+        for (int i = 0; i < n; ++i)
+            if (B->h_done[i] == 0u) left += B->m[i] * B->p[i];
         running = left;
-        if (t + 1 < itmax && left < B->planned_samples - B->planned_samples / 50) {
-            rc = build_plan(B, active);
-            if (rc != MCUBES_OK) return rc;
-            ++replans;
-        }
     }
     e = hipEventRecord(B->ev[1], s);
     if (e == hipSuccess) e = hipEventSynchronize(B->ev[1]);

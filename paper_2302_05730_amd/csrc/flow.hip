@@ -420,6 +420,11 @@ __global__ void wgrad_sum_kernel(const float *__restrict__ part, int slices,
     grad[i] = a;
 }
 
+__global__ void widen_kernel(const float *__restrict__ in, int64_t n, double *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (double)in[i];
+}
+
 __global__ void pow_kernel(double *__restrict__ w, int64_t n, double power) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) w[i] = pow(w[i], power);
@@ -687,6 +692,12 @@ hipError_t launch_flow_wgrad(const float *scratch_in, int64_t n, float *grad, hi
                        n, ks, part);
     hipLaunchKernelGGL(wgrad_sum_kernel, dim3((PARAMS + 255) / 256), dim3(256), 0, s, part,
                        (int)slices, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_flow_widen(const float *in, int64_t n, double *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(widen_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, n, out);
     return hipGetLastError();
 }
 

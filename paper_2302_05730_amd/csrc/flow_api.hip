@@ -33,17 +33,17 @@ constexpr int kVsBlocks = 2048;  // workgroups of the flow-mapped iteration (gri
 
 void release(mcubes_flow *F) {
     if (!F) return;
-    hipFree(F->d_theta);
-    hipFree(F->d_m);
-    hipFree(F->d_v);
-    hipFree(F->d_grad);
-    hipFree(F->d_thetaT);
-    hipFree(F->d_frags);
-    hipFree(F->d_bfrags);
-    hipFree(F->d_fbias);
-    hipFree(F->d_aux);
-    hipFree(F->d_part);
-    hipFree(F->d_scratch);
+    (void)hipFree(F->d_theta);
+    (void)hipFree(F->d_m);
+    (void)hipFree(F->d_v);
+    (void)hipFree(F->d_grad);
+    (void)hipFree(F->d_thetaT);
+    (void)hipFree(F->d_frags);
+    (void)hipFree(F->d_bfrags);
+    (void)hipFree(F->d_fbias);
+    (void)hipFree(F->d_aux);
+    (void)hipFree(F->d_part);
+    (void)hipFree(F->d_scratch);
     delete F;
 }
 
@@ -78,7 +78,7 @@ int check_n(int64_t n) {
 
 int ensure_scratch(mcubes_flow *F, int64_t n) {
     if (n <= F->scratch_n) return MCUBES_OK;
-    hipFree(F->d_scratch);
+    (void)hipFree(F->d_scratch);
     F->d_scratch = nullptr;
     F->scratch_n = 0;
     const size_t bytes = (size_t)flow_scratch_floats(n) * sizeof(float);
@@ -205,17 +205,8 @@ int mcubes_flow_loss_grad(mcubes_flow *F, int precision, const double *d_x, cons
     if (rc != MCUBES_OK) return rc;
     hipStream_t s = as_stream(stream);
     hipError_t e = train_step(F, precision, d_x, d_w, n, d_loss, s);
-    if (e == hipSuccess && d_grad) {
-        // widen the kept FP32 gradient for the caller
-        std::vector<float> h(flow::PARAMS);
-        e = hipMemcpyAsync(h.data(), F->d_grad, h.size() * sizeof(float), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e == hipSuccess) {
-            std::vector<double> g(h.begin(), h.end());
-            e = hipMemcpyAsync(d_grad, g.data(), g.size() * sizeof(double), hipMemcpyHostToDevice, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
-        }
-    }
+    // widen the kept FP32 gradient for the caller
+    if (e == hipSuccess && d_grad) e = launch_flow_widen(F->d_grad, flow::PARAMS, d_grad, s);
     return e == hipSuccess ? MCUBES_OK : hip_fail(e, "flow gradient");
 }
 
@@ -527,8 +518,8 @@ cleanup:
 #undef FI_CHECK
 #undef FI_CALL
     for (auto &x : ev)
-        if (x) hipEventDestroy(x);
-    hipFree(buf);
+        if (x) (void)hipEventDestroy(x);
+    (void)hipFree(buf);
     mcubes_plan_destroy(P);
     return rc;
 }

@@ -531,9 +531,9 @@ int mcubes_integrate(int family, const double *params, int dim, int64_t ncall, i
 cleanup:
 #undef MC_CHECK
 #undef MC_CALL
-    if (ev0) hipEventDestroy(ev0);
-    if (ev1) hipEventDestroy(ev1);
-    hipFree(buf);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    (void)hipFree(buf);
     mcubes_plan_destroy(P);
     return rc;
 }

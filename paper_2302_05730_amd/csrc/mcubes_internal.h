@@ -138,6 +138,8 @@ hipError_t launch_flow_sample(const float *theta, const double *z, int64_t n, do
                               double *logq, hipStream_t s);
 int64_t flow_scratch_floats(int64_t n);
 int64_t flow_transposed_floats();
+// out[i] <- (double)in[i]
+hipError_t launch_flow_widen(const float *in, int64_t n, double *out, hipStream_t s);
 // w[i] <- w[i]^power (training weights of the tail rounds)
 hipError_t launch_pow_weights(double *w, int64_t n, double power, hipStream_t s);
 // One training step's passes: wsum <- sum of the n weights; the forward and
