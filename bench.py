@@ -220,7 +220,8 @@ def bench_flow(mc, ncall, plain_iters=50):
             "chi2_dof": res["chi2_dof"], "true_rel_error": abs(res["estimate"] - 1.0),
             "error_in_sigma": (abs(res["estimate"] - 1.0) / res["error"]
                                if res["error"] else None),
-            "used_flow": rep["used_flow"], "last_plain_var": rep["last_plain_var"],
+            "used_flow": rep["used_flow"], "weight_tail_shape": rep["tail_shape"],
+            "last_plain_var": rep["last_plain_var"],
             "first_flow_var": rep["first_flow_var"],
             "training_samples_per_s": trained / (rep["train_ms"] * 1e-3),
             "proposal_evals_per_s": evals,

@@ -449,6 +449,30 @@ int mcubes_flow_draw(mcubes_flow *flow, const mcubes_plan *plan, uint32_t iterat
 int mcubes_flow_vsample(mcubes_flow *flow, int precision, const mcubes_plan *plan,
                         uint32_t iteration, double *d_est, void *stream);
 
+/* Tail diagnostic of importance weights.  Each mcubes_flow_vsample call
+ * histograms log2 of its weights w = f/q: MCUBES_WTAIL_BINS bins, bin b
+ * holding 2^((b - 2048)/8) <= w < 2^((b - 2047)/8) (the first and last bins
+ * also take everything below and above; w <= 0 is not counted).  The shape
+ * is the Hill estimate of the generalised Pareto shape of the upper tail,
+ * xi = mean of ln(w / u) over the k = min(N/5, 3 sqrt N) largest weights, u
+ * the lower edge of the bin where they start (the within-bin position is
+ * taken at the bin's middle: at most 0.04 off).  Reading, for a Pareto
+ * tail of shape xi (moments of order below 1/xi exist):
+ *   xi < 0.25  the weights have a finite fourth moment, so the estimated
+ *              variance is itself reliable: the error bar can be trusted;
+ *   0.25-0.5   finite variance, but the variance estimate has none of its
+ *              own: it is usually too small (rare large weights missing);
+ *   xi >= 0.5  the variance is infinite: the error bar means nothing.
+ * A bounded but strongly peaked weight distribution (a proposal much flatter
+ * than f) reads high as well: there too a handful of weights decides the
+ * estimate.  Host only: *shape = NaN when fewer than 100 weights were
+ * counted; tail_count (may be NULL) receives k. */
+#define MCUBES_WTAIL_BINS 4096
+int mcubes_weight_tail_shape(const uint32_t *hist, double *shape, int64_t *tail_count);
+/* The same for the weights of the last mcubes_flow_vsample call on `flow`
+ * (synchronises with that call's stream). */
+int mcubes_flow_weight_tail(mcubes_flow *flow, double *shape, int64_t *tail_count);
+
 /* The whole learned-proposal pipeline for one integrand of dim 6:
  *   1. warmup_iters plain m-Cubes iterations (grid refined every time);
  *   2. the samples and weights of train_items work items of the last of them
@@ -496,6 +520,7 @@ typedef struct {
     double last_plain_var, first_flow_var; /* the judge's comparison */
     double final_loss;     /* mean batch loss of the last training epoch */
     int32_t flow_iterations, used_flow;
+    double tail_shape;     /* largest weight-tail shape of the flow iterations (NaN if none) */
 } mcubes_flow_report;
 
 void mcubes_default_flow_options(mcubes_flow_options *opt);

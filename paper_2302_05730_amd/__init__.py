@@ -80,7 +80,8 @@ class mcubes_flow_report(ctypes.Structure):
                 ("plain_estimate", ctypes.c_double), ("plain_error", ctypes.c_double),
                 ("plain_chi2_dof", ctypes.c_double), ("last_plain_var", ctypes.c_double),
                 ("first_flow_var", ctypes.c_double), ("final_loss", ctypes.c_double),
-                ("flow_iterations", ctypes.c_int32), ("used_flow", ctypes.c_int32)]
+                ("flow_iterations", ctypes.c_int32), ("used_flow", ctypes.c_int32),
+                ("tail_shape", ctypes.c_double)]
 
 
 class mcubes_batch_item(ctypes.Structure):
@@ -166,6 +167,8 @@ _SIGNATURES = {
     "mcubes_flow_vsample": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_uint32, _vp, _vp]),
     "mcubes_flow_draw": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, ctypes.c_int64, _vp, _vp, _vp]),
     "mcubes_default_flow_options": (None, [ctypes.POINTER(mcubes_flow_options)]),
+    "mcubes_weight_tail_shape": (ctypes.c_int, [_vp, _dp, ctypes.POINTER(ctypes.c_int64)]),
+    "mcubes_flow_weight_tail": (ctypes.c_int, [_vp, _dp, ctypes.POINTER(ctypes.c_int64)]),
     "mcubes_flow_integrate": (ctypes.c_int, [_vp, ctypes.c_int, _dp, ctypes.c_int64, ctypes.c_int,
                                              ctypes.c_double, ctypes.c_uint64,
                                              ctypes.POINTER(mcubes_options),
@@ -571,10 +574,34 @@ class Flow:
         out["converged"] = bool(out["converged"])
         return out, {f: getattr(rep, f) for f, _ in mcubes_flow_report._fields_}
 
+    def weight_tail(self):
+        """(shape, tail count) of the last flow iteration's weights."""
+        shape = ctypes.c_double()
+        k = ctypes.c_int64()
+        _check(lib().mcubes_flow_weight_tail(self.handle, ctypes.byref(shape), ctypes.byref(k)))
+        return shape.value, k.value
+
     def vsample(self, plan, iteration, d_est, precision=MCUBES_FP32, stream=None):
         _check(lib().mcubes_flow_vsample(self.handle, int(precision), plan.handle,
                                          int(iteration), _dev(d_est, 2, "est"),
                                          _stream(stream)))
+
+
+MCUBES_WTAIL_BINS = 4096
+
+
+def mcubes_weight_tail_shape(hist):
+    """(shape, tail count) of a MCUBES_WTAIL_BINS-bin log2 weight histogram
+    (host only; shape is NaN below 100 counted weights)."""
+    import numpy as np
+    h = np.ascontiguousarray(hist, dtype=np.uint32)
+    if h.shape != (MCUBES_WTAIL_BINS,):
+        raise ValueError(f"the histogram needs {MCUBES_WTAIL_BINS} bins")
+    shape = ctypes.c_double()
+    k = ctypes.c_int64()
+    _check(lib().mcubes_weight_tail_shape(h.ctypes.data_as(_vp), ctypes.byref(shape),
+                                          ctypes.byref(k)))
+    return shape.value, k.value
 
 
 def mcubes_vsample_dump(plan, iteration, d_grid, w_begin, count, d_x, d_w, stream=None):

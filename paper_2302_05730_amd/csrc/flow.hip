@@ -420,6 +420,11 @@ __global__ void wgrad_sum_kernel(const float *__restrict__ part, int slices,
     grad[i] = a;
 }
 
+__global__ void zero_u32_kernel(uint32_t *__restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
 __global__ void widen_kernel(const float *__restrict__ in, int64_t n, double *__restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = (double)in[i];
@@ -451,8 +456,12 @@ __global__ void adam_kernel(float *__restrict__ theta, float *__restrict__ m,
 template <int F>
 __global__ __launch_bounds__(256) void flow_vsample_kernel(const float *__restrict__ theta,
                                                            const VsArgs A, uint32_t stream_word,
-                                                           double *__restrict__ partials) {
+                                                           double *__restrict__ partials,
+                                                           uint32_t *__restrict__ whist) {
     constexpr int NBLK = (D + 3) / 4;
+    __shared__ uint32_t hist[WH_BINS];
+    wh_clear(hist);
+    __syncthreads();
     const uint32_t T = gridDim.x * blockDim.x;
     double tS = 0.0, tV = 0.0;
     for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < A.m; c += T) {
@@ -484,6 +493,7 @@ __global__ __launch_bounds__(256) void flow_vsample_kernel(const float *__restri
 #pragma unroll
             for (int j = 0; j < D; ++j) Family<F, D>::axis(acc, A.ca[j], A.cu[j], (double)u[j]);
             const double w = Family<F, D>::end(acc, A) / exp((double)lq);
+            wh_add(hist, w);
             S = S + w;
             if (k == 0) w0 = w;
             const double dlt = w - w0;
@@ -510,6 +520,7 @@ __global__ __launch_bounds__(256) void flow_vsample_kernel(const float *__restri
         partials[2 * blockIdx.x] = s;
         partials[2 * blockIdx.x + 1] = v;
     }
+    wh_flush(hist, whist);
 }
 
 // The samples of work items [w0, w0 + count) of one plain iteration (cube
@@ -617,9 +628,9 @@ hipError_t launch_flow_draw_f(const float *theta, const VsArgs &A, uint32_t stre
 
 template <int F>
 hipError_t launch_flow_vsample_f(const float *theta, const VsArgs &A, uint32_t stream_word,
-                                 double *partials, int blocks, hipStream_t s) {
+                                 double *partials, uint32_t *whist, int blocks, hipStream_t s) {
     hipLaunchKernelGGL((flow_vsample_kernel<F>), dim3(blocks), dim3(256), 0, s, theta, A,
-                       stream_word, partials);
+                       stream_word, partials, whist);
     return hipGetLastError();
 }
 
@@ -695,6 +706,12 @@ hipError_t launch_flow_wgrad(const float *scratch_in, int64_t n, float *grad, hi
     return hipGetLastError();
 }
 
+hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_flow_widen(const float *in, int64_t n, double *out, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(widen_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, n, out);
@@ -716,17 +733,17 @@ hipError_t launch_flow_adam(float *theta, float *m, float *v, const float *grad,
 }
 
 hipError_t launch_flow_vsample(int family, const float *theta, const VsArgs &A,
-                               uint32_t stream_word, double *partials, int blocks,
-                               hipStream_t s) {
+                               uint32_t stream_word, double *partials, uint32_t *whist,
+                               int blocks, hipStream_t s) {
     switch (family) {
-    case MCUBES_OSCILLATORY: return launch_flow_vsample_f<MCUBES_OSCILLATORY>(theta, A, stream_word, partials, blocks, s);
-    case MCUBES_PRODUCT_PEAK: return launch_flow_vsample_f<MCUBES_PRODUCT_PEAK>(theta, A, stream_word, partials, blocks, s);
-    case MCUBES_CORNER_PEAK: return launch_flow_vsample_f<MCUBES_CORNER_PEAK>(theta, A, stream_word, partials, blocks, s);
-    case MCUBES_GAUSSIAN: return launch_flow_vsample_f<MCUBES_GAUSSIAN>(theta, A, stream_word, partials, blocks, s);
-    case MCUBES_C0: return launch_flow_vsample_f<MCUBES_C0>(theta, A, stream_word, partials, blocks, s);
-    case MCUBES_DISCONTINUOUS: return launch_flow_vsample_f<MCUBES_DISCONTINUOUS>(theta, A, stream_word, partials, blocks, s);
-    case MCUBES_ADDITION: return launch_flow_vsample_f<MCUBES_ADDITION>(theta, A, stream_word, partials, blocks, s);
-    case MCUBES_MIXTURE: return launch_flow_vsample_f<MCUBES_MIXTURE>(theta, A, stream_word, partials, blocks, s);
+    case MCUBES_OSCILLATORY: return launch_flow_vsample_f<MCUBES_OSCILLATORY>(theta, A, stream_word, partials, whist, blocks, s);
+    case MCUBES_PRODUCT_PEAK: return launch_flow_vsample_f<MCUBES_PRODUCT_PEAK>(theta, A, stream_word, partials, whist, blocks, s);
+    case MCUBES_CORNER_PEAK: return launch_flow_vsample_f<MCUBES_CORNER_PEAK>(theta, A, stream_word, partials, whist, blocks, s);
+    case MCUBES_GAUSSIAN: return launch_flow_vsample_f<MCUBES_GAUSSIAN>(theta, A, stream_word, partials, whist, blocks, s);
+    case MCUBES_C0: return launch_flow_vsample_f<MCUBES_C0>(theta, A, stream_word, partials, whist, blocks, s);
+    case MCUBES_DISCONTINUOUS: return launch_flow_vsample_f<MCUBES_DISCONTINUOUS>(theta, A, stream_word, partials, whist, blocks, s);
+    case MCUBES_ADDITION: return launch_flow_vsample_f<MCUBES_ADDITION>(theta, A, stream_word, partials, whist, blocks, s);
+    case MCUBES_MIXTURE: return launch_flow_vsample_f<MCUBES_MIXTURE>(theta, A, stream_word, partials, whist, blocks, s);
     default: return hipErrorInvalidValue;
     }
 }

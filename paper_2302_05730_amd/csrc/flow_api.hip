@@ -4,6 +4,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -20,6 +21,8 @@ struct mcubes_flow {
     bool packed = false;               // fragments up to date with d_theta
     double *d_aux = nullptr;           // [0] sum of weights, [1] loss
     double *d_part = nullptr;          // per-block partials of the flow-mapped iteration
+    uint32_t *d_whist = nullptr;       // log2 histogram of the last flow iteration's weights
+    hipStream_t last_stream = nullptr; // stream of the last flow iteration
     float *d_scratch = nullptr;
     int64_t scratch_n = 0;             // samples the scratch buffer holds
     int step = 0;                      // Adam steps taken
@@ -43,6 +46,7 @@ void release(mcubes_flow *F) {
     (void)hipFree(F->d_fbias);
     (void)hipFree(F->d_aux);
     (void)hipFree(F->d_part);
+    (void)hipFree(F->d_whist);
     (void)hipFree(F->d_scratch);
     delete F;
 }
@@ -136,6 +140,9 @@ int mcubes_flow_create(const double *theta, mcubes_flow **out) {
         e = hipMalloc((void **)&F->d_fbias, (size_t)flow_bf16_bias_floats() * sizeof(float));
     if (e == hipSuccess) e = hipMalloc((void **)&F->d_aux, 2 * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&F->d_part, 2 * kVsBlocks * sizeof(double));
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&F->d_whist, (size_t)MCUBES_WTAIL_BINS * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemset(F->d_whist, 0, (size_t)MCUBES_WTAIL_BINS * sizeof(uint32_t));
     if (e != hipSuccess) {
         release(F);
         return fail(MCUBES_E_ALLOC, "flow allocation: %s", hipGetErrorString(e));
@@ -304,25 +311,59 @@ int mcubes_flow_vsample(mcubes_flow *F, int precision, const mcubes_plan *P, uin
     A.iteration = iteration;
     const uint32_t stream_word = A.stream_id | 0x80000000u;
     hipStream_t s = as_stream(stream);
-    hipError_t e;
+    F->last_stream = s;
+    hipError_t e = launch_zero_u32(F->d_whist, MCUBES_WTAIL_BINS, s);
     int blocks;
     if (precision == MCUBES_BF16) {
         // 256 samples per workgroup pass (four waves of 64)
         const int64_t groups = (P->m * P->p + 255) / 256;
         blocks = groups < kVsBlocks ? (int)groups : kVsBlocks;
-        e = ensure_packed(F, s);
+        if (e == hipSuccess) e = ensure_packed(F, s);
         if (e == hipSuccess)
             e = launch_flow_vsample_bf16(P->family, F->d_frags, F->d_fbias, A, stream_word,
-                                         F->d_part, blocks, s);
+                                         F->d_part, F->d_whist, blocks, s);
     } else {
         blocks = (int)((P->m + 255) / 256);
         if (blocks > kVsBlocks) blocks = kVsBlocks;
-        e = launch_flow_vsample(P->family, F->d_theta, A, stream_word, F->d_part, blocks, s);
+        if (e == hipSuccess)
+            e = launch_flow_vsample(P->family, F->d_theta, A, stream_word, F->d_part, F->d_whist,
+                                    blocks, s);
     }
     const double n = (double)P->m * (double)P->p;
     const double denom = (double)P->p * (double)P->m * (double)P->m;
     if (e == hipSuccess) e = launch_reduce(F->d_part, blocks, n, denom, d_est, s);
     return e == hipSuccess ? MCUBES_OK : hip_fail(e, "flow V-Sample launch");
+}
+
+int mcubes_weight_tail_shape(const uint32_t *hist, double *shape, int64_t *tail_count) {
+    if (!hist || !shape) return fail(MCUBES_E_ARG, "NULL argument");
+    *shape = NAN;
+    if (tail_count) *tail_count = 0;
+    int64_t total = 0;
+    for (int b = 0; b < MCUBES_WTAIL_BINS; ++b) total += hist[b];
+    if (total < 100) return MCUBES_OK;
+    const int64_t k = std::min<int64_t>(total / 5, (int64_t)floor(3.0 * sqrt((double)total)));
+    // the bins holding the k largest weights, from the top down
+    int b = MCUBES_WTAIL_BINS - 1;
+    int64_t c = hist[b];
+    while (c < k && b > 0) c += hist[--b];
+    // Hill estimate over them, threshold the lower edge of bin b, each weight
+    // at the middle of its bin (in log2, bins are 1/8 wide)
+    double acc = 0.0;
+    for (int q = b; q < MCUBES_WTAIL_BINS; ++q) acc += (double)hist[q] * ((double)(q - b) + 0.5);
+    *shape = acc / (double)c * (log(2.0) / 8.0);
+    if (tail_count) *tail_count = c;
+    return MCUBES_OK;
+}
+
+int mcubes_flow_weight_tail(mcubes_flow *F, double *shape, int64_t *tail_count) {
+    if (!F || !shape) return fail(MCUBES_E_ARG, "NULL argument");
+    std::vector<uint32_t> h(MCUBES_WTAIL_BINS);
+    hipError_t e = hipStreamSynchronize(F->last_stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(h.data(), F->d_whist, h.size() * sizeof(uint32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "weight histogram");
+    return mcubes_weight_tail_shape(h.data(), shape, tail_count);
 }
 
 void mcubes_default_flow_options(mcubes_flow_options *o) {
@@ -449,6 +490,7 @@ int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int6
         }
     }
     FI_CHECK(hipEventRecord(ev[2], s), "hipEventRecord");
+    R.tail_shape = NAN;
     R.plain_estimate = head[0];
     R.plain_error = head[1];
     R.plain_chi2_dof = head[2];
@@ -471,6 +513,11 @@ int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int6
         FI_CHECK(hipMemcpyAsync(&ev_var, est + 1, sizeof ev_var, hipMemcpyDeviceToHost, s),
                  "hipMemcpyAsync");
         FI_CHECK(hipStreamSynchronize(s), "hipStreamSynchronize");
+        if (used) {
+            double xi = NAN;
+            FI_CALL(mcubes_flow_weight_tail(F, &xi, nullptr));
+            if (isnan(R.tail_shape) || xi > R.tail_shape) R.tail_shape = xi;
+        }
         done = t + 1;
         if (used && t == 0) {
             R.first_flow_var = ev_var;

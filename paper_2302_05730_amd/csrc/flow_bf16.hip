@@ -239,8 +239,12 @@ __global__ __launch_bounds__(256) void flow_vsample_bf16_kernel(const bf16x8 *__
                                                                 const float *__restrict__ bias,
                                                                 const VsArgs A,
                                                                 uint32_t stream_word,
-                                                                double *__restrict__ partials) {
+                                                                double *__restrict__ partials,
+                                                                uint32_t *__restrict__ whist) {
     constexpr int NBLK = (D + 3) / 4;
+    __shared__ uint32_t hist[WH_BINS];
+    wh_clear(hist);
+    __syncthreads();
     const uint64_t N = (uint64_t)A.m * A.p;
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
     const uint64_t wid = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -274,6 +278,7 @@ __global__ __launch_bounds__(256) void flow_vsample_bf16_kernel(const bf16x8 *__
 #pragma unroll
         for (int j = 0; j < D; ++j) Family<F, D>::axis(acc, A.ca[j], A.cu[j], (double)u[j]);
         const double w = Family<F, D>::end(acc, A) / exp((double)lq);
+        if (live) wh_add(hist, w);
         // per-cube sums over the p lanes of the cube, shifted by its first sample
         const int first = lane - (lane % p);
         const double w0 = __shfl(w, first);
@@ -306,6 +311,7 @@ __global__ __launch_bounds__(256) void flow_vsample_bf16_kernel(const bf16x8 *__
         partials[2 * blockIdx.x] = s;
         partials[2 * blockIdx.x + 1] = v;
     }
+    wh_flush(hist, whist);
 }
 
 // ---------------------------------------------------------------------
@@ -622,9 +628,10 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
 
 template <int F>
 hipError_t launch_bf16_f(const void *frags, const float *bias, const VsArgs &A,
-                         uint32_t stream_word, double *partials, int blocks, hipStream_t s) {
+                         uint32_t stream_word, double *partials, uint32_t *whist, int blocks,
+                         hipStream_t s) {
     hipLaunchKernelGGL((flow_vsample_bf16_kernel<F>), dim3(blocks), dim3(256), 0, s,
-                       (const bf16x8 *)frags, bias, A, stream_word, partials);
+                       (const bf16x8 *)frags, bias, A, stream_word, partials, whist);
     return hipGetLastError();
 }
 
@@ -673,16 +680,16 @@ hipError_t launch_flow_sample_bf16(const void *frags, const float *bias, const d
 
 hipError_t launch_flow_vsample_bf16(int family, const void *frags, const float *bias,
                                     const VsArgs &A, uint32_t stream_word, double *partials,
-                                    int blocks, hipStream_t s) {
+                                    uint32_t *whist, int blocks, hipStream_t s) {
     switch (family) {
-    case MCUBES_OSCILLATORY: return launch_bf16_f<MCUBES_OSCILLATORY>(frags, bias, A, stream_word, partials, blocks, s);
-    case MCUBES_PRODUCT_PEAK: return launch_bf16_f<MCUBES_PRODUCT_PEAK>(frags, bias, A, stream_word, partials, blocks, s);
-    case MCUBES_CORNER_PEAK: return launch_bf16_f<MCUBES_CORNER_PEAK>(frags, bias, A, stream_word, partials, blocks, s);
-    case MCUBES_GAUSSIAN: return launch_bf16_f<MCUBES_GAUSSIAN>(frags, bias, A, stream_word, partials, blocks, s);
-    case MCUBES_C0: return launch_bf16_f<MCUBES_C0>(frags, bias, A, stream_word, partials, blocks, s);
-    case MCUBES_DISCONTINUOUS: return launch_bf16_f<MCUBES_DISCONTINUOUS>(frags, bias, A, stream_word, partials, blocks, s);
-    case MCUBES_ADDITION: return launch_bf16_f<MCUBES_ADDITION>(frags, bias, A, stream_word, partials, blocks, s);
-    case MCUBES_MIXTURE: return launch_bf16_f<MCUBES_MIXTURE>(frags, bias, A, stream_word, partials, blocks, s);
+    case MCUBES_OSCILLATORY: return launch_bf16_f<MCUBES_OSCILLATORY>(frags, bias, A, stream_word, partials, whist, blocks, s);
+    case MCUBES_PRODUCT_PEAK: return launch_bf16_f<MCUBES_PRODUCT_PEAK>(frags, bias, A, stream_word, partials, whist, blocks, s);
+    case MCUBES_CORNER_PEAK: return launch_bf16_f<MCUBES_CORNER_PEAK>(frags, bias, A, stream_word, partials, whist, blocks, s);
+    case MCUBES_GAUSSIAN: return launch_bf16_f<MCUBES_GAUSSIAN>(frags, bias, A, stream_word, partials, whist, blocks, s);
+    case MCUBES_C0: return launch_bf16_f<MCUBES_C0>(frags, bias, A, stream_word, partials, whist, blocks, s);
+    case MCUBES_DISCONTINUOUS: return launch_bf16_f<MCUBES_DISCONTINUOUS>(frags, bias, A, stream_word, partials, whist, blocks, s);
+    case MCUBES_ADDITION: return launch_bf16_f<MCUBES_ADDITION>(frags, bias, A, stream_word, partials, whist, blocks, s);
+    case MCUBES_MIXTURE: return launch_bf16_f<MCUBES_MIXTURE>(frags, bias, A, stream_word, partials, whist, blocks, s);
     default: return hipErrorInvalidValue;
     }
 }

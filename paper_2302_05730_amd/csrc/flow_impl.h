@@ -38,6 +38,29 @@ static_assert(PARAMS == MCUBES_FLOW_PARAMS, "flow parameter count");
 constexpr int FS_U = 0, FS_H1 = FS_U + D, FS_H2 = FS_H1 + HID, FS_DOUT = FS_H2 + HID;
 constexpr int FS_D2 = FS_DOUT + OUT, FS_D1 = FS_D2 + HID, FS = FS_D1 + HID;
 
+// Histogram of log2 of the flow-mapped weights (the tail diagnostic): bin
+// floor(8 log2 w) + 2048, clamped to [0, 4095]; weights that are not
+// positive (or not numbers) are not counted.  Kept per workgroup in LDS.
+constexpr int WH_BINS = MCUBES_WTAIL_BINS, WH_PER_OCTAVE = 8, WH_ZERO = WH_BINS / 2;
+
+__device__ __forceinline__ void wh_add(uint32_t *hist, double w) {
+    if (!(w > 0.0)) return;
+    double v = floor(log2(w) * (double)WH_PER_OCTAVE);
+    v = fmin(fmax(v, -(double)WH_ZERO), (double)(WH_ZERO - 1));
+    atomicAdd(&hist[(int)v + WH_ZERO], 1u);
+}
+
+__device__ __forceinline__ void wh_clear(uint32_t *hist) {
+    for (int i = threadIdx.x; i < WH_BINS; i += blockDim.x) hist[i] = 0u;
+}
+
+// adds the workgroup's histogram to the global one (barrier first)
+__device__ __forceinline__ void wh_flush(const uint32_t *hist, uint32_t *__restrict__ out) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < WH_BINS; i += blockDim.x)
+        if (hist[i]) atomicAdd(&out[i], hist[i]);
+}
+
 // coordinate t of A_l and of B_l
 __device__ __forceinline__ int a_idx(int l, int t) {
     return l == 0 ? t : (l == 1 ? 3 + t : (l == 2 ? 2 * t : 2 * t + 1));

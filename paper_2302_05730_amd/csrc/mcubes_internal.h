@@ -138,6 +138,7 @@ hipError_t launch_flow_sample(const float *theta, const double *z, int64_t n, do
                               double *logq, hipStream_t s);
 int64_t flow_scratch_floats(int64_t n);
 int64_t flow_transposed_floats();
+hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
 // out[i] <- (double)in[i]
 hipError_t launch_flow_widen(const float *in, int64_t n, double *out, hipStream_t s);
 // w[i] <- w[i]^power (training weights of the tail rounds)
@@ -159,9 +160,10 @@ int64_t flow_bf16_bwd_frag_bytes();
 hipError_t launch_flow_adam(float *theta, float *m, float *v, const float *grad, float lr,
                             float beta1, float beta2, float eps, float c1, float c2,
                             hipStream_t s);
+// whist: MCUBES_WTAIL_BINS counters the log2 histogram of the weights is added to
 hipError_t launch_flow_vsample(int family, const float *theta, const VsArgs &A,
-                               uint32_t stream_word, double *partials, int blocks,
-                               hipStream_t s);
+                               uint32_t stream_word, double *partials, uint32_t *whist,
+                               int blocks, hipStream_t s);
 hipError_t launch_vsample_dump(int family, int dim, const VsArgs &A, const double *grid,
                                uint32_t w0, uint32_t count, double *xs, double *ws,
                                hipStream_t s);
@@ -177,7 +179,7 @@ hipError_t launch_flow_sample_bf16(const void *frags, const float *bias, const d
                                    int64_t n, double *x, double *logq, hipStream_t s);
 hipError_t launch_flow_vsample_bf16(int family, const void *frags, const float *bias,
                                     const VsArgs &A, uint32_t stream_word, double *partials,
-                                    int blocks, hipStream_t s);
+                                    uint32_t *whist, int blocks, hipStream_t s);
 
 // Microbenchmarks (microbench.hip).
 hipError_t launch_microbench(int kind, int family, int dim, const VsArgs &A, const double *pts,

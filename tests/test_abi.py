@@ -63,6 +63,7 @@ int main(void) {
     F(mcubes_flow_options, train_items) F(mcubes_flow_options, tail_rounds) F(mcubes_flow_options, batch) F(mcubes_flow_options, round_lr) F(mcubes_flow_options, tail_lr) F(mcubes_flow_options, train_precision)
     printf("mcubes_flow_report size %zu\n", sizeof(mcubes_flow_report));
     F(mcubes_flow_report, final_loss) F(mcubes_flow_report, used_flow)
+    F(mcubes_flow_report, tail_shape)
     printf("MCUBES_STATE_LEN x %d\n", MCUBES_STATE_LEN);
     return 0;
 }

@@ -198,6 +198,33 @@ def test_bf16_loss_gradient_tracks_the_oracle(mc):
     assert np.all(np.sign(g[big]) == np.sign(g_ref[big]))
 
 
+def test_flow_iteration_weight_tail(mc):
+    """The weight histogram of a flow-mapped iteration feeds the tail
+    diagnostic, in FP32 and BF16.  The identity flow (uniform proposal) on
+    the additive integrand (weights sum x in (0, 6), flat at the top) reads
+    as a light tail; on a peaked 6-D Gaussian (a = 5) the few samples near
+    the peak carry weights spread over a factor of ~15 above the tail's
+    threshold, which reads as heavy (the estimate for uniform sampling of
+    exp(-25 |x - u|^2) over the top 0.6% is 0.67), as it should: there a
+    handful of weights decides the estimate.  The tail count is
+    min(N/5, 3 sqrt N) or a little more (whole bins)."""
+    import torch
+    opts = mc.mcubes_default_options(nbins=50)
+    fl = mc.Flow(workloads.flow_init(7))
+    d_est = torch.zeros(2, dtype=torch.float64, device="cuda")
+    gauss = [5.0] * 6 + [0.4, 0.5, 0.6, 0.45, 0.55, 0.5]
+    for family, params, lo, hi in ((workloads.ADDITION, None, 0.0, 0.2),
+                                   (workloads.GAUSSIAN, gauss, 0.5, 0.9)):
+        plan = mc.mcubes_plan_create(family, params, 6, 1 << 18, 3, opts)
+        n = plan.info["samples_per_iter"]
+        for prec in (mc.MCUBES_FP32, mc.MCUBES_BF16):
+            fl.vsample(plan, 2, d_est, precision=prec)
+            shape, k = fl.weight_tail()
+            _say(f"family {family} precision {prec}: tail shape {shape:.3f} over {k} of {n}")
+            assert k >= min(n // 5, int(3 * math.sqrt(n)))
+            assert lo < shape < hi
+
+
 def test_sample_export_is_the_iterations_own_samples(mc):
     """The exported samples of an iteration: every weight and point of a few
     cubes against the oracle's own map (bitwise), and the sum of all weights
@@ -337,7 +364,9 @@ def test_flow_pipeline_beats_plain_mcubes_on_the_mixture(mc):
              f"vars {rep['last_plain_var']:.2e} -> {rep['first_flow_var']:.2e}; "
              f"ms warmup {rep['warmup_ms']:.1f} train {rep['train_ms']:.1f} "
              f"flow {rep['flow_ms']:.1f}")
+        _say(f"weight tail shape {rep['tail_shape']:.3f}")
         assert rep["used_flow"] == 1 and res["iterations"] == 4
+        assert math.isfinite(rep["tail_shape"])
         assert abs(res["estimate"] - 1.0) <= 1.5e-3
         assert abs(res["estimate"] - 1.0) < abs(rep["plain_estimate"] - 1.0) / 10
         # typically 1e4 times lower; one of the rare weights of 1e4 adds
