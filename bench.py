@@ -181,6 +181,15 @@ def bench_batch(mc, n, iters, full=True):
 # network multiply-adds per flow sample: 4 coupling layers, each 96x64 + 64x64 + 64x99
 FLOW_GEMM_FLOPS = 2 * 4 * (96 * 64 + 64 * 64 + 64 * 99)
 BF16_MFMA_PEAK_TFLOPS = 2500.0
+HBM_PEAK_GBPS = 8000.0
+# per training sample: the forward products, the input-gradient products and
+# the weight-gradient sums (three times the network); and the FP32 scratch
+# fields per layer that the pass writes (u, h1, h2, spline parameters), reads
+# back and overwrites with deltas (spline parameters, d2, d1), and that the
+# weight-gradient tiles read (inputs and deltas of the five output tiles)
+FLOW_TRAIN_FLOPS = 3 * FLOW_GEMM_FLOPS
+FLOW_TRAIN_BYTES = 4 * 4 * ((6 + 64 + 64 + 99) + (6 + 99 + 64 + 64) + (99 + 64 + 64)
+                            + (6 + 64) * 2 + (64 + 64) + (64 + 64) + (64 + 35))
 
 
 def bench_flow(mc, ncall, plain_iters=50):
@@ -224,11 +233,16 @@ def bench_flow(mc, ncall, plain_iters=50):
             "last_plain_var": rep["last_plain_var"],
             "first_flow_var": rep["first_flow_var"],
             "training_samples_per_s": trained / (rep["train_ms"] * 1e-3),
+            "training_network_tflops": trained / (rep["train_ms"] * 1e-3) * FLOW_TRAIN_FLOPS / 1e12,
+            "training_scratch_gbps": trained / (rep["train_ms"] * 1e-3) * FLOW_TRAIN_BYTES / 1e9,
             "proposal_evals_per_s": evals,
             "proposal_network_tflops": (evals * FLOW_GEMM_FLOPS / 1e12) if evals else None}
     if flow["proposal_network_tflops"]:
         flow["proposal_frac_of_bf16_mfma_peak"] = (flow["proposal_network_tflops"]
                                                    / BF16_MFMA_PEAK_TFLOPS)
+    flow["training_frac_of_bf16_mfma_peak"] = (flow["training_network_tflops"]
+                                               / BF16_MFMA_PEAK_TFLOPS)
+    flow["training_frac_of_hbm_peak"] = flow["training_scratch_gbps"] / HBM_PEAK_GBPS
     return {"workload": ("6-D mixture of two correlated Gaussians (sigma 0.05, correlation "
                          f"0.9, centres 1/3 and 2/3 on the diagonal), {ncall} samples/iter, "
                          "500 bins; integral 1"),

@@ -321,6 +321,7 @@ __global__ __launch_bounds__(CT, 4) void train_kernel(const float *__restrict__ 
 constexpr int WT = 64, WKC = 32, WPAD = WT + 4;
 constexpr int TILES_L = 5;  // W1 rows 0-63 | W1 rows 64-95 | W2 | W3 cols 0-63 | W3 cols 64-98
 constexpr int kMaxSlices = 64;
+static_assert(kMaxSlices <= kWgradSlices, "slice buffer");
 
 __global__ __launch_bounds__(256) void wgrad_kernel(const float *__restrict__ scratch, int64_t n,
                                                     int64_t ks, float *__restrict__ part) {
@@ -670,8 +671,17 @@ hipError_t launch_flow_sample(const float *theta, const double *z, int64_t n, do
     return hipGetLastError();
 }
 
-// per-sample fields, then the partial weight gradients of the slices
-int64_t flow_scratch_floats(int64_t n) { return (int64_t)L * FS * n + (int64_t)kMaxSlices * PARAMS; }
+// per-sample fields, the partial weight gradients of the slices, then the
+// BF16 training pass's own per-sample state
+int64_t flow_scratch_floats(int64_t n) {
+    return (int64_t)L * FS * n + (int64_t)kWgradSlices * PARAMS + flow_bf16_train_extra_floats(n);
+}
+
+hipError_t launch_flow_wgrad_sum(const float *part, int slices, float *grad, hipStream_t s) {
+    hipLaunchKernelGGL(wgrad_sum_kernel, dim3((PARAMS + 255) / 256), dim3(256), 0, s, part, slices,
+                       grad);
+    return hipGetLastError();
+}
 
 int64_t flow_transposed_floats() { return (int64_t)L * LPT; }
 

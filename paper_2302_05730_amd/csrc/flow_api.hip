@@ -104,7 +104,8 @@ hipError_t train_step(mcubes_flow *F, int precision, const double *d_x, const do
         e = launch_flow_train_fp32(F->d_theta, F->d_thetaT, d_x, d_w, n, F->d_aux, F->d_scratch,
                                    d_loss, s);
     if (e != hipSuccess) return e;
-    return launch_flow_wgrad(F->d_scratch, n, F->d_grad, s);
+    return precision == MCUBES_BF16 ? launch_flow_wgrad_bf16(F->d_scratch, n, F->d_grad, s)
+                                    : launch_flow_wgrad(F->d_scratch, n, F->d_grad, s);
 }
 
 int check_train_precision(int precision) {

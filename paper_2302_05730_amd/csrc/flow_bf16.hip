@@ -368,23 +368,76 @@ __device__ __forceinline__ void swap_halves(const bf16x8 &a, const bf16x8 &b, bf
     hi = __builtin_bit_cast(bf16x8, r1);
 }
 
+// The third product of layer l for one sample block from its BF16 operands.
+__device__ __forceinline__ void third_product(const bf16x8 *__restrict__ Fr,
+                                              const bf16x8 (&h2)[G3K], f32x16 (&out)[G3T]) {
+#pragma unroll
+    for (int t = 0; t < G3T; ++t) out[t] = f32x16{};
+#pragma unroll
+    for (int ks = 0; ks < G3K; ++ks)
+#pragma unroll
+        for (int t = 0; t < G3T; ++t)
+            out[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Fr[(OFF_G3 + t * G3K + ks) * 64], h2[ks],
+                                                             out[t], 0, 0, 0);
+}
+
+// Bias added, and every lane handed its own sample's 99 outputs: afterwards
+// out[hh][t][r] holds feature acc_feature(t, r, hh) of the lane's sample.
+__device__ __forceinline__ void own_outputs(const float *__restrict__ bias, int l,
+                                            f32x16 (&out)[2][G3T]) {
+#pragma unroll
+    for (int t = 0; t < G3T; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const auto sw = __builtin_amdgcn_permlane32_swap(
+                __float_as_uint(out[0][t][r]), __float_as_uint(out[1][t][r]), false, false);
+            out[0][t][r] = __uint_as_float(sw[0]) + bias[l * BIAS + BOFF_3 + t * 32 + r];
+            out[1][t][r] = __uint_as_float(sw[1]) + bias[l * BIAS + BOFF_3 + t * 32 + 16 + r];
+        }
+}
+
+__device__ __forceinline__ void raw_of(const f32x16 (&own)[2][G3T], int b, float raw[RAW]) {
+#pragma unroll
+    for (int k = 0; k < RAW; ++k) {
+        const int f = b * RAW + k, t = f / 32, ww = f % 32;
+        raw[k] = own[(ww / 4) % 2][t][4 * (ww / 8) + ww % 4];
+    }
+}
+
+// Per-wave training state beyond the FP32 fields, per layer and group of 64
+// samples: the second hidden layer as the BF16 operands of the third product
+// ([block][K step][lane], 8 KB), from which the backward pass recomputes the
+// spline parameters, and the ReLU masks of h1 and h2 as bits ([block][h1,
+// h2][lane], one word per lane: bit 16 t + r for accumulator register r of
+// row tile t).
+constexpr int BF_EXTRA = 36;  // floats per sample and layer
+
+__device__ __forceinline__ bf16x8 *h2_ops(float *ext_l, int64_t group, int sb) {
+    return reinterpret_cast<bf16x8 *>(ext_l) + (group * 2 + sb) * G3K * 64;
+}
+__device__ __forceinline__ uint32_t *relu_bits(float *ext_l, int64_t n64, int64_t group, int sb,
+                                               int which) {
+    return reinterpret_cast<uint32_t *>(ext_l + 32 * n64) + ((group * 2 + sb) * 2 + which) * 64;
+}
+
 // Forward and backward pass of the weighted negative log-likelihood, 64
 // samples per wave (lane = sample for the per-sample work), the nine
-// products per layer on the matrix cores.  Writes the same scratch fields
-// as the FP32 form (activations and deltas FP32, taken from the FP32
-// accumulators) for the weight-gradient kernels; loss += sum c log q with
-// c = -w / sum w.  Lanes past n work on a copy of the last sample with
-// c = 0 and store nothing.
+// products per layer on the matrix cores.  Writes the FP32 scratch fields
+// the weight-gradient kernels read (u, h1, h2, and the deltas, taken from
+// the FP32 accumulators); loss += sum c log q with c = -w / sum w.  Lanes
+// past n work on a copy of the last sample with c = 0 and store nothing.
 __global__ __launch_bounds__(64) void train_bf16_kernel(
     const bf16x8 *__restrict__ frags, const bf16x8 *__restrict__ bfrags,
     const float *__restrict__ bias, const double *__restrict__ x, const double *__restrict__ w,
-    int64_t n, const double *__restrict__ wsum, float *__restrict__ scratch,
+    int64_t n, const double *__restrict__ wsum, float *__restrict__ scratch, float *__restrict__ ext,
     double *__restrict__ loss) {
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
     const int64_t wid = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63, h = lane >> 5, col = lane & 31;
+    const int64_t n64 = (n + 63) / 64 * 64;
     double lsum = 0.0;
     for (int64_t base = wid * 64; base < n; base += waves * 64) {
+        const int64_t group = base / 64;
         const bool live = base + lane < n;
         const int64_t s = live ? base + lane : n - 1;
         // the sample of column col in block sb, and whether it is real
@@ -404,13 +457,14 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
 #pragma unroll 1
         for (int l = 0; l < L; ++l) {
             float *sc = scratch + (int64_t)l * FS * n;
+            float *ext_l = ext + (int64_t)l * BF_EXTRA * n64;
             if (live) {
 #pragma unroll
                 for (int j = 0; j < D; ++j) sc[(FS_U + j) * n + s] = u[j];
             }
             const bf16x8 *Fr = frags + (size_t)l * FRAGS * 64 + lane;
             const float *Bs = bias + l * BIAS + h * 16;
-            f32x16 out[2][G3T];
+            f32x16 own[2][G3T];
 #pragma unroll
             for (int sb = 0; sb < 2; ++sb) {
                 float ua[NA];
@@ -431,6 +485,7 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
                             Fr[(OFF_G1 + t * G1K + ks) * 64], bop, acc1[t], 0, 0, 0);
                 }
                 bf16x8 h1[G2K];
+                uint32_t m1 = 0u;
 #pragma unroll
                 for (int ks = 0; ks < G2K; ++ks) {
                     float v[8];
@@ -438,10 +493,12 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
                     for (int i = 0; i < 8; ++i) {
                         const int r = 8 * (ks % 2) + i;
                         v[i] = fmaxf(acc1[ks / 2][r] + Bs[BOFF_1 + (ks / 2) * 32 + r], 0.0f);
+                        m1 |= (v[i] > 0.0f ? 1u : 0u) << (8 * ks + i);
                         if (clive[sb]) sc[(FS_H1 + acc_feature(ks / 2, r, h)) * n + cs[sb]] = v[i];
                     }
                     h1[ks] = pack8(v);
                 }
+                relu_bits(ext_l, n64, group, sb, 0)[lane] = m1;
                 f32x16 acc2[G2T];
 #pragma unroll
                 for (int t = 0; t < G2T; ++t) acc2[t] = f32x16{};
@@ -451,6 +508,8 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
                     for (int t = 0; t < G2T; ++t)
                         acc2[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
                             Fr[(OFF_G2 + t * G2K + ks) * 64], h1[ks], acc2[t], 0, 0, 0);
+                uint32_t m2 = 0u;
+                bf16x8 *ops = h2_ops(ext_l, group, sb);
                 bf16x8 h2[G3K];
 #pragma unroll
                 for (int ks = 0; ks < G3K; ++ks) {
@@ -459,38 +518,20 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
                     for (int i = 0; i < 8; ++i) {
                         const int r = 8 * (ks % 2) + i;
                         v[i] = fmaxf(acc2[ks / 2][r] + Bs[BOFF_2 + (ks / 2) * 32 + r], 0.0f);
+                        m2 |= (v[i] > 0.0f ? 1u : 0u) << (8 * ks + i);
                         if (clive[sb]) sc[(FS_H2 + acc_feature(ks / 2, r, h)) * n + cs[sb]] = v[i];
                     }
                     h2[ks] = pack8(v);
+                    ops[ks * 64 + lane] = h2[ks];
                 }
-#pragma unroll
-                for (int t = 0; t < G3T; ++t) out[sb][t] = f32x16{};
-#pragma unroll
-                for (int ks = 0; ks < G3K; ++ks)
-#pragma unroll
-                    for (int t = 0; t < G3T; ++t)
-                        out[sb][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                            Fr[(OFF_G3 + t * G3K + ks) * 64], h2[ks], out[sb][t], 0, 0, 0);
+                relu_bits(ext_l, n64, group, sb, 1)[lane] = m2;
+                third_product(Fr, h2, own[sb]);
             }
-#pragma unroll
-            for (int t = 0; t < G3T; ++t)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const auto sw = __builtin_amdgcn_permlane32_swap(
-                        __float_as_uint(out[0][t][r]), __float_as_uint(out[1][t][r]), false, false);
-                    out[0][t][r] = __uint_as_float(sw[0]) + bias[l * BIAS + BOFF_3 + t * 32 + r];
-                    out[1][t][r] = __uint_as_float(sw[1]) + bias[l * BIAS + BOFF_3 + t * 32 + 16 + r];
-                }
-            f32x16(&own)[2][G3T] = out;
+            own_outputs(bias, l, own);
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 float raw[RAW];
-#pragma unroll
-                for (int k = 0; k < RAW; ++k) {
-                    const int f = b * RAW + k, t = f / 32, ww = f % 32;
-                    raw[k] = own[(ww / 4) % 2][t][4 * (ww / 8) + ww % 4];
-                    if (live) sc[(FS_DOUT + f) * n + s] = raw[k];
-                }
+                raw_of(own, b, raw);
                 Spline sp;
                 spline_setup(raw, sp);
                 const int j = b_idx(l, b);
@@ -508,21 +549,34 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
 #pragma unroll 1
         for (int l = L - 1; l >= 0; --l) {
             float *sc = scratch + (int64_t)l * FS * n;
+            float *ext_l = ext + (int64_t)l * BF_EXTRA * n64;
             float uin[D], gprev[D];
 #pragma unroll
             for (int j = 0; j < D; ++j) {
                 uin[j] = sc[(FS_U + j) * n + s];
                 gprev[j] = g[j];
             }
-            // spline deltas of the own sample, natural order padded to 112
+            // the spline parameters again, from the stored operands
+            f32x16 own[2][G3T];
+#pragma unroll
+            for (int sb = 0; sb < 2; ++sb) {
+                const bf16x8 *ops = h2_ops(ext_l, group, sb);
+                bf16x8 h2[G3K];
+#pragma unroll
+                for (int ks = 0; ks < G3K; ++ks) h2[ks] = ops[ks * 64 + lane];
+                third_product(frags + (size_t)l * FRAGS * 64 + lane, h2, own[sb]);
+            }
+            own_outputs(bias, l, own);
+            // spline deltas of the own sample, natural order padded to 112,
+            // packed to BF16 eight at a time as soon as each octet is complete
             float gr[16 * B3K];
+            bf16x8 oct[2 * B3K];
 #pragma unroll
             for (int k = NB * RAW; k < 16 * B3K; ++k) gr[k] = 0.0f;
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 float raw[RAW];
-#pragma unroll
-                for (int k = 0; k < RAW; ++k) raw[k] = sc[(FS_DOUT + b * RAW + k) * n + s];
+                raw_of(own, b, raw);
                 Spline sp;
                 spline_setup(raw, sp);
                 const int j = b_idx(l, b);
@@ -536,16 +590,21 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
                     gr[b * RAW + k] = graw[k];
                     if (live) sc[(FS_DOUT + b * RAW + k) * n + s] = graw[k];
                 }
+                const int from = (b * RAW) / 8, to = b == NB - 1 ? 2 * B3K : ((b + 1) * RAW) / 8;
+#pragma unroll
+                for (int o = 0; o < 2 * B3K; ++o)
+                    if (o >= from && o < to) oct[o] = pack8(&gr[8 * o]);
             }
             // operands of the two sample blocks
             bf16x8 X[2][B3K];
 #pragma unroll
-            for (int ks = 0; ks < B3K; ++ks)
-                swap_halves(pack8(&gr[16 * ks]), pack8(&gr[16 * ks + 8]), X[0][ks], X[1][ks]);
+            for (int ks = 0; ks < B3K; ++ks) swap_halves(oct[2 * ks], oct[2 * ks + 1], X[0][ks], X[1][ks]);
             const bf16x8 *Br = bfrags + (size_t)l * BFRAGS * 64 + lane;
             float tot[NA];
 #pragma unroll
             for (int sb = 0; sb < 2; ++sb) {
+                const uint32_t m1 = relu_bits(ext_l, n64, group, sb, 0)[lane];
+                const uint32_t m2 = relu_bits(ext_l, n64, group, sb, 1)[lane];
                 // through W3 and the second ReLU
                 f32x16 a3[B3T];
 #pragma unroll
@@ -563,8 +622,7 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
 #pragma unroll
                     for (int i = 0; i < 8; ++i) {
                         const int r = 8 * (ks % 2) + i, f = acc_feature(ks / 2, r, h);
-                        const float hv = sc[(FS_H2 + f) * n + cs[sb]];
-                        v[i] = hv > 0.0f ? a3[ks / 2][r] : 0.0f;
+                        v[i] = ((m2 >> (8 * ks + i)) & 1u) ? a3[ks / 2][r] : 0.0f;
                         if (clive[sb]) sc[(FS_D2 + f) * n + cs[sb]] = v[i];
                     }
                     Y[ks] = pack8(v);
@@ -586,8 +644,7 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
 #pragma unroll
                     for (int i = 0; i < 8; ++i) {
                         const int r = 8 * (ks % 2) + i, f = acc_feature(ks / 2, r, h);
-                        const float hv = sc[(FS_H1 + f) * n + cs[sb]];
-                        v[i] = hv > 0.0f ? a2[ks / 2][r] : 0.0f;
+                        v[i] = ((m1 >> (8 * ks + i)) & 1u) ? a2[ks / 2][r] : 0.0f;
                         if (clive[sb]) sc[(FS_D1 + f) * n + cs[sb]] = v[i];
                     }
                     Z[ks] = pack8(v);
@@ -626,6 +683,121 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
     if (lane == 0) unsafeAtomicAdd(loss, v);
 }
 
+// Weight gradients of the BF16 form on the matrix cores: per layer the
+// products inputs^T deltas over the batch as C[row][col] = sum_s A[row][s]
+// B[s][col], K = samples: lane l of an operand holds feature l % 32 for the
+// 8 consecutive samples 8 (l / 32) .. +7 of a 16-sample step, read straight
+// from the field-major scratch (BF16 operands, FP32 accumulation).  One wave
+// owns up to 2 x 2 output tiles of 32 x 32: W1 rows 0-63 | W1 rows 64-95 |
+// W2 | W3 columns 0-63 | W3 columns 64-98 (padded to 128), over a slice of
+// ks samples (blockIdx.y); the tiles whose rows start at 0 also sum their
+// delta columns (the bias gradients, FP32).  Partial sums go to
+// part[slice][parameter], added in slice order afterwards.
+constexpr int WB_TILES = 5;
+
+// v[e] = row[sb + e] for the samples below s_end (zero past it, and all zero
+// unless `use`); `whole`: all 8 are below s_end and 16-byte aligned.
+__device__ __forceinline__ void load8(const float *__restrict__ row, int64_t sb, int64_t s_end,
+                                      bool whole, bool use, float v[8]) {
+    if (use && whole) {
+        const float4 x = *reinterpret_cast<const float4 *>(row + sb);
+        const float4 y = *reinterpret_cast<const float4 *>(row + sb + 4);
+        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+        v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (use && sb + e < s_end) ? row[sb + e] : 0.0f;
+    }
+}
+
+__global__ __launch_bounds__(64) void wgrad_bf16_kernel(const float *__restrict__ scratch,
+                                                        int64_t n, int64_t ks,
+                                                        float *__restrict__ part) {
+    const int l = blockIdx.x / WB_TILES, tile = blockIdx.x % WB_TILES;
+    const int64_t s_begin = (int64_t)blockIdx.y * ks;
+    const int64_t s_end = s_begin + ks < n ? s_begin + ks : n;
+    int mat, r0, nrt, c0, cols;
+    switch (tile) {
+    case 0: mat = 0; r0 = 0; nrt = 2; c0 = 0; cols = HID; break;
+    case 1: mat = 0; r0 = 64; nrt = 1; c0 = 0; cols = HID; break;
+    case 2: mat = 1; r0 = 0; nrt = 2; c0 = 0; cols = HID; break;
+    case 3: mat = 2; r0 = 0; nrt = 2; c0 = 0; cols = 64; break;
+    default: mat = 2; r0 = 0; nrt = 2; c0 = 64; cols = OUT - 64; break;
+    }
+    const int lane = threadIdx.x, h = lane >> 5, idx = lane & 31;
+    const float *sc = scratch + (int64_t)l * FS * n;
+    const int bfield = mat == 0 ? FS_D1 : (mat == 1 ? FS_D2 : FS_DOUT);
+    const bool bias_tile = r0 == 0;
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = f32x16{};
+    float bsum[2] = {0.0f, 0.0f};
+    // a field row starts 16-byte aligned when n is a multiple of 4; the
+    // 8 samples of a lane then are two float4 (slices are multiples of 16)
+    const bool aligned = (n & 3) == 0;
+    for (int64_t s0 = s_begin; s0 < s_end; s0 += 16) {
+        const int64_t sb = s0 + 8 * h;
+        const bool whole = aligned && sb + 8 <= s_end;
+        bf16x8 A[2], B[2];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+            float v[8];
+            const int R = r0 + 32 * rt + idx;
+            const int field = mat == 0 ? FS_U + a_idx(l, R / BLOBS) : (mat == 1 ? FS_H1 : FS_H2) + R;
+            load8(sc + (int64_t)field * n, sb, s_end, whole, rt < nrt, v);
+            if (mat == 0) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    v[e] = (rt < nrt && sb + e < s_end) ? blob(v[e], R % BLOBS) : 0.0f;
+            }
+            A[rt] = pack8(v);
+        }
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+            float v[8];
+            const int C = 32 * ct + idx;
+            load8(sc + (int64_t)(bfield + c0 + (C < cols ? C : 0)) * n, sb, s_end, whole, C < cols,
+                  v);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) bsum[ct] += v[e];
+            B[ct] = pack8(v);
+        }
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+                if (rt < nrt)
+                    acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[rt], B[ct], acc[rt][ct],
+                                                                          0, 0, 0);
+    }
+    float *G = part + (int64_t)blockIdx.y * PARAMS + l * LP;
+    const int off = mat == 0 ? OFF_W1 : (mat == 1 ? OFF_W2 : OFF_W3);
+    const int ld = mat == 2 ? OUT : HID;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+        if (rt >= nrt) continue;
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+            const int C = 32 * ct + idx;
+            if (C >= cols) continue;
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                G[off + (r0 + 32 * rt + acc_feature(0, r, h)) * ld + c0 + C] = acc[rt][ct][r];
+        }
+    }
+    if (bias_tile) {
+        const int boff = mat == 0 ? OFF_B1 : (mat == 1 ? OFF_B2 : OFF_B3);
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+            const float tot = bsum[ct] + __shfl_xor(bsum[ct], 32);
+            const int C = 32 * ct + idx;
+            if (h == 0 && C < cols) G[boff + c0 + C] = tot;
+        }
+    }
+}
+
 template <int F>
 hipError_t launch_bf16_f(const void *frags, const float *bias, const VsArgs &A,
                          uint32_t stream_word, double *partials, uint32_t *whist, int blocks,
@@ -648,6 +820,7 @@ hipError_t launch_flow_pack_bf16(const float *theta, void *frags, float *bias, h
 }
 
 int64_t flow_bf16_bwd_frag_bytes() { return (int64_t)L * BFRAGS * 64 * sizeof(bf16x8); }
+int64_t flow_bf16_train_extra_floats(int64_t n) { return (int64_t)L * BF_EXTRA * ((n + 63) / 64 * 64); }
 
 hipError_t launch_flow_train_bf16(const float *theta, void *frags, void *bfrags, float *bias,
                                   const double *x, const double *w, int64_t n, const double *wsum,
@@ -662,10 +835,28 @@ hipError_t launch_flow_train_bf16(const float *theta, void *frags, void *bfrags,
     int64_t blocks = (n + 63) / 64;
     const int64_t cap = 8 * (int64_t)(cus > 0 ? cus : 256);
     if (blocks > cap) blocks = cap;
+    float *ext = scratch + (int64_t)L * FS * n + (int64_t)kWgradSlices * PARAMS;
     hipLaunchKernelGGL(train_bf16_kernel, dim3((unsigned)blocks), dim3(64), 0, s,
                        (const bf16x8 *)frags, (const bf16x8 *)bfrags, bias, x, w, n, wsum, scratch,
-                       loss);
+                       ext, loss);
     return hipGetLastError();
+}
+
+hipError_t launch_flow_wgrad_bf16(const float *scratch_in, int64_t n, float *grad,
+                                  hipStream_t s) {
+    float *scratch = const_cast<float *>(scratch_in);
+    // slices of at least 512 samples (a multiple of 16), at most kWgradSlices
+    int64_t slices = (n + 511) / 512;
+    if (slices > kWgradSlices) slices = kWgradSlices;
+    int64_t ks = (n + slices - 1) / slices;
+    ks = (ks + 15) / 16 * 16;
+    slices = (n + ks - 1) / ks;
+    float *part = scratch + (int64_t)L * FS * n;
+    hipLaunchKernelGGL(wgrad_bf16_kernel, dim3(L * WB_TILES, (unsigned)slices), dim3(64), 0, s,
+                       scratch, n, ks, part);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_flow_wgrad_sum(part, (int)slices, grad, s);
 }
 
 hipError_t launch_flow_sample_bf16(const void *frags, const float *bias, const double *z,

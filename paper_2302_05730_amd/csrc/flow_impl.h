@@ -37,6 +37,9 @@ static_assert(PARAMS == MCUBES_FLOW_PARAMS, "flow parameter count");
 // backward pass) and the deltas after the second and the first ReLU.
 constexpr int FS_U = 0, FS_H1 = FS_U + D, FS_H2 = FS_H1 + HID, FS_DOUT = FS_H2 + HID;
 constexpr int FS_D2 = FS_DOUT + OUT, FS_D1 = FS_D2 + HID, FS = FS_D1 + HID;
+// most sample slices the weight-gradient kernels cut a batch into (their
+// partial sums follow the fields in the scratch buffer)
+constexpr int kWgradSlices = 128;
 
 // Histogram of log2 of the flow-mapped weights (the tail diagnostic): bin
 // floor(8 log2 w) + 2048, clamped to [0, 4095]; weights that are not

@@ -156,7 +156,12 @@ hipError_t launch_flow_train_bf16(const float *theta, void *frags, void *bfrags,
                                   const double *x, const double *w, int64_t n, const double *wsum,
                                   float *scratch, double *loss, int cus, hipStream_t s);
 hipError_t launch_flow_wgrad(const float *scratch, int64_t n, float *grad, hipStream_t s);
+// the same sums on the matrix cores (BF16 operands, FP32 accumulation)
+hipError_t launch_flow_wgrad_bf16(const float *scratch, int64_t n, float *grad, hipStream_t s);
+// grad[i] <- sum over the slices of part[slice][i], in slice order
+hipError_t launch_flow_wgrad_sum(const float *part, int slices, float *grad, hipStream_t s);
 int64_t flow_bf16_bwd_frag_bytes();
+int64_t flow_bf16_train_extra_floats(int64_t n);
 hipError_t launch_flow_adam(float *theta, float *m, float *v, const float *grad, float lr,
                             float beta1, float beta2, float eps, float c1, float c2,
                             hipStream_t s);
