@@ -213,12 +213,12 @@ __device__ __forceinline__ float sample_wave(const bf16x8 *__restrict__ frags,
                 raw[k] = own[hh][t][r];
             }
             Spline s;
-            spline_setup(raw, s);
+            spline_setup<true>(raw, s);
             const int j = b_idx(l, b);
             float v, pdf;
             spline_inverse(s, getu(u, j), v, pdf);
             setu(u, j, v);
-            lq += logf(pdf);
+            lq += __logf(pdf);
         }
     }
     return lq;
@@ -550,12 +550,12 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
                 float raw[RAW];
                 raw_of(own, b, raw);
                 Spline sp;
-                spline_setup(raw, sp);
+                spline_setup<true>(raw, sp);
                 const int j = b_idx(l, b);
                 float v, pdf;
                 spline_forward(sp, getu(u, j), v, pdf);
                 setu(u, j, v);
-                lq += logf(pdf);
+                lq += __logf(pdf);
             }
         }
         lsum += live ? (double)c * (double)lq : 0.0;
@@ -595,7 +595,7 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
                 float raw[RAW];
                 raw_of(own, b, raw);
                 Spline sp;
-                spline_setup(raw, sp);
+                spline_setup<true>(raw, sp);
                 const int j = b_idx(l, b);
                 const float ub = getu(uin, j);
                 float y, pdf, gu, graw[RAW];

@@ -139,6 +139,15 @@ struct Spline {
     float W[BINS], V[BINS + 1], E[BINS + 1], Z;
 };
 
+// FAST: the hardware exponential (a few ulp instead of correctly rounded
+// to 1 ulp), for the BF16 path whose spline inputs already carry the BF16
+// products' ~1e-3 relative error.
+template <bool FAST = false>
+__device__ __forceinline__ float sexp(float x) {
+    return FAST ? __expf(x) : expf(x);
+}
+
+template <bool FAST = false>
 __device__ __forceinline__ void spline_setup(const float raw[RAW], Spline &s) {
     float mw = raw[0], mv = raw[BINS];
 #pragma unroll
@@ -148,14 +157,14 @@ __device__ __forceinline__ void spline_setup(const float raw[RAW], Spline &s) {
     float sw = 0.0f;
 #pragma unroll
     for (int i = 0; i < BINS; ++i) {
-        s.W[i] = expf(raw[i] - mw);
+        s.W[i] = sexp<FAST>(raw[i] - mw);
         sw += s.W[i];
     }
     const float inv = 1.0f / sw;
 #pragma unroll
     for (int i = 0; i < BINS; ++i) s.W[i] *= inv;
 #pragma unroll
-    for (int i = 0; i <= BINS; ++i) s.E[i] = expf(raw[BINS + i] - mv);
+    for (int i = 0; i <= BINS; ++i) s.E[i] = sexp<FAST>(raw[BINS + i] - mv);
     float Z = 0.0f;
 #pragma unroll
     for (int i = 0; i < BINS; ++i) Z += 0.5f * (s.E[i] + s.E[i + 1]) * s.W[i];
