@@ -18,7 +18,7 @@
 // values in all: W1[96][64], b1[64], W2[64][64], b2[64], W3[64][99], b3[99].
 #pragma once
 
-#include "mcubes_internal.h"
+#include "flow_internal.h"
 
 namespace mcubes {
 namespace flow {
