@@ -1,8 +1,9 @@
-// Kernels of the learned proposal (FP32, one thread per sample): density
-// and sampling of the flow, the training gradient (per-sample backward pass
-// into a scratch buffer, then the weight gradients as sums over samples),
-// Adam, the flow-mapped m-Cubes iteration and the export of one iteration's
-// own samples and weights as training data.
+// FP32 kernels of the learned proposal: density and sampling of the flow,
+// the draw of training samples and the training pass (forward, then the
+// backward pass into per-sample scratch fields), in a cooperative form with
+// eight waves per 64 samples; the weight gradients as sums over the
+// samples; Adam; the FP32 flow-mapped m-Cubes iteration (one thread per
+// cube); and the export of one plain iteration's own samples and weights.
 #include "flow_impl.h"
 #include "vsample_impl.h"
 

@@ -1,9 +1,11 @@
 // Device functions of the learned proposal: a normalizing flow of four
 // piecewise-quadratic coupling layers over (0,1)^6 (the design of "Neural
-// Importance Sampling", Müller et al. 2019), evaluated in FP32 by one thread
-// per sample.  Every lane of a wave uses the same weight at the same time:
-// kernels that take one sample per thread stage a layer's weights in LDS
-// (broadcast reads), the others read them through scalar loads.
+// Importance Sampling", Müller et al. 2019): its dimensions and parameter
+// layout, the one-blob encoding, the splines with their inverse and
+// derivative (FP32), and a one-thread-per-sample form of a whole layer
+// whose weights, the same for every lane, come through scalar loads (used
+// by the FP32 flow-mapped iteration; the other FP32 kernels split the
+// products over a workgroup, the BF16 ones run them on the matrix cores).
 //
 //   layer l keeps the coordinates A_l and maps every coordinate j of B_l
 //   through the CDF of a piecewise-linear density on (0,1) with 16 bins;
@@ -277,10 +279,9 @@ __device__ __forceinline__ void spline_backward(const Spline &s, float u, float 
     for (int k = 0; k < BINS; ++k) graw[k] = s.W[k] * (gW[k] - dot);
 }
 
-// One coupling layer on one sample, P = that layer's parameters (in LDS
-// when the caller staged them): density direction (u_B <- C(u_B)) or
-// sampling direction (u_B <- C^-1(u_B)); returns the log of the spline
-// densities met.
+// One coupling layer on one sample, P = that layer's parameters: density
+// direction (u_B <- C(u_B)) or sampling direction (u_B <- C^-1(u_B));
+// returns the log of the spline densities met.
 template <bool INVERSE>
 __device__ __forceinline__ float layer_step(const float *__restrict__ P, int l, float u[D]) {
     float ua[NA], h1[HID], h2[HID];
@@ -307,8 +308,7 @@ __device__ __forceinline__ float layer_step(const float *__restrict__ P, int l, 
 }
 
 // Sampling direction through all layers with the weights read from theta
-// (global memory, scalar loads): for kernels that cannot stage a layer at a
-// time because each thread runs whole samples in a loop.
+// (global memory, scalar loads), for a thread that runs whole samples.
 __device__ __forceinline__ float sample(const float *__restrict__ theta, float u[D]) {
     float lq = 0.0f;
 #pragma unroll 1
