@@ -433,13 +433,14 @@ int mcubes_flow_train(mcubes_flow *flow, int precision, const double *d_x, const
 int mcubes_vsample_dump(const mcubes_plan *plan, uint32_t iteration, const double *d_grid,
                         int64_t w_begin, int64_t count, double *d_x, double *d_w, void *stream);
 
-/* n unstratified samples of the flow (FP32) with weights w = f(x)/q(x) for
- * the plan's integrand (dim 6): sample i draws z from Philox counter
- * (i, stream_id | 0xC0000000, block, iteration) under the plan's seed.
- * d_x: n x 6, d_w: n (device).  Training data for refining the flow on
- * its own samples. */
-int mcubes_flow_draw(mcubes_flow *flow, const mcubes_plan *plan, uint32_t iteration, int64_t n,
-                     double *d_x, double *d_w, void *stream);
+/* n unstratified samples of the flow with weights w = f(x)/q(x) for the
+ * plan's integrand (dim 6): sample i draws z from Philox counter
+ * (i, stream_id | 0xC0000000, block, iteration) under the plan's seed and
+ * maps it through the flow in `precision` (MCUBES_FP32, or MCUBES_BF16 on
+ * the matrix cores).  d_x: n x 6, d_w: n (device).  Training data for
+ * refining the flow on its own samples. */
+int mcubes_flow_draw(mcubes_flow *flow, int precision, const mcubes_plan *plan,
+                     uint32_t iteration, int64_t n, double *d_x, double *d_w, void *stream);
 
 /* One m-Cubes iteration with the flow as the map (plan of dim 6, p >= 2):
  * cube c's sample k draws u from Philox with the plan's seed and stream word
@@ -478,7 +479,8 @@ int mcubes_flow_weight_tail(mcubes_flow *flow, double *shape, int64_t *tail_coun
  *   2. the samples and weights of train_items work items of the last of them
  *      (mcubes_vsample_dump) train the flow for `epochs` epochs;
  *   3. `rounds` times: round_samples samples of the flow itself with weights
- *      f/q (mcubes_flow_draw) train it for round_epochs epochs; then
+ *      f/q (mcubes_flow_draw, in train_precision) train it for round_epochs
+ *      epochs; then
  *      tail_rounds more such rounds with the weights raised to tail_power
  *      (> 1 stresses the samples the flow under-weights: between the
  *      Kullback-Leibler objective, power 1, and the variance, power 2) at

@@ -165,7 +165,8 @@ _SIGNATURES = {
     "mcubes_vsample_dump": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, ctypes.c_int64,
                                            ctypes.c_int64, _vp, _vp, _vp]),
     "mcubes_flow_vsample": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_uint32, _vp, _vp]),
-    "mcubes_flow_draw": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, ctypes.c_int64, _vp, _vp, _vp]),
+    "mcubes_flow_draw": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_uint32, ctypes.c_int64,
+                                        _vp, _vp, _vp]),
     "mcubes_default_flow_options": (None, [ctypes.POINTER(mcubes_flow_options)]),
     "mcubes_weight_tail_shape": (ctypes.c_int, [_vp, _dp, ctypes.POINTER(ctypes.c_int64)]),
     "mcubes_flow_weight_tail": (ctypes.c_int, [_vp, _dp, ctypes.POINTER(ctypes.c_int64)]),
@@ -549,9 +550,9 @@ class Flow:
                                        float(lr), losses, _stream(stream)))
         return list(losses)[:int(epochs)]
 
-    def draw(self, plan, iteration, n, d_x, d_w, stream=None):
-        _check(lib().mcubes_flow_draw(self.handle, plan.handle, int(iteration), int(n),
-                                      _dev(d_x, 6 * n, "x"), _dev(d_w, n, "w"),
+    def draw(self, plan, iteration, n, d_x, d_w, stream=None, precision=MCUBES_BF16):
+        _check(lib().mcubes_flow_draw(self.handle, int(precision), plan.handle, int(iteration),
+                                      int(n), _dev(d_x, 6 * n, "x"), _dev(d_w, n, "w"),
                                       _stream(stream)))
 
     def integrate(self, family, params, ncall, itmax, rel_tol, seed, options=None, **flow_opts):

@@ -422,6 +422,23 @@ __global__ void wgrad_sum_kernel(const float *__restrict__ part, int slices,
     grad[i] = a;
 }
 
+// one workgroup per minibatch: the sum of its weights (fixed order)
+__global__ __launch_bounds__(1024) void batch_wsum_kernel(const double *__restrict__ w, int64_t n,
+                                                          int64_t batch, double *__restrict__ out) {
+    __shared__ double red[1024];
+    const int64_t b0 = (int64_t)blockIdx.x * batch;
+    const int64_t b1 = b0 + batch < n ? b0 + batch : n;
+    double a = 0.0;
+    for (int64_t s = b0 + threadIdx.x; s < b1; s += 1024) a += w[s];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int h = 512; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
 __global__ void zero_u32_kernel(uint32_t *__restrict__ p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0u;
@@ -714,6 +731,14 @@ hipError_t launch_flow_wgrad(const float *scratch_in, int64_t n, float *grad, hi
                        n, ks, part);
     hipLaunchKernelGGL(wgrad_sum_kernel, dim3((PARAMS + 255) / 256), dim3(256), 0, s, part,
                        (int)slices, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_flow_batch_wsums(const double *w, int64_t n, int64_t batch, double *out,
+                                   hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_wsum_kernel, dim3((unsigned)((n + batch - 1) / batch)), dim3(1024), 0,
+                       s, w, n, batch, out);
     return hipGetLastError();
 }
 

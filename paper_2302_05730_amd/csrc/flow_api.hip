@@ -22,6 +22,8 @@ struct mcubes_flow {
     double *d_aux = nullptr;           // [0] sum of weights, [1] loss
     double *d_part = nullptr;          // per-block partials of the flow-mapped iteration
     uint32_t *d_whist = nullptr;       // log2 histogram of the last flow iteration's weights
+    double *d_wsums = nullptr;         // weight sum of each minibatch of a training call
+    int64_t wsums_cap = 0;
     hipStream_t last_stream = nullptr; // stream of the last flow iteration
     float *d_scratch = nullptr;
     int64_t scratch_n = 0;             // samples the scratch buffer holds
@@ -47,6 +49,7 @@ void release(mcubes_flow *F) {
     (void)hipFree(F->d_aux);
     (void)hipFree(F->d_part);
     (void)hipFree(F->d_whist);
+    (void)hipFree(F->d_wsums);
     (void)hipFree(F->d_scratch);
     delete F;
 }
@@ -93,15 +96,20 @@ int ensure_scratch(mcubes_flow *F, int64_t n) {
 }
 
 // One step's forward/backward pass and weight gradients (loss += its value).
+// wsum: the sum of the n weights on the device, or NULL to form it first.
 hipError_t train_step(mcubes_flow *F, int precision, const double *d_x, const double *d_w,
-                      int64_t n, double *d_loss, hipStream_t s) {
-    hipError_t e = launch_flow_wsum(d_w, n, F->d_aux, s);
+                      int64_t n, const double *wsum, double *d_loss, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    if (!wsum) {
+        e = launch_flow_wsum(d_w, n, F->d_aux, s);
+        wsum = F->d_aux;
+    }
     if (e != hipSuccess) return e;
     if (precision == MCUBES_BF16)
         e = launch_flow_train_bf16(F->d_theta, F->d_frags, F->d_bfrags, F->d_fbias, d_x, d_w, n,
-                                   F->d_aux, F->d_scratch, d_loss, F->cus, s);
+                                   wsum, F->d_scratch, d_loss, F->cus, s);
     else
-        e = launch_flow_train_fp32(F->d_theta, F->d_thetaT, d_x, d_w, n, F->d_aux, F->d_scratch,
+        e = launch_flow_train_fp32(F->d_theta, F->d_thetaT, d_x, d_w, n, wsum, F->d_scratch,
                                    d_loss, s);
     if (e != hipSuccess) return e;
     return precision == MCUBES_BF16 ? launch_flow_wgrad_bf16(F->d_scratch, n, F->d_grad, s)
@@ -212,7 +220,7 @@ int mcubes_flow_loss_grad(mcubes_flow *F, int precision, const double *d_x, cons
     rc = ensure_scratch(F, n);
     if (rc != MCUBES_OK) return rc;
     hipStream_t s = as_stream(stream);
-    hipError_t e = train_step(F, precision, d_x, d_w, n, d_loss, s);
+    hipError_t e = train_step(F, precision, d_x, d_w, n, nullptr, d_loss, s);
     // widen the kept FP32 gradient for the caller
     if (e == hipSuccess && d_grad) e = launch_flow_widen(F->d_grad, flow::PARAMS, d_grad, s);
     return e == hipSuccess ? MCUBES_OK : hip_fail(e, "flow gradient");
@@ -247,12 +255,25 @@ int mcubes_flow_train(mcubes_flow *F, int precision, const double *d_x, const do
     hipStream_t s = as_stream(stream);
     double *d_loss = F->d_aux + 1;
     F->packed = false;
+    // the weights stay fixed: every minibatch's sum once, for all epochs
+    const int64_t nb_total = (n + batch - 1) / batch;
+    if (nb_total > F->wsums_cap) {
+        (void)hipFree(F->d_wsums);
+        F->d_wsums = nullptr;
+        F->wsums_cap = 0;
+        const hipError_t ea = hipMalloc((void **)&F->d_wsums, (size_t)nb_total * sizeof(double));
+        if (ea != hipSuccess) return fail(MCUBES_E_ALLOC, "hipMalloc: %s", hipGetErrorString(ea));
+        F->wsums_cap = nb_total;
+    }
+    hipError_t ew = launch_flow_batch_wsums(d_w, n, batch, F->d_wsums, s);
+    if (ew != hipSuccess) return hip_fail(ew, "minibatch weight sums");
     for (int ep = 0; ep < epochs; ++ep) {
         hipError_t e = hipMemsetAsync(d_loss, 0, sizeof(double), s);
         int nbatch = 0;
         for (int64_t b0 = 0; b0 < n && e == hipSuccess; b0 += batch) {
             const int64_t nb = n - b0 < batch ? n - b0 : batch;
-            e = train_step(F, precision, d_x + b0 * flow::D, d_w + b0, nb, d_loss, s);
+            e = train_step(F, precision, d_x + b0 * flow::D, d_w + b0, nb, F->d_wsums + b0 / batch,
+                           d_loss, s);
             if (e == hipSuccess) {
                 F->step += 1;
                 const double c1 = 1.0 - pow(0.9, (double)F->step);
@@ -286,16 +307,26 @@ int mcubes_vsample_dump(const mcubes_plan *P, uint32_t iteration, const double *
     return e == hipSuccess ? MCUBES_OK : hip_fail(e, "sample export launch");
 }
 
-int mcubes_flow_draw(mcubes_flow *F, const mcubes_plan *P, uint32_t iteration, int64_t n,
-                     double *d_x, double *d_w, void *stream) {
+int mcubes_flow_draw(mcubes_flow *F, int precision, const mcubes_plan *P, uint32_t iteration,
+                     int64_t n, double *d_x, double *d_w, void *stream) {
     if (!F || !P || (n > 0 && (!d_x || !d_w))) return fail(MCUBES_E_ARG, "NULL argument");
     if (P->dim != flow::D) return fail(MCUBES_E_ARG, "the flow needs a plan of dim %d", flow::D);
     if (n < 0 || n > 0xFFFFFFFFll) return fail(MCUBES_E_ARG, "n must be in [0, 2^32)");
+    if (precision != MCUBES_FP32 && precision != MCUBES_BF16)
+        return fail(MCUBES_E_ARG, "precision must be MCUBES_FP32 or MCUBES_BF16");
     VsArgs A = P->args;
     A.iteration = iteration;
     const uint32_t stream_word = A.stream_id | 0xC0000000u;
-    const hipError_t e = launch_flow_draw(P->family, F->d_theta, A, stream_word, (uint32_t)n, d_x,
-                                          d_w, as_stream(stream));
+    hipStream_t s = as_stream(stream);
+    hipError_t e;
+    if (precision == MCUBES_BF16) {
+        e = ensure_packed(F, s);
+        if (e == hipSuccess)
+            e = launch_flow_draw_bf16(P->family, F->d_frags, F->d_fbias, A, stream_word,
+                                      (uint32_t)n, d_x, d_w, s);
+    } else {
+        e = launch_flow_draw(P->family, F->d_theta, A, stream_word, (uint32_t)n, d_x, d_w, s);
+    }
     return e == hipSuccess ? MCUBES_OK : hip_fail(e, "flow draw launch");
 }
 
@@ -479,7 +510,8 @@ int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int6
         const int rep_ep = fo.round_epochs < 1024 ? fo.round_epochs : 1024;
         for (int r = 0; r < fo.rounds + fo.tail_rounds; ++r) {
             const bool tail = r >= fo.rounds;
-            FI_CALL(mcubes_flow_draw(F, P, (uint32_t)(1000 + r), fo.round_samples, dx, dw, opt.stream));
+            FI_CALL(mcubes_flow_draw(F, fo.train_precision, P, (uint32_t)(1000 + r),
+                                     fo.round_samples, dx, dw, opt.stream));
             if (tail && fo.tail_power != 1.0)
                 FI_CHECK(launch_pow_weights(dw, fo.round_samples, fo.tail_power, s), "weights launch");
             if (rep_ep > 0) {

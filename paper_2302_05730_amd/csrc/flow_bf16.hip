@@ -79,9 +79,8 @@ __device__ __forceinline__ void blob8(float u, int k0, float e[8]) {
 
 // One thread per (layer, fragment, lane): the 8 BF16 weights lane `lane`
 // feeds to the matrix core, and the biases in accumulator order.
-__global__ void pack_kernel(const float *__restrict__ theta, bf16x8 *__restrict__ frags,
-                            float *__restrict__ bias) {
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void pack_fwd(int gid, const float *__restrict__ theta,
+                                         bf16x8 *__restrict__ frags, float *__restrict__ bias) {
     if (gid < L * BIAS) {
         const int l = gid / BIAS, q = gid % BIAS;
         const float *P = theta + l * LP;
@@ -116,6 +115,11 @@ __global__ void pack_kernel(const float *__restrict__ theta, bf16x8 *__restrict_
         }
     }
     frags[gid] = pack8(v);
+}
+
+__global__ void pack_kernel(const float *__restrict__ theta, bf16x8 *__restrict__ frags,
+                            float *__restrict__ bias) {
+    pack_fwd(blockIdx.x * blockDim.x + threadIdx.x, theta, frags, bias);
 }
 
 // 64 samples through the inverse flow: lane s holds sample s in u[] and
@@ -332,6 +336,44 @@ __global__ __launch_bounds__(256) void flow_vsample_bf16_kernel(const bf16x8 *__
     wh_flush(hist, whist);
 }
 
+// n plain (unstratified) samples of the flow on the matrix cores with their
+// weights w = f / q: sample i draws z from Philox counter (i, stream word,
+// block, iteration), as the FP32 draw does; 64 samples per wave, lanes past
+// n work on a copy of the last sample and store nothing.
+template <int F>
+__global__ __launch_bounds__(256) void flow_draw_bf16_kernel(const bf16x8 *__restrict__ frags,
+                                                             const float *__restrict__ bias,
+                                                             const VsArgs A, uint32_t stream_word,
+                                                             uint32_t n, double *__restrict__ xs,
+                                                             double *__restrict__ ws) {
+    constexpr int NBLK = (D + 3) / 4;
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    const uint64_t wid = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    for (uint64_t base = wid * 64; base < n; base += waves * 64) {
+        const bool live = base + lane < n;
+        const uint32_t i = live ? (uint32_t)(base + lane) : n - 1;
+        float u[D];
+#pragma unroll
+        for (int b = 0; b < NBLK; ++b) {
+            uint32_t r[4];
+            philox10(i, stream_word, b, A.iteration, A.key0, A.key1, r);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (4 * b + t < D) u[4 * b + t] = (float)__fma_rn((double)r[t], 0x1p-32, 0x1p-33);
+        }
+        const float lq = sample_wave(frags, bias, u);
+        if (!live) continue;
+        Acc acc = Family<F, D>::begin(A.phase);
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            Family<F, D>::axis(acc, A.ca[j], A.cu[j], (double)u[j]);
+            xs[(uint64_t)i * D + j] = (double)u[j];
+        }
+        ws[i] = Family<F, D>::end(acc, A) / exp((double)lq);
+    }
+}
+
 // ---------------------------------------------------------------------
 // Training on the matrix cores.  The backward pass runs the three products
 // through the transposed weights in the same orientation (features = rows,
@@ -344,8 +386,8 @@ constexpr int B3T = 2, B3K = 7, B2T = 2, B2K = 4, B1T = 3, B1K = 4;
 constexpr int OFF_B3F = 0, OFF_B2F = OFF_B3F + B3T * B3K, OFF_B1F = OFF_B2F + B2T * B2K;
 constexpr int BFRAGS = OFF_B1F + B1T * B1K;  // 34
 
-__global__ void pack_bwd_kernel(const float *__restrict__ theta, bf16x8 *__restrict__ frags) {
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void pack_bwd(int gid, const float *__restrict__ theta,
+                                         bf16x8 *__restrict__ frags) {
     if (gid >= L * BFRAGS * 64) return;
     const int lane = gid % 64, fr = (gid / 64) % BFRAGS, l = gid / (64 * BFRAGS);
     const float *P = theta + l * LP;
@@ -367,6 +409,17 @@ __global__ void pack_bwd_kernel(const float *__restrict__ theta, bf16x8 *__restr
             v[e] = P[OFF_W1 + r * HID + acc_feature(ks / 2, 8 * (ks % 2) + e, h)];
     }
     frags[gid] = pack8(v);
+}
+
+// forward and backward fragments (and biases) in one launch: threads
+// [0, nf) pack the forward ones, the rest the backward ones
+__global__ void pack_train_kernel(const float *__restrict__ theta, bf16x8 *__restrict__ frags,
+                                  float *__restrict__ bias, bf16x8 *__restrict__ bfrags, int nf) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid < nf)
+        pack_fwd(gid, theta, frags, bias);
+    else
+        pack_bwd(gid - nf, theta, bfrags);
 }
 
 // lane < 32 gets (a of lane, a of lane + 32), lane >= 32 (b of lane - 32,
@@ -842,11 +895,10 @@ int64_t flow_bf16_train_extra_floats(int64_t n) { return (int64_t)L * BF_EXTRA *
 hipError_t launch_flow_train_bf16(const float *theta, void *frags, void *bfrags, float *bias,
                                   const double *x, const double *w, int64_t n, const double *wsum,
                                   float *scratch, double *loss, int cus, hipStream_t s) {
+    // the forward part covers the bias entries too (L BIAS < L FRAGS 64)
     const int nf = L * FRAGS * 64, nb = L * BFRAGS * 64;
-    hipLaunchKernelGGL(pack_kernel, dim3((nf + 255) / 256), dim3(256), 0, s, theta,
-                       (bf16x8 *)frags, bias);
-    hipLaunchKernelGGL(pack_bwd_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, theta,
-                       (bf16x8 *)bfrags);
+    hipLaunchKernelGGL(pack_train_kernel, dim3((nf + nb + 255) / 256), dim3(256), 0, s, theta,
+                       (bf16x8 *)frags, bias, (bf16x8 *)bfrags, nf);
     // one single-wave workgroup per 64 samples (spread over every CU), at
     // most 8 per CU
     int64_t blocks = (n + 63) / 64;
@@ -874,6 +926,34 @@ hipError_t launch_flow_wgrad_bf16(const float *scratch_in, int64_t n, float *gra
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_flow_wgrad_sum(part, (int)slices, grad, s);
+}
+
+template <int F>
+hipError_t launch_draw_bf16_f(const void *frags, const float *bias, const VsArgs &A,
+                              uint32_t stream_word, uint32_t n, double *xs, double *ws,
+                              hipStream_t s) {
+    int64_t blocks = ((int64_t)n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL((flow_draw_bf16_kernel<F>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       (const bf16x8 *)frags, bias, A, stream_word, n, xs, ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_flow_draw_bf16(int family, const void *frags, const float *bias,
+                                 const VsArgs &A, uint32_t stream_word, uint32_t n, double *xs,
+                                 double *ws, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    switch (family) {
+    case MCUBES_OSCILLATORY: return launch_draw_bf16_f<MCUBES_OSCILLATORY>(frags, bias, A, stream_word, n, xs, ws, s);
+    case MCUBES_PRODUCT_PEAK: return launch_draw_bf16_f<MCUBES_PRODUCT_PEAK>(frags, bias, A, stream_word, n, xs, ws, s);
+    case MCUBES_CORNER_PEAK: return launch_draw_bf16_f<MCUBES_CORNER_PEAK>(frags, bias, A, stream_word, n, xs, ws, s);
+    case MCUBES_GAUSSIAN: return launch_draw_bf16_f<MCUBES_GAUSSIAN>(frags, bias, A, stream_word, n, xs, ws, s);
+    case MCUBES_C0: return launch_draw_bf16_f<MCUBES_C0>(frags, bias, A, stream_word, n, xs, ws, s);
+    case MCUBES_DISCONTINUOUS: return launch_draw_bf16_f<MCUBES_DISCONTINUOUS>(frags, bias, A, stream_word, n, xs, ws, s);
+    case MCUBES_ADDITION: return launch_draw_bf16_f<MCUBES_ADDITION>(frags, bias, A, stream_word, n, xs, ws, s);
+    case MCUBES_MIXTURE: return launch_draw_bf16_f<MCUBES_MIXTURE>(frags, bias, A, stream_word, n, xs, ws, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_flow_sample_bf16(const void *frags, const float *bias, const double *z,

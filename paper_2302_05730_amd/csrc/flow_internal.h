@@ -57,6 +57,13 @@ int64_t flow_bf16_bias_floats();
 hipError_t launch_flow_pack_bf16(const float *theta, void *frags, float *bias, hipStream_t s);
 hipError_t launch_flow_sample_bf16(const void *frags, const float *bias, const double *z,
                                    int64_t n, double *x, double *logq, hipStream_t s);
+hipError_t launch_flow_draw_bf16(int family, const void *frags, const float *bias,
+                                 const VsArgs &A, uint32_t stream_word, uint32_t n, double *xs,
+                                 double *ws, hipStream_t s);
+// sums of the consecutive minibatches [k batch, (k + 1) batch) of w, one
+// per entry of out (ceil(n / batch) of them)
+hipError_t launch_flow_batch_wsums(const double *w, int64_t n, int64_t batch, double *out,
+                                   hipStream_t s);
 hipError_t launch_flow_vsample_bf16(int family, const void *frags, const float *bias,
                                     const VsArgs &A, uint32_t stream_word, double *partials,
                                     uint32_t *whist, int blocks, hipStream_t s);

@@ -225,6 +225,36 @@ def test_flow_iteration_weight_tail(mc):
             assert lo < shape < hi
 
 
+def test_bf16_draw_follows_the_fp32_draw(mc):
+    """Training samples drawn on the matrix cores use the same counters as
+    the FP32 draw: the same z, mapped with BF16 products, so the points agree
+    to the BF16 sampling tolerance (99% within 2e-3, all within 2e-2) and
+    the weights f/q of a smooth integrand to a few 1e-3 (99% within 1e-2
+    relative); the ragged tail of a wave is drawn as well."""
+    import torch
+    theta = _f32(workloads.flow_random(5, out_scale=0.3))
+    fl = mc.Flow(theta)
+    params = [2.0] * 6 + [0.4, 0.5, 0.6, 0.45, 0.55, 0.5]
+    plan = mc.mcubes_plan_create(workloads.GAUSSIAN, params, 6, 1 << 16, 9,
+                                 mc.mcubes_default_options(nbins=50))
+    n = 5000
+    out = {}
+    for prec in (mc.MCUBES_FP32, mc.MCUBES_BF16):
+        d_x = torch.zeros(n * 6, dtype=torch.float64, device="cuda")
+        d_w = torch.zeros(n, dtype=torch.float64, device="cuda")
+        fl.draw(plan, 77, n, d_x, d_w, precision=prec)
+        torch.cuda.synchronize()
+        out[prec] = (d_x.cpu().numpy().reshape(n, 6), d_w.cpu().numpy())
+    (x32, w32), (x16, w16) = out[mc.MCUBES_FP32], out[mc.MCUBES_BF16]
+    dx = np.abs(x16 - x32).max(axis=1)
+    dw = np.abs(w16 / w32 - 1.0)
+    _say(f"bf16 draw: |dx| 99% {np.quantile(dx, 0.99):.1e} max {dx.max():.1e}; "
+         f"|dw/w| 99% {np.quantile(dw, 0.99):.1e}")
+    assert np.all(w32 > 0) and np.all(w16 > 0)
+    assert np.quantile(dx, 0.99) <= 2e-3 and dx.max() <= 2e-2
+    assert np.quantile(dw, 0.99) <= 1e-2
+
+
 def test_sample_export_is_the_iterations_own_samples(mc):
     """The exported samples of an iteration: every weight and point of a few
     cubes against the oracle's own map (bitwise), and the sum of all weights
