@@ -507,11 +507,11 @@ typedef struct {
     int64_t round_samples; /* default 2^22 */
     int32_t round_epochs;  /* default 2 */
     int32_t tail_rounds;   /* default 2 */
-    int64_t batch;         /* default 32768 */
-    double lr;             /* default 2e-3 */
-    double round_lr;       /* default 1e-3 */
+    int64_t batch;         /* default 65536 */
+    double lr;             /* default 4e-3 */
+    double round_lr;       /* default 2e-3 */
     double tail_power;     /* default 1.5 */
-    double tail_lr;        /* default 4e-4 */
+    double tail_lr;        /* default 8e-4 */
     int32_t train_precision; /* training products: MCUBES_BF16 (default) or MCUBES_FP32 */
     int32_t reserved;
 } mcubes_flow_options;

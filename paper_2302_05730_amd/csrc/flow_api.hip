@@ -409,11 +409,11 @@ void mcubes_default_flow_options(mcubes_flow_options *o) {
     o->round_samples = (int64_t)1 << 22;
     o->round_epochs = 2;
     o->tail_rounds = 2;
-    o->batch = 32768;
-    o->lr = 2e-3;
-    o->round_lr = 1e-3;
+    o->batch = 65536;
+    o->lr = 4e-3;
+    o->round_lr = 2e-3;
     o->tail_power = 1.5;
-    o->tail_lr = 4e-4;
+    o->tail_lr = 8e-4;
     o->train_precision = MCUBES_BF16;
 }
 
