@@ -476,8 +476,11 @@ int mcubes_flow_weight_tail(mcubes_flow *flow, double *shape, int64_t *tail_coun
 
 /* The whole learned-proposal pipeline for one integrand of dim 6:
  *   1. warmup_iters plain m-Cubes iterations (grid refined every time);
- *   2. the samples and weights of train_items work items of the last of them
- *      (mcubes_vsample_dump) train the flow for `epochs` epochs;
+ *   2. the samples and weights of train_items work items, an equal share
+ *      from each of them (mcubes_vsample_dump with that iteration's grid),
+ *      train the flow for `epochs` epochs.  The early iterations' broad
+ *      grids keep every peak of f in the data: on a multimodal integrand a
+ *      separable map can settle on one peak within a few iterations;
  *   3. `rounds` times: round_samples samples of the flow itself with weights
  *      f/q (mcubes_flow_draw, in train_precision) train it for round_epochs
  *      epochs; then
@@ -490,7 +493,10 @@ int mcubes_flow_weight_tail(mcubes_flow *flow, double *shape, int64_t *tail_coun
  *      itmax of them.
  * Plain m-Cubes stays the judge: if the first flow iteration's variance is
  * not below the last plain iteration's, the flow is dropped and the
- * remaining iterations run plain (report->used_flow = 0).  `flow` is trained
+ * remaining iterations run plain (report->used_flow = 0).  A flow result
+ * whose weight-tail shape (report->tail_shape, the largest over its
+ * iterations) reaches 0.5 is never reported converged: its error bar has
+ * no meaning (see mcubes_weight_tail_shape).  `flow` is trained
  * in place (start from an identity flow for a fresh run).  out receives the
  * combined result of the iterations that decide it (flow, or plain on
  * fallback).  Synchronous; allocates its buffers.
@@ -501,7 +507,7 @@ int mcubes_flow_weight_tail(mcubes_flow *flow, double *shape, int64_t *tail_coun
 typedef struct {
     int32_t warmup_iters;  /* default 8 */
     int32_t precision;     /* proposal iterations: MCUBES_BF16 (default) or MCUBES_FP32 */
-    int64_t train_items;   /* default 2^20 (each gives p samples) */
+    int64_t train_items;   /* default 2^20 over all warm-up iterations (each gives p samples) */
     int32_t epochs;        /* default 10 */
     int32_t rounds;        /* default 6 */
     int64_t round_samples; /* default 2^22 */

@@ -35,6 +35,7 @@ namespace {
 
 constexpr int64_t kMaxSamples = (int64_t)1 << 31;
 constexpr int kVsBlocks = 2048;  // workgroups of the flow-mapped iteration (grid-stride)
+constexpr double kTailLimit = 0.5;  // weight-tail shape from which the variance is infinite
 
 void release(mcubes_flow *F) {
     if (!F) return;
@@ -446,7 +447,10 @@ int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int6
     hipStream_t s = as_stream(opt.stream);
     const int64_t ng = (int64_t)P->dim * (P->nb + 1), nbn = (int64_t)P->dim * P->nb;
     const int64_t items = fo.train_items < P->m ? fo.train_items : P->m;
-    const int64_t rows = items * P->p;
+    // training rows: an equal share of the items from each warm-up iteration
+    const int64_t per_it = items / fo.warmup_iters > 0 ? items / fo.warmup_iters : 1;
+    const int64_t rows = per_it * P->p * fo.warmup_iters;
+    int64_t trows = 0;
     const int64_t drows = rows > fo.round_samples ? rows : fo.round_samples;
     const int64_t total = 2 * ng + nbn + 2 * (int64_t)P->blocks + 2 + 2 * MCUBES_STATE_LEN +
                           7 * drows;
@@ -489,21 +493,29 @@ int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int6
     // 1. plain warm-up iterations
     FI_CHECK(launch_init_grid(grid[0], P->dim, P->nb, s), "init_grid launch");
     FI_CHECK(launch_fill(st_plain, 2 * MCUBES_STATE_LEN, 0.0, s), "fill launch");
-    for (int t = 0; t < fo.warmup_iters; ++t)
+    // The training samples: an equal share of the work items from every
+    // warm-up iteration, taken with that iteration's grid right after it
+    // (the next iteration overwrites that grid).  Each share is an unbiased
+    // weighted sample of f; the early, still broad grids reach every mode,
+    // which the later ones may have given up (a separable map can settle on
+    // one of several peaks).
+    for (int t = 0; t < fo.warmup_iters; ++t) {
         FI_CALL(mcubes_iteration(P, (uint32_t)t, grid[t & 1], grid[(t + 1) & 1], bins, partials, est,
                                  st_plain, 0.0, opt.stream));
+        FI_CALL(mcubes_vsample_dump(P, (uint32_t)t, grid[t & 1], 0, per_it, dx + trows * flow::D,
+                                    dw + trows, opt.stream));
+        trows += per_it * P->p;
+    }
     FI_CHECK(hipMemcpyAsync(&R.last_plain_var, est + 1, sizeof(double), hipMemcpyDeviceToHost, s),
              "hipMemcpyAsync");
     FI_CHECK(hipMemcpyAsync(head, st_plain, sizeof head, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
     FI_CHECK(hipEventRecord(ev[1], s), "hipEventRecord");
-    // 2-3. training on the last warm-up iteration's samples, then on the flow's own
-    FI_CALL(mcubes_vsample_dump(P, (uint32_t)(fo.warmup_iters - 1), grid[(fo.warmup_iters - 1) & 1],
-                                0, items, dx, dw, opt.stream));
+    // 2-3. training on the warm-up's samples, then on the flow's own
     {
         double losses[1024];
         const int ep = fo.epochs < 1024 ? fo.epochs : 1024;
         if (ep > 0) {
-            FI_CALL(mcubes_flow_train(F, fo.train_precision, dx, dw, rows, ep, fo.batch, fo.lr,
+            FI_CALL(mcubes_flow_train(F, fo.train_precision, dx, dw, trows, ep, fo.batch, fo.lr,
                                       losses, opt.stream));
             R.final_loss = losses[ep - 1];
         }
@@ -584,7 +596,9 @@ int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int6
     out->chi2_dof = head[2];
     out->dof = (int32_t)head[3];
     out->iterations = (int32_t)head[4];
-    out->converged = head[5] != 0.0;
+    // the error bar of flow iterations whose weights have no finite
+    // variance (tail shape >= 1/2) means nothing: never call that converged
+    out->converged = head[5] != 0.0 && !(used && R.tail_shape >= kTailLimit);
     out->cube_side = P->g;
     out->ncubes = P->m;
     out->samples_per_cube = P->p;
