@@ -542,6 +542,91 @@ __global__ __launch_bounds__(256) void flow_vsample_kernel(const float *__restri
     wh_flush(hist, whist);
 }
 
+// The FP32 flow-mapped iteration in the cooperative form, for p dividing
+// 64: each pass of a workgroup takes 64 consecutive samples q (cube q / p,
+// sample q % p), so the p samples of a cube sit in one wave; the same
+// counters and map as flow_vsample_kernel, the flow run by the eight waves
+// together, and the per-cube sums by butterfly shuffles in wave 0.
+template <int F>
+__global__ __launch_bounds__(CT) void flow_vsample_coop_kernel(const float *__restrict__ theta,
+                                                               const VsArgs A,
+                                                               uint32_t stream_word,
+                                                               double *__restrict__ partials,
+                                                               uint32_t *__restrict__ whist) {
+    constexpr int NBLK = (D + 3) / 4;
+    __shared__ Coop S;
+    __shared__ uint32_t hist[WH_BINS];
+    wh_clear(hist);
+    const int q = wave_index(), lane = threadIdx.x % CS;
+    const uint64_t N = (uint64_t)A.m * A.p;
+    const int p = (int)A.p;
+    double tS = 0.0, tV = 0.0;
+    for (uint64_t base = (uint64_t)blockIdx.x * CS; base < N; base += (uint64_t)gridDim.x * CS) {
+        const uint64_t qs = base + lane;
+        const bool live = qs < N;  // N is a multiple of p: a cube is live or not as a whole
+        if (q == 0) {
+            const uint32_t c = live ? (uint32_t)(qs / p) : 0u;
+            const uint32_t k = live ? (uint32_t)(qs % p) : 0u;
+            uint32_t rest = c;
+#pragma unroll
+            for (int b = 0; b < NBLK; ++b) {
+                uint32_t r[4];
+                philox10(c, stream_word, k * NBLK + b, A.iteration, A.key0, A.key1, r);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int j = 4 * b + i;
+                    if (j < D) {
+                        const double dig = (double)(rest % A.g);
+                        rest /= A.g;
+                        const double uu = __fma_rn((double)r[i], 0x1p-32, 0x1p-33);
+                        S.U[0][j * CS + lane] = (float)((dig + uu) / (double)A.g);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int step = 0; step < L; ++step)
+            coop_layer<true, false>(theta + (L - 1 - step) * LP, L - 1 - step, step, q, lane, S,
+                                    nullptr, 0, live);
+        if (q == 0) {
+            double w = 0.0;
+            if (live) {
+                Acc acc = Family<F, D>::begin(A.phase);
+#pragma unroll
+                for (int j = 0; j < D; ++j)
+                    Family<F, D>::axis(acc, A.ca[j], A.cu[j], (double)S.U[L][j * CS + lane]);
+                w = Family<F, D>::end(acc, A) / exp((double)coop_logq(S, lane));
+                wh_add(hist, w);
+            }
+            // per-cube sums over the p lanes of the cube, shifted by its first sample
+            const int first = lane - (lane % p);
+            const double w0 = __shfl(w, first);
+            const double dlt = w - w0;
+            double Sc = w, D1 = dlt, D2 = dlt * dlt;
+            for (int off = 1; off < p; off <<= 1) {
+                Sc += __shfl_xor(Sc, off);
+                D1 += __shfl_xor(D1, off);
+                D2 += __shfl_xor(D2, off);
+            }
+            if (live && lane == first) {
+                tS += Sc;
+                tV += (D2 - D1 * D1 * A.inv_p) * A.inv_pm1;
+            }
+        }
+        __syncthreads();  // S is reused by the next pass
+    }
+    if (q == 0) {
+        tS = wave_sum(tS);
+        tV = wave_sum(tV);
+        if (lane == 0) {
+            partials[2 * blockIdx.x] = tS;
+            partials[2 * blockIdx.x + 1] = tV;
+        }
+    }
+    wh_flush(hist, whist);
+}
+
 // The samples of work items [w0, w0 + count) of one plain iteration (cube
 // (w mult) mod m, the order in which V-Sample's threads visit the cubes, so
 // that a prefix of the work items is spread over the whole domain), with
@@ -648,8 +733,12 @@ hipError_t launch_flow_draw_f(const float *theta, const VsArgs &A, uint32_t stre
 template <int F>
 hipError_t launch_flow_vsample_f(const float *theta, const VsArgs &A, uint32_t stream_word,
                                  double *partials, uint32_t *whist, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL((flow_vsample_kernel<F>), dim3(blocks), dim3(256), 0, s, theta, A,
-                       stream_word, partials, whist);
+    if (64 % A.p == 0)
+        hipLaunchKernelGGL((flow_vsample_coop_kernel<F>), dim3(blocks), dim3(CT), 0, s, theta, A,
+                           stream_word, partials, whist);
+    else
+        hipLaunchKernelGGL((flow_vsample_kernel<F>), dim3(blocks), dim3(256), 0, s, theta, A,
+                           stream_word, partials, whist);
     return hipGetLastError();
 }
 

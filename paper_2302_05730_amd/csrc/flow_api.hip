@@ -356,8 +356,10 @@ int mcubes_flow_vsample(mcubes_flow *F, int precision, const mcubes_plan *P, uin
             e = launch_flow_vsample_bf16(P->family, F->d_frags, F->d_fbias, A, stream_word,
                                          F->d_part, F->d_whist, blocks, s);
     } else {
-        blocks = (int)((P->m + 255) / 256);
-        if (blocks > kVsBlocks) blocks = kVsBlocks;
+        // cooperative form for p dividing 64 (64 samples per workgroup pass),
+        // else one cube per thread
+        const int64_t groups = 64 % P->p == 0 ? (P->m * P->p + 63) / 64 : (P->m + 255) / 256;
+        blocks = groups < kVsBlocks ? (int)groups : kVsBlocks;
         if (e == hipSuccess)
             e = launch_flow_vsample(P->family, F->d_theta, A, stream_word, F->d_part, F->d_whist,
                                     blocks, s);
