@@ -170,3 +170,38 @@ def test_batch_create_rejects(items, opt, code):
     msg = mc.mcubes_last_error()
     if len(items) > 1:
         assert f"item {len(items) - 1}" in msg, msg
+
+
+def test_flow_entry_points_reject_bad_arguments():
+    """Checks that return before any device work: NULL objects and buffers,
+    non-finite parameters, unknown precisions."""
+    L = mc.lib()
+    E = mc.MCUBES_E_ARG
+    out = ctypes.c_void_p()
+    assert L.mcubes_flow_create(None, ctypes.byref(out)) == E
+    theta = (ctypes.c_double * mc.MCUBES_FLOW_PARAMS)()
+    theta[5] = float("nan")
+    assert L.mcubes_flow_create(theta, ctypes.byref(out)) == E
+    assert L.mcubes_flow_train(None, mc.MCUBES_BF16, None, None, 10, 1, 16, 1e-3, None, None) == E
+    assert L.mcubes_flow_loss_grad(None, mc.MCUBES_FP32, None, None, 10, None, None, None) == E
+    assert L.mcubes_flow_draw(None, mc.MCUBES_BF16, None, 0, 10, None, None, None) == E
+    assert L.mcubes_flow_vsample(None, mc.MCUBES_BF16, None, 0, None, None) == E
+    assert L.mcubes_flow_density(None, mc.MCUBES_FP32, None, 1, None, None, None) == E
+    assert L.mcubes_flow_sample(None, mc.MCUBES_FP32, None, 1, None, None, None) == E
+    assert L.mcubes_flow_weight_tail(None, None, None) == E
+    assert L.mcubes_weight_tail_shape(None, None, None) == E
+    res = mc.mcubes_result()
+    assert L.mcubes_flow_integrate(None, mc.MCUBES_MIXTURE, None,
+                                   1 << 20, 4, 0.0, 1, None, None, ctypes.byref(res),
+                                   None) == E
+    assert L.mcubes_last_error()
+
+
+def test_default_flow_options():
+    fo = mc.mcubes_flow_options()
+    mc.lib().mcubes_default_flow_options(ctypes.byref(fo))
+    assert (fo.warmup_iters, fo.train_items, fo.epochs, fo.rounds, fo.round_samples,
+            fo.round_epochs, fo.tail_rounds, fo.batch) == (8, 1 << 20, 10, 6, 1 << 22, 2, 2,
+                                                           65536)
+    assert (fo.lr, fo.round_lr, fo.tail_power, fo.tail_lr) == (4e-3, 2e-3, 1.5, 8e-4)
+    assert fo.precision == mc.MCUBES_BF16 and fo.train_precision == mc.MCUBES_BF16
