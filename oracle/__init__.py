@@ -96,6 +96,8 @@ def lib():
                                      ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,
                                      ctypes.c_int64, _dp]
     L.mcf_proposal_range.restype = ctypes.c_int
+    L.mcf_combine_equal.argtypes = [ctypes.c_int, _dp, _dp, _dp]
+    L.mcf_combine_equal.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -311,3 +313,13 @@ def flow_proposal_range(theta, family, params, g, m, p, seed, stream, iteration,
     if rc != 0:
         raise ValueError("mcf_proposal_range failed")
     return float(sums[0]), float(sums[1])
+
+
+def flow_combine(I, var):
+    """Equal-weight combination of flow-mapped iterations -> (Ibar, sigma,
+    chi2_dof, dof)."""
+    I, ip = _d(I)
+    var, vp = _d(var)
+    out = np.zeros(3)
+    dof = lib().mcf_combine_equal(len(I), ip, vp, out.ctypes.data_as(_dp))
+    return float(out[0]), float(out[1]), float(out[2]), int(dof)

@@ -469,3 +469,42 @@ int mcf_proposal_range(const double *theta, int use_bf16, int family, const doub
     sums[1] = vs + vc;
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Combination of flow-mapped iterations t = 0..T-1.  Every one of them     */
+/* samples the same fixed proposal with the same number of points, so the   */
+/* estimates are independent draws of one distribution and the plain mean   */
+/* is the unbiased combination (weighting by the estimated variances, as    */
+/* VEGAS does for iterations whose map changes, favours the iterations that */
+/* missed the rare large weights):                                          */
+/*   Ibar = sum(I_t) / T,  sigma = sqrt(sum v_t) / T,                        */
+/*   chi2/dof = sum over v_t > 0 of (I_t - Ibar)^2 / v_t, over (T - 1)        */
+/*   (0 when T = 1).                                                         */
+/* out = [Ibar, sigma, chi2/dof]; returns the degrees of freedom T - 1.      */
+/* ------------------------------------------------------------------------ */
+int mcf_combine_equal(int T, const double *I, const double *var, double out[3])
+{
+    if (T < 1) {
+        out[0] = 0.0;
+        out[1] = INFINITY;
+        out[2] = 0.0;
+        return 0;
+    }
+    double si = 0.0, sv = 0.0;
+    for (int t = 0; t < T; ++t) {
+        si = si + I[t];
+        sv = sv + var[t];
+    }
+    const double Ibar = si / (double)T;
+    double chi2 = 0.0;
+    for (int t = 0; t < T; ++t) {
+        if (var[t] > 0.0) {
+            const double dv = I[t] - Ibar;
+            chi2 = chi2 + dv * dv / var[t];
+        }
+    }
+    out[0] = Ibar;
+    out[1] = sqrt(sv) / (double)T;
+    out[2] = (T > 1) ? chi2 / (double)(T - 1) : 0.0;
+    return T - 1;
+}

@@ -2,7 +2,8 @@
  * flow_oracle.h -- TEST INFRASTRUCTURE, not part of the product.
  * Plain FP64 reference of the learned proposal: a normalizing flow of
  * piecewise-quadratic coupling layers over (0,1)^6, its training loss and
- * gradient, one Adam step, and an m-Cubes iteration that samples through it.
+ * gradient, one Adam step, an m-Cubes iteration that samples through it and
+ * the equal-weight combination of such iterations.
  * See flow_oracle.c for the definitions.
  */
 #ifndef FLOW_ORACLE_H
@@ -41,5 +42,6 @@ void mcf_adam(double *theta, double *m, double *v, const double *grad, int64_t c
 int mcf_proposal_range(const double *theta, int bf16, int family, const double *params, int64_t g,
                        int64_t m, int64_t p, uint64_t seed, uint32_t stream, uint32_t iteration,
                        int64_t c_begin, int64_t c_end, double sums[2]);
+int mcf_combine_equal(int T, const double *I, const double *var, double out[3]);
 
 #endif

@@ -35,3 +35,66 @@ def test_identical_iterations_have_zero_chi2():
 def test_exact_iteration_dominates():
     Ibar, sigma, chi2, dof = oracle.combine([1.0, 7.0, 1.5], [1.0, 0.0, 2.0])
     assert Ibar == 7.0 and sigma == 0.0
+
+
+# --- equal-weight combination of flow-mapped iterations ---------------------
+# Every flow-mapped iteration samples one fixed proposal with the same number
+# of points, so the estimates are independent draws of one distribution: the
+# plain mean is unbiased and its variance is sum(var_t) / T^2.
+
+
+def test_flow_combine_hand_example():
+    # I = (1, 2, 4), var = (1, 1, 4): Ibar = 7/3, sigma = sqrt(6)/3,
+    # chi2 = (4/3)^2 + (1/3)^2 + (5/3)^2/4 = 31/12, chi2/dof = 31/24
+    Ibar, sigma, chi2, dof = oracle.flow_combine([1.0, 2.0, 4.0], [1.0, 1.0, 4.0])
+    assert Ibar == pytest.approx(float(Fraction(7, 3)), rel=1e-15)
+    assert sigma == pytest.approx(6 ** 0.5 / 3, rel=1e-15)
+    assert chi2 == pytest.approx(float(Fraction(31, 24)), rel=1e-14)
+    assert dof == 2
+
+
+def test_flow_combine_equal_variances_reduce_to_inverse_variance():
+    I = [0.9, 1.3, 1.05, 0.7, 1.2]
+    v = [0.04] * 5
+    a = oracle.flow_combine(I, v)
+    b = oracle.combine(I, v)
+    assert a[3] == b[3]
+    for x, y in zip(a[:3], b[:3]):
+        assert x == pytest.approx(y, rel=1e-14)
+
+
+def test_flow_combine_single_and_empty():
+    assert oracle.flow_combine([3.25], [0.0625]) == (3.25, 0.25, 0.0, 0)
+    Ibar, sigma, chi2, dof = oracle.flow_combine([], [])
+    assert (Ibar, chi2, dof) == (0.0, 0.0, 0) and sigma == float("inf")
+    # an exact iteration (var 0) adds nothing to chi2 and its share of sigma is 0
+    Ibar, sigma, chi2, dof = oracle.flow_combine([2.0, 4.0], [0.0, 1.0])
+    assert (Ibar, sigma, dof) == (3.0, 0.5, 1) and chi2 == 1.0
+
+
+def test_flow_combine_is_unbiased_on_heavy_tailed_iterations():
+    """Iterations = means of 200 log-normal(0, 1.5) draws (mean e^1.125, a
+    long right tail like importance weights).  Over 3000 repetitions of 8
+    iterations the equal-weight mean is unbiased and the mean of sigma^2
+    matches the scatter of Ibar (E sigma^2 = Var Ibar exactly), while the
+    inverse-variance mean is far too low: an iteration that caught a large
+    draw also has a large variance estimate and is weighted down."""
+    import math
+    import numpy as np
+
+    rng = np.random.default_rng(5)
+    mu = math.exp(1.5 ** 2 / 2)
+    eq, ivw, s2 = [], [], []
+    for _ in range(3000):
+        x = rng.lognormal(0.0, 1.5, size=(8, 200))
+        I = x.mean(1)
+        v = x.var(1, ddof=1) / 200
+        a = oracle.flow_combine(I, v)
+        eq.append(a[0] - mu)
+        s2.append(a[1] ** 2)
+        ivw.append(oracle.combine(I, v)[0] - mu)
+    eq, ivw = np.array(eq), np.array(ivw)
+    se = eq.std() / len(eq) ** 0.5
+    assert abs(eq.mean()) < 4 * se
+    assert np.mean(s2) / eq.var() == pytest.approx(1.0, abs=0.15)
+    assert ivw.mean() < -20 * se
