@@ -424,6 +424,16 @@ int mcubes_flow_train(mcubes_flow *flow, int precision, const double *d_x, const
                       int64_t n, int epochs, int64_t batch, double lr, double *losses,
                       void *stream);
 
+/* Shuffles n training rows (x: n x 6, w: n; device) into (d_x_out, d_w_out):
+ * output row j is input row (a j) mod n, a the odd number at or above
+ * n (sqrt(5) - 1)/2 stepped until coprime to n.  A permutation whose
+ * consecutive outputs lie about 0.618 n apart, so every mini-batch of
+ * mcubes_flow_train (consecutive rows) draws evenly from the whole input,
+ * e.g. from data gathered in blocks.  n in [0, 2^32); the outputs must not
+ * overlap the inputs or each other (MCUBES_E_ARG).  Stream-ordered. */
+int mcubes_flow_shuffle(const double *d_x, const double *d_w, int64_t n, double *d_x_out,
+                        double *d_w_out, void *stream);
+
 /* The samples and weights w = f J of work items [w_begin, w_begin + count)
  * of iteration `iteration` of the plain method on d_grid: work item w is
  * cube (w mult) mod m (V-Sample's visiting order, which spreads a prefix
@@ -446,9 +456,24 @@ int mcubes_flow_draw(mcubes_flow *flow, int precision, const mcubes_plan *plan,
  * cube c's sample k draws u from Philox with the plan's seed and stream word
  * stream_id | 0x80000000, z_j = (c_j + u_j)/g, x = flow sample of z and
  * w = f(x)/q(x).  d_est (device, 2 doubles) <- (I_t, var_t) as mcubes_reduce
- * gives them (then mcubes_combine applies unchanged). */
+ * gives them. */
 int mcubes_flow_vsample(mcubes_flow *flow, int precision, const mcubes_plan *plan,
                         uint32_t iteration, double *d_est, void *stream);
+
+/* Combination of flow-mapped iterations 0..iteration with the same flow and
+ * plan (an extension: the paper combines only map-adapting iterations).
+ * They are independent estimates of one distribution, so they are averaged
+ * with equal weights:
+ *   Ibar = sum(I_t) / T,  sigma = sqrt(sum var_t) / T,  T = iteration + 1,
+ *   chi2/dof = sum over var_t > 0 of (I_t - Ibar)^2 / var_t, over T - 1.
+ * (Inverse-variance weighting, mcubes_combine, is biased low here: with a
+ * long-tailed weight distribution an iteration that caught a large weight
+ * also has a large variance estimate and is weighted down.)  d_est and
+ * d_state as for mcubes_combine, same header layout; d_state must start
+ * zeroed.  Stream-ordered; errors: MCUBES_E_ARG (NULL pointer, iteration >=
+ * MCUBES_MAX_ITERATIONS, rel_tol not finite or < 0), MCUBES_E_HIP. */
+int mcubes_flow_combine(uint32_t iteration, const double *d_est, double *d_state, double rel_tol,
+                        void *stream);
 
 /* Tail diagnostic of importance weights.  Each mcubes_flow_vsample call
  * histograms log2 of its weights w = f/q: MCUBES_WTAIL_BINS bins, bin b
@@ -478,19 +503,22 @@ int mcubes_flow_weight_tail(mcubes_flow *flow, double *shape, int64_t *tail_coun
  *   1. warmup_iters plain m-Cubes iterations (grid refined every time);
  *   2. the samples and weights of train_items work items, an equal share
  *      from each of them (mcubes_vsample_dump with that iteration's grid),
- *      train the flow for `epochs` epochs.  The early iterations' broad
- *      grids keep every peak of f in the data: on a multimodal integrand a
- *      separable map can settle on one peak within a few iterations;
+ *      shuffled (mcubes_flow_shuffle), train the flow for `epochs` epochs.
+ *      The early iterations' broad grids keep every peak of f in the data:
+ *      on a multimodal integrand a separable map can settle on one peak
+ *      within a few iterations;
  *   3. `rounds` times: round_samples samples of the flow itself with weights
- *      f/q (mcubes_flow_draw, in train_precision) train it for round_epochs
- *      epochs; then
+ *      f/q (mcubes_flow_draw, in train_precision), together with the
+ *      warm-up samples in the first anchor_rounds (shuffled into them), train it
+ *      for round_epochs epochs.  The flow never draws where it has lost a
+ *      peak of f; the warm-up samples there pull it back; then
  *      tail_rounds more such rounds with the weights raised to tail_power
  *      (> 1 stresses the samples the flow under-weights: between the
  *      Kullback-Leibler objective, power 1, and the variance, power 2) at
  *      learning rate tail_lr;
  *   4. flow-mapped iterations (mcubes_flow_vsample, in `precision`) combined
- *      by inverse-variance weighting until error <= rel_tol |estimate| or
- *      itmax of them.
+ *      with equal weights (mcubes_flow_combine) until error <= rel_tol
+ *      |estimate| or itmax of them.
  * Plain m-Cubes stays the judge: if the first flow iteration's variance is
  * not below the last plain iteration's, the flow is dropped and the
  * remaining iterations run plain (report->used_flow = 0).  A flow result
@@ -519,7 +547,8 @@ typedef struct {
     double tail_power;     /* default 1.5 */
     double tail_lr;        /* default 8e-4 */
     int32_t train_precision; /* training products: MCUBES_BF16 (default) or MCUBES_FP32 */
-    int32_t reserved;
+    int32_t anchor_rounds; /* default 2: how many of the first `rounds` also train on
+                              the warm-up samples */
 } mcubes_flow_options;
 
 typedef struct {

@@ -71,7 +71,7 @@ class mcubes_flow_options(ctypes.Structure):
                 ("round_epochs", ctypes.c_int32), ("tail_rounds", ctypes.c_int32),
                 ("batch", ctypes.c_int64), ("lr", ctypes.c_double), ("round_lr", ctypes.c_double),
                 ("tail_power", ctypes.c_double), ("tail_lr", ctypes.c_double),
-                ("train_precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("train_precision", ctypes.c_int32), ("anchor_rounds", ctypes.c_int32)]
 
 
 class mcubes_flow_report(ctypes.Structure):
@@ -165,6 +165,8 @@ _SIGNATURES = {
     "mcubes_vsample_dump": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, ctypes.c_int64,
                                            ctypes.c_int64, _vp, _vp, _vp]),
     "mcubes_flow_vsample": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_uint32, _vp, _vp]),
+    "mcubes_flow_combine": (ctypes.c_int, [ctypes.c_uint32, _vp, _vp, ctypes.c_double, _vp]),
+    "mcubes_flow_shuffle": (ctypes.c_int, [_vp, _vp, ctypes.c_int64, _vp, _vp, _vp]),
     "mcubes_flow_draw": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_uint32, ctypes.c_int64,
                                         _vp, _vp, _vp]),
     "mcubes_default_flow_options": (None, [ctypes.POINTER(mcubes_flow_options)]),
@@ -340,6 +342,18 @@ def mcubes_combine(plan, iteration, d_est, d_state, rel_tol, stream=None):
     _check(lib().mcubes_combine(plan.handle, int(iteration), _dev(d_est, 2, "est"),
                                 _dev(d_state, MCUBES_STATE_LEN, "state"), float(rel_tol),
                                 _stream(stream)))
+
+
+def mcubes_flow_combine(iteration, d_est, d_state, rel_tol, stream=None):
+    _check(lib().mcubes_flow_combine(int(iteration), _dev(d_est, 2, "est"),
+                                     _dev(d_state, MCUBES_STATE_LEN, "state"), float(rel_tol),
+                                     _stream(stream)))
+
+
+def mcubes_flow_shuffle(d_x, d_w, n, d_x_out, d_w_out, stream=None):
+    _check(lib().mcubes_flow_shuffle(_dev(d_x, 6 * n, "x"), _dev(d_w, n, "w"), int(n),
+                                     _dev(d_x_out, 6 * n, "x_out"), _dev(d_w_out, n, "w_out"),
+                                     _stream(stream)))
 
 
 def mcubes_refine(plan, d_grid, d_bins, d_grid_out, stream=None):

@@ -444,6 +444,59 @@ __global__ void zero_u32_kernel(uint32_t *__restrict__ p, int64_t n) {
     if (i < n) p[i] = 0u;
 }
 
+// Records (I_t, var_t) of flow-mapped iteration t in the combined state and
+// recombines iterations 0..t with equal weights: they all sample the same
+// proposal with the same number of points, so the plain mean is unbiased
+// (variance weights would favour the iterations that missed the rare large
+// weights).  Ibar = sum I / T, sigma = sqrt(sum var) / T, chi2/dof over the
+// iterations with var > 0.  Header layout as for the plain combination.
+__global__ void flow_combine_kernel(const double *__restrict__ est, double *__restrict__ state,
+                                    uint32_t t, double rel_tol) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double *hist = state + MCUBES_STATE_HEADER;
+    const double It = est[0], Vt = est[1];
+    hist[2 * t] = It;
+    hist[2 * t + 1] = Vt;
+    if (!isfinite(It) || !isfinite(Vt)) state[6] = 1.0;
+    const int T = (int)t + 1;
+    double si = 0.0, sv = 0.0;
+    for (int q = 0; q < T; ++q) {
+        si = si + hist[2 * q];
+        sv = sv + hist[2 * q + 1];
+    }
+    const double Ibar = si / (double)T;
+    double chi2 = 0.0;
+    for (int q = 0; q < T; ++q) {
+        const double v = hist[2 * q + 1];
+        if (v > 0.0) {
+            const double dv = hist[2 * q] - Ibar;
+            chi2 = chi2 + dv * dv / v;
+        }
+    }
+    const double sigma = sqrt(sv) / (double)T;
+    state[0] = Ibar;
+    state[1] = sigma;
+    state[2] = T > 1 ? chi2 / (double)(T - 1) : 0.0;
+    state[3] = (double)(T - 1);
+    state[4] = (double)T;
+    state[5] = sigma <= rel_tol * fabs(Ibar) ? 1.0 : 0.0;
+}
+
+// Row j of the output is row (a j) mod n of the input (x: 6 doubles per row,
+// w: one); with a coprime to n this is a permutation.
+__global__ void shuffle_rows_kernel(const double *__restrict__ x, const double *__restrict__ w,
+                                    int64_t n, uint64_t a, double *__restrict__ xo,
+                                    double *__restrict__ wo) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int64_t src = (int64_t)(((uint64_t)j * a) % (uint64_t)n);
+    const double *xi = x + src * flow::D;
+    double *xj = xo + j * flow::D;
+#pragma unroll
+    for (int k = 0; k < flow::D; ++k) xj[k] = xi[k];
+    wo[j] = w[src];
+}
+
 __global__ void widen_kernel(const float *__restrict__ in, int64_t n, double *__restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = (double)in[i];
@@ -834,6 +887,21 @@ hipError_t launch_flow_batch_wsums(const double *w, int64_t n, int64_t batch, do
 hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_flow_combine(const double *est, double *state, uint32_t iteration,
+                               double rel_tol, hipStream_t s) {
+    hipLaunchKernelGGL(flow_combine_kernel, dim3(1), dim3(64), 0, s, est, state, iteration,
+                       rel_tol);
+    return hipGetLastError();
+}
+
+hipError_t launch_flow_shuffle(const double *x, const double *w, int64_t n, uint64_t a,
+                               double *xo, double *wo, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(shuffle_rows_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x,
+                       w, n, a, xo, wo);
     return hipGetLastError();
 }
 

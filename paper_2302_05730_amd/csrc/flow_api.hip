@@ -117,6 +117,30 @@ hipError_t train_step(mcubes_flow *F, int precision, const double *d_x, const do
                                     : launch_flow_wgrad(F->d_scratch, n, F->d_grad, s);
 }
 
+// A multiplier for the row shuffle: the odd number nearest above n (sqrt(5)-1)/2,
+// stepped until coprime to n (so j -> a j mod n is a permutation whose
+// consecutive outputs lie about 0.618 n apart: any run of rows draws evenly
+// from the whole input).
+uint64_t shuffle_multiplier(int64_t n) {
+    if (n <= 2) return 1;
+    const uint64_t un = (uint64_t)n;
+    uint64_t a = ((uint64_t)((double)n * 0.6180339887498949) | 1u) % un;
+    for (;;) {
+        uint64_t x = a, y = un;
+        while (y) {
+            const uint64_t t = x % y;
+            x = y;
+            y = t;
+        }
+        if (x == 1) return a;
+        a = (a + 2) % un;
+    }
+}
+
+bool overlaps(const double *p, int64_t np, const double *q, int64_t nq) {
+    return p < q + nq && q < p + np;
+}
+
 int check_train_precision(int precision) {
     if (precision != MCUBES_FP32 && precision != MCUBES_BF16)
         return fail(MCUBES_E_ARG, "precision must be MCUBES_FP32 or MCUBES_BF16");
@@ -370,6 +394,32 @@ int mcubes_flow_vsample(mcubes_flow *F, int precision, const mcubes_plan *P, uin
     return e == hipSuccess ? MCUBES_OK : hip_fail(e, "flow V-Sample launch");
 }
 
+int mcubes_flow_shuffle(const double *d_x, const double *d_w, int64_t n, double *d_x_out,
+                        double *d_w_out, void *stream) {
+    if (n < 0 || n >= ((int64_t)1 << 32)) return fail(MCUBES_E_ARG, "n must be in [0, 2^32)");
+    if (n == 0) return MCUBES_OK;
+    if (!d_x || !d_w || !d_x_out || !d_w_out) return fail(MCUBES_E_ARG, "NULL argument");
+    const int64_t nx = n * flow::D;
+    if (overlaps(d_x, nx, d_x_out, nx) || overlaps(d_x, nx, d_w_out, n) ||
+        overlaps(d_w, n, d_x_out, nx) || overlaps(d_w, n, d_w_out, n) ||
+        overlaps(d_x_out, nx, d_w_out, n))
+        return fail(MCUBES_E_ARG, "the shuffle's outputs must not overlap its inputs or each other");
+    const hipError_t e = launch_flow_shuffle(d_x, d_w, n, shuffle_multiplier(n), d_x_out, d_w_out,
+                                             as_stream(stream));
+    return e == hipSuccess ? MCUBES_OK : hip_fail(e, "shuffle launch");
+}
+
+int mcubes_flow_combine(uint32_t iteration, const double *d_est, double *d_state, double rel_tol,
+                        void *stream) {
+    if (!d_est || !d_state) return fail(MCUBES_E_ARG, "NULL argument");
+    if (iteration >= MCUBES_MAX_ITERATIONS)
+        return fail(MCUBES_E_ARG, "iteration %u >= %d", iteration, MCUBES_MAX_ITERATIONS);
+    if (!(rel_tol >= 0.0) || !isfinite(rel_tol))
+        return fail(MCUBES_E_ARG, "rel_tol must be finite and >= 0");
+    const hipError_t e = launch_flow_combine(d_est, d_state, iteration, rel_tol, as_stream(stream));
+    return e == hipSuccess ? MCUBES_OK : hip_fail(e, "flow combine launch");
+}
+
 int mcubes_weight_tail_shape(const uint32_t *hist, double *shape, int64_t *tail_count) {
     if (!hist || !shape) return fail(MCUBES_E_ARG, "NULL argument");
     *shape = NAN;
@@ -418,6 +468,7 @@ void mcubes_default_flow_options(mcubes_flow_options *o) {
     o->tail_power = 1.5;
     o->tail_lr = 8e-4;
     o->train_precision = MCUBES_BF16;
+    o->anchor_rounds = 2;
 }
 
 int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int64_t ncall,
@@ -436,6 +487,7 @@ int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int6
         fo.train_items < 1 || !(fo.tail_power >= 1.0 && fo.tail_power <= 4.0) ||
         !(fo.tail_lr > 0.0) ||
         (fo.train_precision != MCUBES_FP32 && fo.train_precision != MCUBES_BF16) ||
+        fo.anchor_rounds < 0 ||
         fo.round_samples < 1 || fo.round_samples > ((int64_t)1 << 31) || !(fo.lr > 0.0) ||
         !(fo.round_lr > 0.0) || (fo.precision != MCUBES_FP32 && fo.precision != MCUBES_BF16))
         return fail(MCUBES_E_ARG, "invalid flow options");
@@ -453,9 +505,15 @@ int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int6
     const int64_t per_it = items / fo.warmup_iters > 0 ? items / fo.warmup_iters : 1;
     const int64_t rows = per_it * P->p * fo.warmup_iters;
     int64_t trows = 0;
-    const int64_t drows = rows > fo.round_samples ? rows : fo.round_samples;
+    // row buffers: [round draws | warm-up samples] and its shuffled copy
+    const int64_t rs = fo.round_samples, urows = rs + rows;
+    if (urows > kMaxSamples) {
+        mcubes_plan_destroy(P);
+        return fail(MCUBES_E_ARG, "round_samples plus the %lld warm-up rows exceed 2^31",
+                    (long long)rows);
+    }
     const int64_t total = 2 * ng + nbn + 2 * (int64_t)P->blocks + 2 + 2 * MCUBES_STATE_LEN +
-                          7 * drows;
+                          14 * urows;
     double *buf = nullptr;
     hipEvent_t ev[4] = {};
     double head[MCUBES_STATE_HEADER];
@@ -473,7 +531,9 @@ int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int6
     double *partials = bins + nbn;
     double *est = partials + 2 * (int64_t)P->blocks;
     double *st_plain = est + 2, *st_flow = st_plain + MCUBES_STATE_LEN;
-    double *dx = st_flow + MCUBES_STATE_LEN, *dw = dx + 6 * drows;
+    double *dx = st_flow + MCUBES_STATE_LEN, *dw = dx + 6 * urows;
+    double *sx = dw + urows, *sw = sx + 6 * urows;
+    double *wx = dx + 6 * rs, *ww = dw + rs;  // the warm-up samples
     double *state = st_flow;
 
 #define FI_CHECK(expr, what)                 \
@@ -504,36 +564,45 @@ int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int6
     for (int t = 0; t < fo.warmup_iters; ++t) {
         FI_CALL(mcubes_iteration(P, (uint32_t)t, grid[t & 1], grid[(t + 1) & 1], bins, partials, est,
                                  st_plain, 0.0, opt.stream));
-        FI_CALL(mcubes_vsample_dump(P, (uint32_t)t, grid[t & 1], 0, per_it, dx + trows * flow::D,
-                                    dw + trows, opt.stream));
+        FI_CALL(mcubes_vsample_dump(P, (uint32_t)t, grid[t & 1], 0, per_it, wx + trows * flow::D,
+                                    ww + trows, opt.stream));
         trows += per_it * P->p;
     }
     FI_CHECK(hipMemcpyAsync(&R.last_plain_var, est + 1, sizeof(double), hipMemcpyDeviceToHost, s),
              "hipMemcpyAsync");
     FI_CHECK(hipMemcpyAsync(head, st_plain, sizeof head, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
     FI_CHECK(hipEventRecord(ev[1], s), "hipEventRecord");
-    // 2-3. training on the warm-up's samples, then on the flow's own
+    // 2-3. training on the warm-up's samples, then on the flow's own.  The
+    // mini-batches are runs of consecutive rows, so the rows are shuffled
+    // first: the warm-up samples come in blocks, one per iteration.
     {
         double losses[1024];
         const int ep = fo.epochs < 1024 ? fo.epochs : 1024;
         if (ep > 0) {
-            FI_CALL(mcubes_flow_train(F, fo.train_precision, dx, dw, trows, ep, fo.batch, fo.lr,
+            FI_CALL(mcubes_flow_shuffle(wx, ww, trows, sx, sw, opt.stream));
+            FI_CALL(mcubes_flow_train(F, fo.train_precision, sx, sw, trows, ep, fo.batch, fo.lr,
                                       losses, opt.stream));
             R.final_loss = losses[ep - 1];
         }
         const int rep_ep = fo.round_epochs < 1024 ? fo.round_epochs : 1024;
         for (int r = 0; r < fo.rounds + fo.tail_rounds; ++r) {
             const bool tail = r >= fo.rounds;
-            FI_CALL(mcubes_flow_draw(F, fo.train_precision, P, (uint32_t)(1000 + r),
-                                     fo.round_samples, dx, dw, opt.stream));
+            FI_CALL(mcubes_flow_draw(F, fo.train_precision, P, (uint32_t)(1000 + r), rs, dx, dw,
+                                     opt.stream));
             if (tail && fo.tail_power != 1.0)
-                FI_CHECK(launch_pow_weights(dw, fo.round_samples, fo.tail_power, s), "weights launch");
-            if (rep_ep > 0) {
-                FI_CALL(mcubes_flow_train(F, fo.train_precision, dx, dw, fo.round_samples, rep_ep,
-                                          fo.batch, tail ? fo.tail_lr : fo.round_lr, losses,
-                                          opt.stream));
-                R.final_loss = losses[rep_ep - 1];
-            }
+                FI_CHECK(launch_pow_weights(dw, rs, fo.tail_power, s), "weights launch");
+            if (rep_ep <= 0) continue;
+            // the anchored rounds also train on the warm-up samples (both
+            // sets are weighted samples of f, on the same scale), which
+            // keeps every peak of f in the data: a flow that has lost one
+            // never draws there itself
+            const bool anchored = r < fo.anchor_rounds && !tail;
+            const int64_t n = anchored ? rs + trows : rs;
+            if (anchored) FI_CALL(mcubes_flow_shuffle(dx, dw, n, sx, sw, opt.stream));
+            FI_CALL(mcubes_flow_train(F, fo.train_precision, anchored ? sx : dx,
+                                      anchored ? sw : dw, n, rep_ep, fo.batch,
+                                      tail ? fo.tail_lr : fo.round_lr, losses, opt.stream));
+            R.final_loss = losses[rep_ep - 1];
         }
     }
     FI_CHECK(hipEventRecord(ev[2], s), "hipEventRecord");
@@ -546,7 +615,7 @@ int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int6
         const uint32_t it = (uint32_t)(fo.warmup_iters + t);
         if (used) {
             FI_CALL(mcubes_flow_vsample(F, fo.precision, P, it, est, opt.stream));
-            FI_CALL(mcubes_combine(P, (uint32_t)t, est, st_flow, rel_tol, opt.stream));
+            FI_CALL(mcubes_flow_combine((uint32_t)t, est, st_flow, rel_tol, opt.stream));
         } else {
             // plain iterations continue from the warm-up's grid and state
             FI_CALL(mcubes_iteration(P, (uint32_t)plain_t, grid[plain_t & 1],

@@ -371,6 +371,120 @@ def test_training_reduces_the_loss(mc):
     assert sd1 < sd0 / 1.5 and ess1 > ess0
 
 
+def test_flow_combine_matches_oracle(mc):
+    """The equal-weight combination of flow-mapped iterations, fed one
+    iteration at a time through the C-ABI, against the oracle on every
+    prefix: the same FP64 sums in the same order, so 1e-14 relative (one
+    zero-variance iteration, which adds nothing to chi2)."""
+    import torch
+    rng = np.random.default_rng(21)
+    T = 12
+    I = 1.0 + 0.01 * rng.standard_normal(T)
+    V = (1e-4 * rng.lognormal(0.0, 1.0, T)) ** 2
+    V[4] = 0.0
+    d_est = torch.empty(2, dtype=torch.float64, device="cuda")
+    d_state = torch.zeros(mc.MCUBES_STATE_LEN, dtype=torch.float64, device="cuda")
+    for t in range(T):
+        d_est.copy_(torch.tensor([I[t], V[t]], dtype=torch.float64))
+        mc.mcubes_flow_combine(t, d_est, d_state, 2e-5)
+        st = d_state.cpu().numpy()
+        Ibar, sigma, chi2, dof = oracle.flow_combine(I[:t + 1], V[:t + 1])
+        assert st[0] == pytest.approx(Ibar, rel=1e-14)
+        assert st[1] == pytest.approx(sigma, rel=1e-14)
+        assert st[2] == pytest.approx(chi2, rel=1e-13, abs=1e-300)
+        assert (st[3], st[4], st[6]) == (dof, t + 1, 0.0)
+        assert st[5] == (1.0 if sigma <= 2e-5 * abs(Ibar) else 0.0)
+        assert (st[8 + 2 * t], st[9 + 2 * t]) == (I[t], V[t])
+    _say(f"flow combine of {T} iterations: {st[0]!r} +- {st[1]:.3e}, chi2/dof {st[2]:.3f}, "
+         f"converged {st[5]}")
+
+
+def _shuffle_multiplier(n):
+    """The documented rule: the odd number at or above n (sqrt(5)-1)/2,
+    stepped by two until coprime to n."""
+    if n <= 2:
+        return 1
+    a = (int(n * 0.6180339887498949) | 1) % n
+    while math.gcd(a, n) != 1:
+        a = (a + 2) % n
+    return a
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 100003, 1 << 20])
+def test_flow_shuffle_is_the_documented_permutation(mc, n):
+    import torch
+    i = torch.arange(n, dtype=torch.float64, device="cuda")
+    x = (i[:, None] + torch.arange(6, dtype=torch.float64, device="cuda")[None, :] / 8).reshape(-1)
+    w = i.clone()
+    xo = torch.full_like(x, -1.0)
+    wo = torch.full_like(w, -1.0)
+    mc.mcubes_flow_shuffle(x, w, n, xo, wo)
+    torch.cuda.synchronize()
+    src = wo.cpu().numpy().astype(np.int64)
+    a = _shuffle_multiplier(n)
+    assert np.array_equal(src, (np.arange(n, dtype=np.int64) * a) % n)
+    assert np.array_equal(np.sort(src), np.arange(n))
+    # each row moves whole: x row j is still (src + k/8)
+    xr = xo.view(n, 6).cpu().numpy()
+    assert np.array_equal(xr, src[:, None] + np.arange(6)[None, :] / 8)
+    if n >= 1 << 16:
+        # every run of 4096 consecutive outputs draws evenly from the input
+        lo = (src < n // 2).reshape(-1)[: (n // 4096) * 4096].reshape(-1, 4096).mean(1)
+        assert lo.min() > 0.45 and lo.max() < 0.55
+
+
+def test_anchored_rounds_recover_a_lost_peak(mc):
+    """A flow trained only on the samples of one peak of the correlated
+    mixture gives about half the integral.  Its own draws rarely reach the
+    other peak, so self-training repairs it slowly if at all; the anchored
+    rounds (the first two, by default) also train on the warm-up samples,
+    which cover both peaks, and bring the estimate back to the integral."""
+    import torch
+    pr = workloads.mixture_6d(ncall=1 << 22)
+    opts = mc.mcubes_default_options(nbins=500)
+    plan = mc.mcubes_plan_create(pr.family, pr.params, 6, pr.ncall, 5, opts)
+    B = mc.Buffers(plan)
+    p = plan.info["samples_per_cube"]
+    mc.mcubes_init_grid(plan, B.grid[0])
+    per_it = 1 << 17
+    x = torch.empty(8 * per_it * p * 6, dtype=torch.float64, device="cuda")
+    w = torch.empty(8 * per_it * p, dtype=torch.float64, device="cuda")
+    for t in range(8):
+        mc.mcubes_iteration(plan, t, B.grid[t & 1], B.grid[(t + 1) & 1], B.bins, B.partials,
+                            B.est, B.state, 0.0)
+        r0 = t * per_it * p
+        mc.mcubes_vsample_dump(plan, t, B.grid[t & 1], 0, per_it, x[6 * r0:], w[r0:])
+    rows = x.view(-1, 6)
+    low = rows.mean(1) < 0.5
+    xl = rows[low].reshape(-1).contiguous()
+    wl = w[low].contiguous()
+    nl = int(wl.numel())
+    xs, ws = torch.empty_like(xl), torch.empty_like(wl)
+    mc.mcubes_flow_shuffle(xl, wl, nl, xs, ws)
+    base = mc.Flow(workloads.flow_init(7))
+    base.train(xs, ws, nl, 10, 65536, 4e-3)
+    est = torch.empty(2, dtype=torch.float64, device="cuda")
+    base.vsample(plan, 100, est, precision=mc.MCUBES_BF16)
+    torch.cuda.synchronize()
+    lost = est[0].item()
+    theta = base.params()
+    _say(f"one-peak flow: {lost}")
+    assert abs(lost - 0.5) < 0.1
+    out = {}
+    for anc in (1, 0):
+        fl = mc.Flow(theta)
+        kw = {} if anc else {"anchor_rounds": 0}
+        res, rep = fl.integrate(pr.family, pr.params, pr.ncall, 4, 0.0, 5, opts, epochs=0, **kw)
+        out[anc] = res["estimate"]
+        _say(f"anchor {anc}: {res['estimate']} +- {res['error']:.2e}, used {rep['used_flow']}, "
+             f"tail {rep['tail_shape']:.2f}")
+    # recovered (measured 0.9987 to 1.0002) against lost (about 0.5)
+    assert abs(out[1] - 1.0) < 5e-3
+    # Without the anchor the result is left to chance (measured 0.51 to
+    # 0.79): the few draws the flow still makes near the lost peak can
+    # bring back part of it, so it is reported, not asserted.
+
+
 def test_flow_pipeline_beats_plain_mcubes_on_the_mixture(mc):
     """The whole pipeline with its default recipe on the correlated mixture
     (6-D, 2^22 samples per iteration; integral 1 to 1.6e-10).  The separable
