@@ -217,8 +217,10 @@ def bench_flow(mc, ncall, plain_iters=50):
     mc.lib().mcubes_default_flow_options(mc.ctypes.byref(fo))
     items = min(fo.train_items, mc.mcubes_plan_sizes(6, ncall)[1])
     p = mc.mcubes_plan_sizes(6, ncall)[2]
-    trained = (items * p * fo.epochs
-               + (fo.rounds + fo.tail_rounds) * fo.round_samples * fo.round_epochs)
+    rows = max(items // fo.warmup_iters, 1) * p * fo.warmup_iters  # warm-up samples
+    trained = (rows * fo.epochs
+               + (fo.rounds + fo.tail_rounds) * fo.round_samples * fo.round_epochs
+               + min(fo.anchor_rounds, fo.rounds) * rows * fo.round_epochs)
     n_eval = mc.mcubes_plan_sizes(6, ncall)[3]
     flow_s = rep["flow_ms"] * 1e-3
     evals = n_eval * res["iterations"] / flow_s if flow_s > 0 else None

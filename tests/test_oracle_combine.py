@@ -1,5 +1,6 @@
 """Pins of the combination of iteration estimates (Lepage's inverse-variance
-weighting; the paper takes the error from the MC standard deviation, §3.2)."""
+weighting; the paper takes the error from the MC standard deviation, §3.2),
+and of the equal-weight combination of flow-mapped iterations."""
 from fractions import Fraction
 
 import pytest
