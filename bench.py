@@ -183,13 +183,16 @@ FLOW_GEMM_FLOPS = 2 * 4 * (96 * 64 + 64 * 64 + 64 * 99)
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 HBM_PEAK_GBPS = 8000.0
 # per training sample: the forward products, the input-gradient products and
-# the weight-gradient sums (three times the network); and the FP32 scratch
-# fields per layer that the pass writes (u, h1, h2, spline parameters), reads
-# back and overwrites with deltas (spline parameters, d2, d1), and that the
-# weight-gradient tiles read (inputs and deltas of the five output tiles)
+# the weight-gradient sums (three times the network); and the scratch bytes
+# per layer of the BF16 training step: the pass writes u (6 FP32), h1, h2,
+# d2, d1 (64 BF16 each), the spline deltas (99 BF16), the third product's
+# BF16 operands (128 B) and the ReLU bit masks (16 B), and reads back u, the
+# operands and the masks; the five weight-gradient tiles read their inputs
+# (2 and 1 u rows, h1, h2 twice) and deltas (d1 twice, d2, spline deltas
+# 0-63 and 64-98)
 FLOW_TRAIN_FLOPS = 3 * FLOW_GEMM_FLOPS
-FLOW_TRAIN_BYTES = 4 * 4 * ((6 + 64 + 64 + 99) + (6 + 99 + 64 + 64) + (99 + 64 + 64)
-                            + (6 + 64) * 2 + (64 + 64) + (64 + 64) + (64 + 35))
+FLOW_TRAIN_BYTES = 4 * ((24 + 4 * 128 + 198 + 128 + 16) + (24 + 128 + 16)
+                        + (8 + 128) + (4 + 128) + (128 + 128) + (128 + 128) + (128 + 70))
 
 
 def bench_flow(mc, ncall, plain_iters=50):

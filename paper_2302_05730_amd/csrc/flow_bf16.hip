@@ -475,6 +475,18 @@ __device__ __forceinline__ void raw_of(const f32x16 (&own)[2][G3T], int b, float
     }
 }
 
+// The training pass keeps u in FP32 fields (the backward pass and the first
+// weight gradient recompute from it) and stores h1, h2 and the three deltas
+// as the BF16 values the matrix cores take: row F of a layer's fields lies at
+// uint16 index F n + s past the first half of the layer's FP32 region, above
+// the u rows.
+__device__ __forceinline__ uint16_t *bf16_rows(float *layer_fields, int64_t n) {
+    return reinterpret_cast<uint16_t *>(layer_fields) + (int64_t)FS * n;
+}
+__device__ __forceinline__ const uint16_t *bf16_rows(const float *layer_fields, int64_t n) {
+    return reinterpret_cast<const uint16_t *>(layer_fields) + (int64_t)FS * n;
+}
+
 // Per-wave training state beyond the FP32 fields, per layer and group of 64
 // samples: the second hidden layer as the BF16 operands of the third product
 // ([block][K step][lane], 8 KB), from which the backward pass recomputes the
@@ -493,10 +505,11 @@ __device__ __forceinline__ uint32_t *relu_bits(float *ext_l, int64_t n64, int64_
 
 // Forward and backward pass of the weighted negative log-likelihood, 64
 // samples per wave (lane = sample for the per-sample work), the nine
-// products per layer on the matrix cores.  Writes the FP32 scratch fields
-// the weight-gradient kernels read (u, h1, h2, and the deltas, taken from
-// the FP32 accumulators); loss += sum c log q with c = -w / sum w.  Lanes
-// past n work on a copy of the last sample with c = 0 and store nothing.
+// products per layer on the matrix cores.  Writes the scratch fields the
+// weight-gradient kernel reads (u in FP32; h1, h2 and the deltas, taken from
+// the FP32 accumulators, rounded to BF16 as the products take them); loss +=
+// sum c log q with c = -w / sum w.  Lanes past n work on a copy of the last
+// sample with c = 0 and store nothing.
 __global__ __launch_bounds__(64) void train_bf16_kernel(
     const bf16x8 *__restrict__ frags, const bf16x8 *__restrict__ bfrags,
     const float *__restrict__ bias, const double *__restrict__ x, const double *__restrict__ w,
@@ -528,6 +541,7 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
 #pragma unroll 1
         for (int l = 0; l < L; ++l) {
             float *sc = scratch + (int64_t)l * FS * n;
+            uint16_t *b16 = bf16_rows(sc, n);
             float *ext_l = ext + (int64_t)l * BF_EXTRA * n64;
             if (live) {
 #pragma unroll
@@ -564,7 +578,8 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
                         const int r = 8 * (ks % 2) + i;
                         v[i] = fmaxf(acc1[ks / 2][r] + Bs[BOFF_1 + (ks / 2) * 32 + r], 0.0f);
                         m1 |= (v[i] > 0.0f ? 1u : 0u) << (8 * ks + i);
-                        if (clive[sb]) sc[(FS_H1 + acc_feature(ks / 2, r, h)) * n + cs[sb]] = v[i];
+                        if (clive[sb])
+                            b16[(FS_H1 + acc_feature(ks / 2, r, h)) * n + cs[sb]] = bf16_bits(v[i]);
                     }
                     h1[ks] = pack8(v);
                 }
@@ -589,7 +604,8 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
                         const int r = 8 * (ks % 2) + i;
                         v[i] = fmaxf(acc2[ks / 2][r] + Bs[BOFF_2 + (ks / 2) * 32 + r], 0.0f);
                         m2 |= (v[i] > 0.0f ? 1u : 0u) << (8 * ks + i);
-                        if (clive[sb]) sc[(FS_H2 + acc_feature(ks / 2, r, h)) * n + cs[sb]] = v[i];
+                        if (clive[sb])
+                            b16[(FS_H2 + acc_feature(ks / 2, r, h)) * n + cs[sb]] = bf16_bits(v[i]);
                     }
                     h2[ks] = pack8(v);
                     ops[ks * 64 + lane] = h2[ks];
@@ -619,6 +635,7 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
 #pragma unroll 1
         for (int l = L - 1; l >= 0; --l) {
             float *sc = scratch + (int64_t)l * FS * n;
+            uint16_t *b16 = bf16_rows(sc, n);
             float *ext_l = ext + (int64_t)l * BF_EXTRA * n64;
             float uin[D], gprev[D];
 #pragma unroll
@@ -658,7 +675,7 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
 #pragma unroll
                 for (int k = 0; k < RAW; ++k) {
                     gr[b * RAW + k] = graw[k];
-                    if (live) sc[(FS_DOUT + b * RAW + k) * n + s] = graw[k];
+                    if (live) b16[(FS_DOUT + b * RAW + k) * n + s] = bf16_bits(graw[k]);
                 }
                 const int from = (b * RAW) / 8, to = b == NB - 1 ? 2 * B3K : ((b + 1) * RAW) / 8;
 #pragma unroll
@@ -693,7 +710,7 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
                     for (int i = 0; i < 8; ++i) {
                         const int r = 8 * (ks % 2) + i, f = acc_feature(ks / 2, r, h);
                         v[i] = ((m2 >> (8 * ks + i)) & 1u) ? a3[ks / 2][r] : 0.0f;
-                        if (clive[sb]) sc[(FS_D2 + f) * n + cs[sb]] = v[i];
+                        if (clive[sb]) b16[(FS_D2 + f) * n + cs[sb]] = bf16_bits(v[i]);
                     }
                     Y[ks] = pack8(v);
                 }
@@ -715,7 +732,7 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
                     for (int i = 0; i < 8; ++i) {
                         const int r = 8 * (ks % 2) + i, f = acc_feature(ks / 2, r, h);
                         v[i] = ((m1 >> (8 * ks + i)) & 1u) ? a2[ks / 2][r] : 0.0f;
-                        if (clive[sb]) sc[(FS_D1 + f) * n + cs[sb]] = v[i];
+                        if (clive[sb]) b16[(FS_D1 + f) * n + cs[sb]] = bf16_bits(v[i]);
                     }
                     Z[ks] = pack8(v);
                 }
@@ -757,12 +774,14 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
 // products inputs^T deltas over the batch as C[row][col] = sum_s A[row][s]
 // B[s][col], K = samples: lane l of an operand holds feature l % 32 for the
 // 8 consecutive samples 8 (l / 32) .. +7 of a 16-sample step, read straight
-// from the field-major scratch (BF16 operands, FP32 accumulation).  One wave
-// owns up to 2 x 2 output tiles of 32 x 32: W1 rows 0-63 | W1 rows 64-95 |
-// W2 | W3 columns 0-63 | W3 columns 64-98 (padded to 128), over a slice of
-// ks samples (blockIdx.y); the tiles whose rows start at 0 also sum their
-// delta columns (the bias gradients, FP32).  Partial sums go to
-// part[slice][parameter], added in slice order afterwards.
+// from the field-major scratch: the BF16 rows of h1, h2 and the deltas as
+// they are, the one-blob inputs encoded from the FP32 u rows (FP32
+// accumulation).  One wave owns up to 2 x 2 output tiles of 32 x 32: W1 rows
+// 0-63 | W1 rows 64-95 | W2 | W3 columns 0-63 | W3 columns 64-98 (padded to
+// 128), over a slice of ks samples (blockIdx.y); the tiles whose rows start
+// at 0 also sum their delta columns (the bias gradients, FP32 sums of the
+// BF16 deltas).  Partial sums go to part[slice][parameter], added in slice
+// order afterwards.
 constexpr int WB_TILES = 5;
 
 // v[e] = row[sb + e] for the samples below s_end (zero past it, and all zero
@@ -778,6 +797,21 @@ __device__ __forceinline__ void load8(const float *__restrict__ row, int64_t sb,
 #pragma unroll
         for (int e = 0; e < 8; ++e) v[e] = (use && sb + e < s_end) ? row[sb + e] : 0.0f;
     }
+}
+
+// The same for a BF16 row, as operand bits (zero past s_end); `whole`: all 8
+// are below s_end and 16-byte aligned.
+__device__ __forceinline__ bf16x8 load8_bf16(const uint16_t *__restrict__ row, int64_t sb,
+                                             int64_t s_end, bool whole, bool use) {
+    typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+    u16x8 v;
+    if (use && whole) {
+        v = *reinterpret_cast<const u16x8 *>(row + sb);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (use && sb + e < s_end) ? row[sb + e] : (uint16_t)0;
+    }
+    return __builtin_bit_cast(bf16x8, v);
 }
 
 __global__ __launch_bounds__(64) void wgrad_bf16_kernel(const float *__restrict__ scratch,
@@ -796,6 +830,7 @@ __global__ __launch_bounds__(64) void wgrad_bf16_kernel(const float *__restrict_
     }
     const int lane = threadIdx.x, h = lane >> 5, idx = lane & 31;
     const float *sc = scratch + (int64_t)l * FS * n;
+    const uint16_t *b16 = bf16_rows(sc, n);
     const int bfield = mat == 0 ? FS_D1 : (mat == 1 ? FS_D2 : FS_DOUT);
     const bool bias_tile = r0 == 0;
     f32x16 acc[2][2];
@@ -804,35 +839,37 @@ __global__ __launch_bounds__(64) void wgrad_bf16_kernel(const float *__restrict_
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = f32x16{};
     float bsum[2] = {0.0f, 0.0f};
-    // a field row starts 16-byte aligned when n is a multiple of 4; the
-    // 8 samples of a lane then are two float4 (slices are multiples of 16)
-    const bool aligned = (n & 3) == 0;
+    // the 8 samples of a lane are two float4 of an FP32 row when n is a
+    // multiple of 4, one 16-byte load of a BF16 row when n is a multiple of
+    // 8 (slices are multiples of 16)
+    const bool aligned32 = (n & 3) == 0, aligned16 = (n & 7) == 0;
     for (int64_t s0 = s_begin; s0 < s_end; s0 += 16) {
         const int64_t sb = s0 + 8 * h;
-        const bool whole = aligned && sb + 8 <= s_end;
+        const bool inside = sb + 8 <= s_end;
         bf16x8 A[2], B[2];
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt) {
-            float v[8];
             const int R = r0 + 32 * rt + idx;
-            const int field = mat == 0 ? FS_U + a_idx(l, R / BLOBS) : (mat == 1 ? FS_H1 : FS_H2) + R;
-            load8(sc + (int64_t)field * n, sb, s_end, whole, rt < nrt, v);
             if (mat == 0) {
+                float v[8];
+                load8(sc + (int64_t)(FS_U + a_idx(l, R / BLOBS)) * n, sb, s_end,
+                      aligned32 && inside, rt < nrt, v);
 #pragma unroll
                 for (int e = 0; e < 8; ++e)
                     v[e] = (rt < nrt && sb + e < s_end) ? blob(v[e], R % BLOBS) : 0.0f;
+                A[rt] = pack8(v);
+            } else {
+                A[rt] = load8_bf16(b16 + (int64_t)((mat == 1 ? FS_H1 : FS_H2) + R) * n, sb, s_end,
+                                   aligned16 && inside, rt < nrt);
             }
-            A[rt] = pack8(v);
         }
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
-            float v[8];
             const int C = 32 * ct + idx;
-            load8(sc + (int64_t)(bfield + c0 + (C < cols ? C : 0)) * n, sb, s_end, whole, C < cols,
-                  v);
+            B[ct] = load8_bf16(b16 + (int64_t)(bfield + c0 + (C < cols ? C : 0)) * n, sb, s_end,
+                               aligned16 && inside, C < cols);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) bsum[ct] += v[e];
-            B[ct] = pack8(v);
+            for (int e = 0; e < 8; ++e) bsum[ct] += (float)B[ct][e];
         }
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt)
