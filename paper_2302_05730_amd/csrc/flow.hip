@@ -417,8 +417,18 @@ __global__ void wgrad_sum_kernel(const float *__restrict__ part, int slices,
                                  float *__restrict__ grad) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= PARAMS) return;
+    // slice order; sixteen loads in flight before their adds (about one wave
+    // per SIMD here, so the loads, not the adds, set the time)
     float a = 0.0f;
-    for (int k = 0; k < slices; ++k) a += part[(int64_t)k * PARAMS + i];
+    int k = 0;
+    for (; k + 16 <= slices; k += 16) {
+        float v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = part[(int64_t)(k + q) * PARAMS + i];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) a += v[q];
+    }
+    for (; k < slices; ++k) a += part[(int64_t)k * PARAMS + i];
     grad[i] = a;
 }
 
