@@ -51,6 +51,15 @@ __device__ __forceinline__ uint16_t bf16_bits(float f) {
     return (uint16_t)(b >> 16);
 }
 
+// Eight consecutive biases (16-byte aligned: every run starts at a multiple
+// of 8 floats) as two 16-byte loads.
+__device__ __forceinline__ void load_bias8(const float *__restrict__ p, float b[8]) {
+    const float4 x = *reinterpret_cast<const float4 *>(p);
+    const float4 y = *reinterpret_cast<const float4 *>(p + 4);
+    b[0] = x.x; b[1] = x.y; b[2] = x.z; b[3] = x.w;
+    b[4] = y.x; b[5] = y.y; b[6] = y.z; b[7] = y.w;
+}
+
 __device__ __forceinline__ bf16x8 pack8(const float v[8]) {
     bf16x8 r;
 #pragma unroll
@@ -157,12 +166,10 @@ __device__ __forceinline__ float sample_wave(const bf16x8 *__restrict__ frags,
             bf16x8 h1[G2K];
 #pragma unroll
             for (int ks = 0; ks < G2K; ++ks) {
-                float v[8];
+                float v[8], bb[8];
+                load_bias8(Bs + BOFF_1 + (ks / 2) * 32 + 8 * (ks % 2), bb);
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const int r = 8 * (ks % 2) + i;
-                    v[i] = fmaxf(acc1[ks / 2][r] + Bs[BOFF_1 + (ks / 2) * 32 + r], 0.0f);
-                }
+                for (int i = 0; i < 8; ++i) v[i] = fmaxf(acc1[ks / 2][8 * (ks % 2) + i] + bb[i], 0.0f);
                 h1[ks] = pack8(v);
             }
             f32x16 acc2[G2T];
@@ -177,12 +184,10 @@ __device__ __forceinline__ float sample_wave(const bf16x8 *__restrict__ frags,
             bf16x8 h2[G3K];
 #pragma unroll
             for (int ks = 0; ks < G3K; ++ks) {
-                float v[8];
+                float v[8], bb[8];
+                load_bias8(Bs + BOFF_2 + (ks / 2) * 32 + 8 * (ks % 2), bb);
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const int r = 8 * (ks % 2) + i;
-                    v[i] = fmaxf(acc2[ks / 2][r] + Bs[BOFF_2 + (ks / 2) * 32 + r], 0.0f);
-                }
+                for (int i = 0; i < 8; ++i) v[i] = fmaxf(acc2[ks / 2][8 * (ks % 2) + i] + bb[i], 0.0f);
                 h2[ks] = pack8(v);
             }
 #pragma unroll
@@ -572,11 +577,12 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
                 uint32_t m1 = 0u;
 #pragma unroll
                 for (int ks = 0; ks < G2K; ++ks) {
-                    float v[8];
+                    float v[8], bb[8];
+                    load_bias8(Bs + BOFF_1 + (ks / 2) * 32 + 8 * (ks % 2), bb);
 #pragma unroll
                     for (int i = 0; i < 8; ++i) {
                         const int r = 8 * (ks % 2) + i;
-                        v[i] = fmaxf(acc1[ks / 2][r] + Bs[BOFF_1 + (ks / 2) * 32 + r], 0.0f);
+                        v[i] = fmaxf(acc1[ks / 2][r] + bb[i], 0.0f);
                         m1 |= (v[i] > 0.0f ? 1u : 0u) << (8 * ks + i);
                         if (clive[sb])
                             b16[(FS_H1 + acc_feature(ks / 2, r, h)) * n + cs[sb]] = bf16_bits(v[i]);
@@ -598,11 +604,12 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
                 bf16x8 h2[G3K];
 #pragma unroll
                 for (int ks = 0; ks < G3K; ++ks) {
-                    float v[8];
+                    float v[8], bb[8];
+                    load_bias8(Bs + BOFF_2 + (ks / 2) * 32 + 8 * (ks % 2), bb);
 #pragma unroll
                     for (int i = 0; i < 8; ++i) {
                         const int r = 8 * (ks % 2) + i;
-                        v[i] = fmaxf(acc2[ks / 2][r] + Bs[BOFF_2 + (ks / 2) * 32 + r], 0.0f);
+                        v[i] = fmaxf(acc2[ks / 2][r] + bb[i], 0.0f);
                         m2 |= (v[i] > 0.0f ? 1u : 0u) << (8 * ks + i);
                         if (clive[sb])
                             b16[(FS_H2 + acc_feature(ks / 2, r, h)) * n + cs[sb]] = bf16_bits(v[i]);
