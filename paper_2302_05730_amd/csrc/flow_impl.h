@@ -33,10 +33,13 @@ constexpr int LP = OFF_B3 + OUT;  // parameters per layer
 constexpr int PARAMS = L * LP;
 static_assert(PARAMS == MCUBES_FLOW_PARAMS, "flow parameter count");
 
-// Per-sample training scratch, FP32, one block of FS fields per layer, each
-// field n floats (sample contiguous): the layer's input u (6), h1 and h2
-// (64 each), the 99 spline parameters (replaced by their deltas in the
-// backward pass) and the deltas after the second and the first ReLU.
+// Per-sample training scratch, one block of FS fields per layer, each field
+// n floats (sample contiguous): the layer's input u (6), h1 and h2 (64
+// each), the 99 spline parameters (replaced by their deltas in the backward
+// pass) and the deltas after the second and the first ReLU.  The FP32
+// training pass writes them all as FP32; the BF16 one writes u as FP32 and
+// the rest as BF16 rows of n values in the upper half of the layer's block
+// (bf16_rows in flow_bf16.hip).
 constexpr int FS_U = 0, FS_H1 = FS_U + D, FS_H2 = FS_H1 + HID, FS_DOUT = FS_H2 + HID;
 constexpr int FS_D2 = FS_DOUT + OUT, FS_D1 = FS_D2 + HID, FS = FS_D1 + HID;
 // most sample slices the weight-gradient kernels cut a batch into (their
