@@ -165,19 +165,21 @@ def test_loss_gradient_and_adam_match_oracle(mc):
     assert np.abs(t_gpu - t_ref).max() <= 1e-6
 
 
-def test_bf16_loss_gradient_tracks_the_oracle(mc):
+@pytest.mark.parametrize("n", [4000, 3999])
+def test_bf16_loss_gradient_tracks_the_oracle(mc, n):
     """The matrix-core form of the training pass (BF16 weights and product
     inputs, 2^-9 relative rounding each; FP32 accumulation; splines and the
     weight-gradient sums FP32) against the FP64 oracle at the same
     parameters: the loss within 2e-3 relative (log q moves by ~1e-3 per
     spline, its weighted mean less), the gradient's direction within
     cosine 0.999 and its relative L2 error below 5e-2, and the sign of
-    every large component right."""
+    every large component right.  n = 4000: many waves and a ragged last
+    one, rows read 16 bytes at a time; n = 3999: rows not 16-byte aligned
+    (read element by element) and a ragged last 16-sample step."""
     import torch
     theta = _f32(workloads.flow_random(4, out_scale=0.4))
     fl = mc.Flow(theta)
     rng = np.random.default_rng(12)
-    n = 4000  # many waves and a ragged last one
     xs = rng.uniform(0.02, 0.98, (n, 6))
     ws = rng.uniform(0.1, 3.0, n)
     d_grad = torch.zeros(mc.MCUBES_FLOW_PARAMS, dtype=torch.float64, device="cuda")
