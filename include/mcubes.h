@@ -425,8 +425,8 @@ int mcubes_flow_train(mcubes_flow *flow, int precision, const double *d_x, const
                       void *stream);
 
 /* Shuffles n training rows (x: n x 6, w: n; device) into (d_x_out, d_w_out):
- * output row j is input row (a j) mod n, a the odd number at or above
- * n (sqrt(5) - 1)/2 stepped until coprime to n.  A permutation whose
+ * output row j is input row (a j) mod n, a = floor(n (sqrt(5) - 1)/2)
+ * with its lowest bit set, stepped by 2 (mod n) until coprime to n.  A permutation whose
  * consecutive outputs lie about 0.618 n apart, so every mini-batch of
  * mcubes_flow_train (consecutive rows) draws evenly from the whole input,
  * e.g. from data gathered in blocks.  n in [0, 2^32); the outputs must not

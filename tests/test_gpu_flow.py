@@ -402,8 +402,8 @@ def test_flow_combine_matches_oracle(mc):
 
 
 def _shuffle_multiplier(n):
-    """The documented rule: the odd number at or above n (sqrt(5)-1)/2,
-    stepped by two until coprime to n."""
+    """The documented rule: floor(n (sqrt(5)-1)/2) with its lowest bit set,
+    stepped by two (mod n) until coprime to n."""
     if n <= 2:
         return 1
     a = (int(n * 0.6180339887498949) | 1) % n
