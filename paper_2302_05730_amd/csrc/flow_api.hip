@@ -118,10 +118,9 @@ hipError_t train_step(mcubes_flow *F, int precision, const double *d_x, const do
 }
 
 // A multiplier for the row shuffle: floor(n (sqrt(5)-1)/2) with its lowest bit
-// set, stepped by 2 (mod n) until coprime to n (so j -> a j mod n is a
-// permutation whose
-// consecutive outputs lie about 0.618 n apart: any run of rows draws evenly
-// from the whole input).
+// set, stepped by 2 (mod n) until coprime to n, so that j -> a j mod n is a
+// permutation whose consecutive outputs lie about 0.618 n apart: any run of
+// rows draws evenly from the whole input.
 uint64_t shuffle_multiplier(int64_t n) {
     if (n <= 2) return 1;
     const uint64_t un = (uint64_t)n;
