@@ -530,8 +530,8 @@ int mcubes_flow_weight_tail(mcubes_flow *flow, double *shape, int64_t *tail_coun
  * fallback).  Synchronous; allocates its buffers.
  * The flow's weights have a long tail where it is thinner than f (regions
  * of f that training has barely sampled): on the 6-D correlated mixture
- * the defaults leave the estimate a few 1e-4 low, with an error estimate
- * that can be a few times too small. */
+ * the defaults leave the estimate within a few 1e-4, more often low than
+ * high, with an error estimate that is often a few times too small. */
 typedef struct {
     int32_t warmup_iters;  /* default 8 */
     int32_t precision;     /* proposal iterations: MCUBES_BF16 (default) or MCUBES_FP32 */
