@@ -88,6 +88,10 @@ def lib():
         fn.restype = None
     L.mcf_loss_grad.argtypes = [_dp, ctypes.c_int64, _dp, _dp, _dp]
     L.mcf_loss_grad.restype = ctypes.c_double
+    L.mcf_loss_grad_ex.argtypes = [_dp, ctypes.c_int64, _dp, _dp, ctypes.c_int, _dp, _dp]
+    L.mcf_loss_grad_ex.restype = ctypes.c_double
+    L.mcf_bf16_array.argtypes = [_dp, ctypes.c_int64, _dp]
+    L.mcf_bf16_array.restype = None
     L.mcf_adam.argtypes = [_dp, _dp, _dp, _dp, ctypes.c_int64, ctypes.c_int, ctypes.c_double,
                            ctypes.c_double, ctypes.c_double, ctypes.c_double]
     L.mcf_adam.restype = None
@@ -279,14 +283,27 @@ def flow_sample(theta, z, bf16=False):
     return x, lq.value
 
 
-def flow_loss_grad(theta, xs, ws):
-    """-> (loss, grad): weighted negative log-likelihood and its gradient."""
+def bf16_round(v):
+    """Values rounded to bfloat16 (nearest, ties to even, through FP32), as FP64."""
+    v, vp = _d(np.asarray(v, dtype=np.float64).ravel())
+    out = np.zeros_like(v)
+    lib().mcf_bf16_array(vp, len(v), out.ctypes.data_as(_dp))
+    return out
+
+
+def flow_loss_grad(theta, xs, ws, bf16=False, with_abs=False):
+    """-> (loss, grad), or (loss, grad, grad_abs) with `with_abs`: weighted
+    negative log-likelihood and its gradient; bf16 rounds the operands of
+    every matrix product as a BF16 matrix unit does; grad_abs holds, per
+    parameter, the sum of the absolute values of its gradient's terms."""
     theta, tp = _d(theta)
     xs, xp = _d(np.asarray(xs).reshape(-1, FLOW_D))
     ws, wp = _d(ws)
     grad = np.zeros(FLOW_PARAMS)
-    loss = lib().mcf_loss_grad(tp, len(ws), xp, wp, grad.ctypes.data_as(_dp))
-    return loss, grad
+    gabs = np.zeros(FLOW_PARAMS) if with_abs else None
+    loss = lib().mcf_loss_grad_ex(tp, len(ws), xp, wp, int(bool(bf16)), grad.ctypes.data_as(_dp),
+                                  gabs.ctypes.data_as(_dp) if with_abs else None)
+    return (loss, grad, gabs) if with_abs else (loss, grad)
 
 
 def flow_adam(theta, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -8,7 +8,8 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(HERE, "mcubes_oracle.c"), os.path.join(HERE, "flow_oracle.c")]
+SRCS = [os.path.join(HERE, "mcubes_oracle.c"), os.path.join(HERE, "mcubes_oracle_abi.c"),
+        os.path.join(HERE, "flow_oracle.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

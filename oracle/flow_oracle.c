@@ -62,18 +62,46 @@ void mcf_masks(int layer, int a_idx[MCF_NA], int b_idx[MCF_NB])
     for (int t = 0; t < MCF_NB; ++t) b_idx[t] = B_IDX[layer][t];
 }
 
-/* round to bfloat16 (nearest, ties to even) through FP32 */
+/* Round to bfloat16, round to nearest with ties to even, through FP32 (the
+ * network values the matrix units take are FP32).  Written from the
+ * definition: the two bfloat16 values that bracket the FP32 value f are its
+ * truncation toward zero (the top 16 bits of its encoding) and the next
+ * bfloat16 away from zero; the nearer one wins, and on a tie the one whose
+ * last kept mantissa bit is 0.  Past the largest finite bfloat16 the upper
+ * neighbour is 2^128 (infinity), as for any IEEE overflow under rounding to
+ * nearest.  The distances are exact in FP64.  Non-finite values pass. */
+static float bits_to_float(uint32_t b)
+{
+    float f;
+    memcpy(&f, &b, 4);
+    return f;
+}
+
 static double bf16(double v)
 {
-    float f = (float)v;
+    const float f = (float)v;
+    if (!isfinite(f)) return (double)f;
     uint32_t b;
     memcpy(&b, &f, 4);
-    if ((b & 0x7f800000u) != 0x7f800000u) {
-        b += 0x7fffu + ((b >> 16) & 1u);
-        b &= 0xffff0000u;
-    }
-    memcpy(&f, &b, 4);
-    return (double)f;
+    const uint32_t lo_bits = b & 0xffff0000u;         /* toward zero */
+    const uint32_t hi_bits = lo_bits + 0x00010000u;   /* away from zero */
+    const double lo = (double)bits_to_float(lo_bits);
+    const int hi_inf = (hi_bits & 0x7f800000u) == 0x7f800000u;
+    const double hi = hi_inf ? copysign(ldexp(1.0, 128), (double)f)
+                             : (double)bits_to_float(hi_bits);
+    const double d_lo = fabs((double)f - lo), d_hi = fabs(hi - (double)f);
+    int up;
+    if (d_lo != d_hi)
+        up = d_hi < d_lo;
+    else
+        up = (lo_bits & 0x00010000u) != 0; /* tie: keep the even neighbour */
+    if (!up) return lo;
+    return hi_inf ? copysign(INFINITY, (double)f) : hi;
+}
+
+void mcf_bf16_array(const double *v, int64_t n, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = bf16(v[i]);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -307,14 +335,35 @@ void mcf_sample(const double *theta, const double z[MCF_D], int use_bf16, double
 }
 
 /* ------------------------------------------------------------------------ */
-/* Training loss and its gradient (FP64, no bfloat16 rounding)               */
+/* Training loss and its gradient                                           */
+/*                                                                          */
+/* loss = -sum_s w_s log q(x_s) / sum_s w_s, by reverse-mode                */
+/* differentiation through the four coupling layers (the chain rule over    */
+/* the spline CDFs, the output layer, the two ReLU layers and the one-blob  */
+/* encoding).                                                               */
+/*                                                                          */
+/* use_bf16 = 0: FP64 throughout.  use_bf16 = 1: the same sums with the     */
+/* operands of every matrix product rounded to bfloat16, as a matrix unit   */
+/* with BF16 inputs and wide accumulation computes them: the forward        */
+/* conditioner as in mcf_conditioner(bf16 = 1); in the backward pass the    */
+/* spline-parameter deltas, and the deltas after each ReLU, are rounded     */
+/* before they meet the (rounded) weights, and the weight gradients are     */
+/* sums of products of rounded operands (inputs h1, h2 and the encoding as  */
+/* the forward pass rounded them); bias gradients sum the rounded deltas.   */
+/* The derivative of the encoding itself (de/du) is taken exactly.          */
+/*                                                                          */
+/* grad_abs (may be NULL) receives, per parameter, the sum over samples of  */
+/* the absolute values of the terms that make up its gradient: the scale    */
+/* against which rounding differences in those terms are measured.         */
 /* ------------------------------------------------------------------------ */
-double mcf_loss_grad(const double *theta, int64_t n, const double *xs, const double *ws,
-                     double *grad)
+static double loss_grad(const double *theta, int64_t n, const double *xs, const double *ws,
+                        int use_bf16, double *grad, double *grad_abs)
 {
+#define RND(v) (use_bf16 ? bf16(v) : (v))
     double sw = 0.0;
     for (int64_t i = 0; i < n; ++i) sw += ws[i];
     memset(grad, 0, sizeof(double) * MCF_PARAMS);
+    if (grad_abs) memset(grad_abs, 0, sizeof(double) * MCF_PARAMS);
     double loss = 0.0;
     cond_cache_t cache[MCF_LAYERS];
     double uin[MCF_LAYERS][MCF_D];
@@ -327,7 +376,7 @@ double mcf_loss_grad(const double *theta, int64_t n, const double *xs, const dou
             memcpy(uin[l], u, sizeof u);
             double ua[MCF_NA];
             for (int t = 0; t < MCF_NA; ++t) ua[t] = u[A_IDX[l][t]];
-            conditioner(theta + (size_t)l * MCF_LAYER_PARAMS, ua, 0, &cache[l]);
+            conditioner(theta + (size_t)l * MCF_LAYER_PARAMS, ua, use_bf16, &cache[l]);
             for (int t = 0; t < MCF_NB; ++t) {
                 const int j = B_IDX[l][t];
                 double y, pdf;
@@ -342,6 +391,7 @@ double mcf_loss_grad(const double *theta, int64_t n, const double *xs, const dou
         for (int l = MCF_LAYERS - 1; l >= 0; --l) {
             const double *P = theta + (size_t)l * MCF_LAYER_PARAMS;
             double *G = grad + (size_t)l * MCF_LAYER_PARAMS;
+            double *GA = grad_abs ? grad_abs + (size_t)l * MCF_LAYER_PARAMS : NULL;
             const cond_cache_t *cc = &cache[l];
             double gout[MCF_OUT];
             double gprev[MCF_D];
@@ -355,48 +405,68 @@ double mcf_loss_grad(const double *theta, int64_t n, const double *xs, const dou
                                 gout + t * MCF_RAW, &gu);
                 gprev[j] = gu;
             }
+            for (int o = 0; o < MCF_OUT; ++o) gout[o] = RND(gout[o]);
             /* output layer */
             double gh2[MCF_HID] = {0};
             for (int o = 0; o < MCF_OUT; ++o) {
                 G[OFF_B3 + o] += gout[o];
+                if (GA) GA[OFF_B3 + o] += fabs(gout[o]);
                 for (int i = 0; i < MCF_HID; ++i) {
                     G[OFF_W3 + i * MCF_OUT + o] += cc->h2[i] * gout[o];
-                    gh2[i] += P[OFF_W3 + i * MCF_OUT + o] * gout[o];
+                    if (GA) GA[OFF_W3 + i * MCF_OUT + o] += fabs(cc->h2[i] * gout[o]);
+                    gh2[i] += RND(P[OFF_W3 + i * MCF_OUT + o]) * gout[o];
                 }
             }
             /* second hidden layer (ReLU: zero where the output is zero) */
             double gh1[MCF_HID] = {0};
             for (int o = 0; o < MCF_HID; ++o) {
-                const double d = cc->h2[o] > 0.0 ? gh2[o] : 0.0;
+                const double d = RND(cc->h2[o] > 0.0 ? gh2[o] : 0.0);
                 G[OFF_B2 + o] += d;
+                if (GA) GA[OFF_B2 + o] += fabs(d);
                 for (int i = 0; i < MCF_HID; ++i) {
                     G[OFF_W2 + i * MCF_HID + o] += cc->h1[i] * d;
-                    gh1[i] += P[OFF_W2 + i * MCF_HID + o] * d;
+                    if (GA) GA[OFF_W2 + i * MCF_HID + o] += fabs(cc->h1[i] * d);
+                    gh1[i] += RND(P[OFF_W2 + i * MCF_HID + o]) * d;
                 }
             }
             /* first hidden layer and the encoding */
             double ge[MCF_IN] = {0};
             for (int o = 0; o < MCF_HID; ++o) {
-                const double d = cc->h1[o] > 0.0 ? gh1[o] : 0.0;
+                const double d = RND(cc->h1[o] > 0.0 ? gh1[o] : 0.0);
                 G[OFF_B1 + o] += d;
+                if (GA) GA[OFF_B1 + o] += fabs(d);
                 for (int i = 0; i < MCF_IN; ++i) {
                     G[OFF_W1 + i * MCF_HID + o] += cc->e[i] * d;
-                    ge[i] += P[OFF_W1 + i * MCF_HID + o] * d;
+                    if (GA) GA[OFF_W1 + i * MCF_HID + o] += fabs(cc->e[i] * d);
+                    ge[i] += RND(P[OFF_W1 + i * MCF_HID + o]) * d;
                 }
             }
             for (int a = 0; a < MCF_NA; ++a) {
                 const int j = A_IDX[l][a];
                 for (int k = 0; k < MCF_BLOBS; ++k) {
                     const double t = (uin[l][j] - blob_center(k)) * (double)MCF_BLOBS;
-                    /* de/du = -e t * 32 */
-                    gprev[j] += ge[a * MCF_BLOBS + k] * (-cc->e[a * MCF_BLOBS + k] * t *
-                                                         (double)MCF_BLOBS);
+                    /* de/du = -e t * 32, with e the unrounded bump */
+                    const double e = exp(-0.5 * t * t);
+                    gprev[j] += ge[a * MCF_BLOBS + k] * (-e * t * (double)MCF_BLOBS);
                 }
             }
             memcpy(g, gprev, sizeof g);
         }
     }
     return loss;
+#undef RND
+}
+
+double mcf_loss_grad(const double *theta, int64_t n, const double *xs, const double *ws,
+                     double *grad)
+{
+    return loss_grad(theta, n, xs, ws, 0, grad, NULL);
+}
+
+double mcf_loss_grad_ex(const double *theta, int64_t n, const double *xs, const double *ws,
+                        int use_bf16, double *grad, double *grad_abs)
+{
+    return loss_grad(theta, n, xs, ws, use_bf16 != 0, grad, grad_abs);
 }
 
 /* One Adam step (Kingma & Ba, 2015) with bias correction; step counts from 1. */
@@ -477,7 +547,15 @@ int mcf_proposal_range(const double *theta, int use_bf16, int family, const doub
 /* is the unbiased combination (weighting by the estimated variances, as    */
 /* VEGAS does for iterations whose map changes, favours the iterations that */
 /* missed the rare large weights):                                          */
-/*   Ibar = sum(I_t) / T,  sigma = sqrt(sum v_t) / T,                        */
+/*   Ibar = sum(I_t) / T.                                                   */
+/* Its error is the standard deviation of that mean (the error model of     */
+/* m-Cubes), estimated two ways, the larger one reported:                   */
+/*   from the iterations' own variances   s_w^2 = sum(v_t) / T^2,           */
+/*   from the scatter of their estimates  s_b^2 = sum (I_t - Ibar)^2        */
+/*                                               / (T (T - 1))  (T >= 2).   */
+/* With importance weights of a long tail an iteration's own variance       */
+/* misses the rare large weights it did not draw; an iteration that drew    */
+/* one stands out from the others, which the scatter sees.                  */
 /*   chi2/dof = sum over v_t > 0 of (I_t - Ibar)^2 / v_t, over (T - 1)        */
 /*   (0 when T = 1).                                                         */
 /* out = [Ibar, sigma, chi2/dof]; returns the degrees of freedom T - 1.      */
@@ -496,15 +574,16 @@ int mcf_combine_equal(int T, const double *I, const double *var, double out[3])
         sv = sv + var[t];
     }
     const double Ibar = si / (double)T;
-    double chi2 = 0.0;
+    double chi2 = 0.0, ss = 0.0;
     for (int t = 0; t < T; ++t) {
-        if (var[t] > 0.0) {
-            const double dv = I[t] - Ibar;
-            chi2 = chi2 + dv * dv / var[t];
-        }
+        const double dv = I[t] - Ibar;
+        ss = ss + dv * dv;
+        if (var[t] > 0.0) chi2 = chi2 + dv * dv / var[t];
     }
+    const double s_w = sqrt(sv) / (double)T;
+    const double s_b = T > 1 ? sqrt(ss / ((double)T * (double)(T - 1))) : 0.0;
     out[0] = Ibar;
-    out[1] = sqrt(sv) / (double)T;
+    out[1] = s_b > s_w ? s_b : s_w;
     out[2] = (T > 1) ? chi2 / (double)(T - 1) : 0.0;
     return T - 1;
 }

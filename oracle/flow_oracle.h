@@ -35,8 +35,11 @@ void mcf_density(const double *theta, const double x[MCF_D], int bf16, double z[
                  double *logq);
 void mcf_sample(const double *theta, const double z[MCF_D], int bf16, double x[MCF_D],
                 double *logq);
+void mcf_bf16_array(const double *v, int64_t n, double *out);
 double mcf_loss_grad(const double *theta, int64_t n, const double *xs, const double *ws,
                      double *grad);
+double mcf_loss_grad_ex(const double *theta, int64_t n, const double *xs, const double *ws,
+                        int bf16, double *grad, double *grad_abs);
 void mcf_adam(double *theta, double *m, double *v, const double *grad, int64_t count, int step,
               double lr, double beta1, double beta2, double eps);
 int mcf_proposal_range(const double *theta, int bf16, int family, const double *params, int64_t g,

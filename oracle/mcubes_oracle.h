@@ -42,4 +42,33 @@ int mco_integrate(int family, int dim, const double *params, int64_t ncall, int 
                   int adapt_iters, int skip, double res[3], int64_t info[7], double *grid_out,
                   double *trace_I, double *trace_var);
 
+/* The library's boundary calls, mirrored (mcubes_oracle_abi.c).  The records
+ * have the field order and types of the library's option and result
+ * records. */
+typedef struct {
+    int32_t nbins, adapt_iters, skip, block_size, blocks;
+    uint32_t stream_id;
+    int32_t precision;
+    double alpha;
+    void *stream;
+} mco_options;
+
+typedef struct {
+    double estimate, error, chi2_dof;
+    int32_t iterations, dof, converged, status;
+    int64_t cube_side, ncubes, samples_per_cube, samples_per_iter;
+    double kernel_ms;
+} mco_result;
+
+typedef struct mco_plan_s mco_plan_t;
+
+int mcubes_oracle_integrate(int family, const double *params, int dim, int64_t ncall, int itmax,
+                            double rel_tol, uint64_t seed, const mco_options *opt,
+                            mco_result *out, double *grid_out, double *trace);
+int mcubes_oracle_plan_create(int family, const double *params, int dim, int64_t ncall,
+                              uint64_t seed, const mco_options *opt, mco_plan_t **plan);
+void mcubes_oracle_plan_destroy(mco_plan_t *plan);
+int mcubes_oracle_iterate(mco_plan_t *plan, const double *grid_in, uint32_t iteration, double *I_t,
+                          double *var_t, double *bins_out, double *grid_out);
+
 #endif
