@@ -135,20 +135,34 @@ typedef struct {
     int64_t state_len;     /* MCUBES_STATE_LEN */
 } mcubes_plan_info;
 
-/* Fill *opt with the defaults listed above. */
+/* Fill *opt with the defaults listed above (host only; no error).  Passage:
+ * none -- the defaults are the readings of §3.2 and Alg. 2 (500 bins) and
+ * of the VEGAS refinement §3.2 relies on (damping alpha = 1.5). */
 void mcubes_default_options(mcubes_options *opt);
 
-/* Message describing the calling thread's last error ("" if none). */
+/* Message describing the calling thread's last error ("" if none).  The
+ * string is owned by the library and valid until the thread's next call.
+ * Passage: none (a convention of this interface). */
 const char *mcubes_last_error(void);
 
-/* Stratification of §3.2 (a 2-point MC per sub-cube, about ncall samples):
- * g = largest integer with g^dim <= floor(ncall/2), m = g^dim,
- * p = max(2, floor(ncall/m)), N = m p.  out = [g, m, p, N].  Host only. */
+/* Stratification.  Passage: §3.2 (m-Cubes splits the domain into m equal
+ * sub-cubes and runs a 2-point Monte Carlo in each, about ncall samples in
+ * all).  Reading: g = largest integer with g^dim <= floor(ncall/2),
+ * m = g^dim, p = max(2, floor(ncall/m)), N = m p.  out (host, 4 int64,
+ * caller-owned) = [g, m, p, N].  Host only.  Errors: MCUBES_E_ARG (out NULL,
+ * dim outside [1, MCUBES_MAX_DIM], ncall < 2, m >= 2^32); out untouched. */
 int mcubes_plan_sizes(int dim, int64_t ncall, int64_t out[4]);
 
-/* Whole integrator: uniform start grid, then per iteration t = 0..itmax-1
- * V-Sample -> estimate -> combine -> refine (while t < adapt_iters), stopping
- * after the first iteration whose combined error <= rel_tol * |estimate|.
+/* Whole integrator.  Passage: §3.2 (m-Cubes: iterations of stratified,
+ * importance-sampled Monte Carlo whose separable grid is adapted after each
+ * iteration, until the error estimate -- the standard deviation of the
+ * estimate -- reaches a user-specified threshold) with Alg. 2 as the
+ * iteration; the grid refinement and the combination are the VEGAS ones
+ * (Lepage 1978) that §3.2 builds on.  Uniform start grid, then per
+ * iteration t = 0..itmax-1 V-Sample -> estimate -> combine -> refine (while
+ * t < adapt_iters), stopping after the first iteration whose combined
+ * error <= rel_tol * |estimate|.  params and every output are host memory
+ * owned by the caller; opt may be NULL (defaults).
  * out (host) receives the result.  grid_out (host, dim*(nbins+1), may be
  * NULL) receives the grid after the last refinement.  trace (host, 2*itmax
  * doubles, may be NULL) receives (I_t, var_t) per iteration run.
@@ -158,21 +172,39 @@ int mcubes_integrate(int family, const double *params, int dim, int64_t ncall, i
                      double rel_tol, uint64_t seed, const mcubes_options *opt,
                      mcubes_result *out, double *grid_out, double *trace);
 
-/* Plan: validated problem, stratification and launch geometry for the device
- * entry points below.  opt may be NULL (defaults).  Host memory only; the
- * plan holds no device memory.  Free with mcubes_plan_destroy. */
+/* Plan: validated problem, stratification (§3.2, as mcubes_plan_sizes) and
+ * V-Sample launch geometry for the entry points below.  params: host,
+ * copied.  opt may be NULL (defaults).  *plan receives a plan owned by the
+ * caller, freed with mcubes_plan_destroy (which also frees the workspace
+ * mcubes_iterate allocates on its first call; the other entry points use
+ * caller-owned device buffers, so a plan otherwise holds no device memory).
+ * Errors: MCUBES_E_ARG (sizes, options), MCUBES_E_INTEGRAND (family or
+ * parameters), MCUBES_E_DEVICE (no usable device); *plan untouched.
+ * Passage: Alg. 2's inputs (f, d, the sub-cube count m, the samples per
+ * sub-cube p, the grid B). */
 int mcubes_plan_create(int family, const double *params, int dim, int64_t ncall, uint64_t seed,
                        const mcubes_options *opt, mcubes_plan **plan);
 int mcubes_plan_get_info(const mcubes_plan *plan, mcubes_plan_info *info);
 void mcubes_plan_destroy(mcubes_plan *plan);
 
-/* d_grid (grid_len) <- the uniform grid E_j[i] = i/nbins. */
+/* d_grid (device, grid_len doubles, caller-owned) <- the uniform grid
+ * E_j[i] = i/nbins, the importance grid of the first iteration (§3.2: the
+ * step-function density starts flat).  Enqueued on `stream`. */
 int mcubes_init_grid(const mcubes_plan *plan, double *d_grid, void *stream);
 
-/* d[0..n) <- value (a fill kernel, safe under graph capture). */
+/* d[0..n) <- value: device buffer, caller-owned; a fill kernel (no memset
+ * node, safe under graph capture).  Passage: none (a utility: the bins and
+ * the combined state must start at zero).  MCUBES_E_ARG if n < 0 or d is
+ * NULL with n > 0. */
 int mcubes_fill(double *d, int64_t n, double value, void *stream);
 
-/* V-Sample (Alg. 2) for iteration `iteration` with grid d_grid:
+/* V-Sample.  Passage: Alg. 2 (§3.2): per sub-cube, p samples drawn, mapped
+ * through the grid (Get-Bin-ID), the integrand evaluated, the cube's mean
+ * and variance accumulated (UpdateVariance), the squared sample estimates
+ * added to the bins C they fell in, and the results reduced into the
+ * iteration's integral and variance.  All pointers are caller-owned device
+ * buffers; enqueued on `stream`.  For iteration `iteration` with grid
+ * d_grid:
  *   d_bins[j*nbins + i] += sum of w^2 over the samples that used bin i on axis j;
  *   d_partials[2b], d_partials[2b+1] <- block b's sum of cube sums S_c = sum_k w_ck
  *   and of unbiased in-cube variances var_c.  Sizes from mcubes_plan_get_info.
@@ -181,12 +213,17 @@ int mcubes_fill(double *d, int64_t n, double value, void *stream);
 int mcubes_vsample(const mcubes_plan *plan, uint32_t iteration, const double *d_grid,
                    double *d_bins, double *d_partials, void *stream);
 
-/* Fixed-order reduction of the block partials: d_est[0] = I_t = sum S_c / N,
- * d_est[1] = var_t = sum var_c / (p m^2). */
+/* Fixed-order reduction of the block partials (device, partials_len), the
+ * Reduce step closing Alg. 2: d_est (device, 2 doubles) <- [I_t = sum S_c / N,
+ * var_t = sum var_c / (p m^2)].  Enqueued on `stream`. */
 int mcubes_reduce(const mcubes_plan *plan, const double *d_partials, double *d_est, void *stream);
 
-/* Records (I_t, var_t) = d_est as iteration `iteration` in d_state and
- * recombines iterations skip..iteration (inverse-variance weighting):
+/* Combination of iterations.  Passage: §3.2 (the error estimate is the
+ * standard deviation of the combined estimate); the weighting is the
+ * inverse-variance one of VEGAS (Lepage 1978), which §3.2 cites -- the
+ * paper itself leaves it unstated.  Device buffers, caller-owned; enqueued
+ * on `stream`.  Records (I_t, var_t) = d_est as iteration `iteration` in
+ * d_state and recombines iterations skip..iteration:
  *   d_state[0] = estimate, [1] = error, [2] = chi2/dof, [3] = dof,
  *   [4] = iterations recorded, [5] = converged (error <= rel_tol |estimate|),
  *   [6] = 1 if any recorded estimate was not finite,
@@ -196,18 +233,44 @@ int mcubes_reduce(const mcubes_plan *plan, const double *d_partials, double *d_e
 int mcubes_combine(const mcubes_plan *plan, uint32_t iteration, const double *d_est,
                    double *d_state, double rel_tol, void *stream);
 
-/* VEGAS rebinning of every axis from the bin sums: smooth, damp with alpha,
- * re-divide into bins of equal damped weight.  d_grid_out may not alias
- * d_grid. */
+/* Grid refinement.  Passage: §3.2 (the step-function importance density is
+ * adapted between iterations from the bin contributions C of Alg. 2); the
+ * rule is VEGAS's (Lepage 1978), which the paper does not spell out: per
+ * axis, smooth the bin sums over neighbours, damp them as
+ * ((r - 1)/ln r)^alpha, and re-divide into bins of equal damped weight.
+ * Device buffers, caller-owned; d_grid_out may not alias d_grid
+ * (MCUBES_E_ARG).  Enqueued on `stream`. */
 int mcubes_refine(const mcubes_plan *plan, const double *d_grid, const double *d_bins,
                   double *d_grid_out, void *stream);
 
-/* One whole iteration: zero d_bins, V-Sample, reduce, combine, then refine
+/* One whole iteration (Alg. 2 and the §3.2 loop body) on caller-owned
+ * device buffers: zero d_bins, V-Sample, reduce, combine, then refine
  * d_grid into d_grid_out.  When iteration >= adapt_iters the grid is copied
- * unchanged and V-Sample runs without bin sums (d_bins is left untouched). */
+ * unchanged and V-Sample runs without bin sums (d_bins is left untouched).
+ * Enqueued on `stream`. */
 int mcubes_iteration(const mcubes_plan *plan, uint32_t iteration, const double *d_grid,
                      double *d_grid_out, double *d_bins, double *d_partials, double *d_est,
                      double *d_state, double rel_tol, void *stream);
+
+/* One iteration on host buffers: Alg. 2's inputs and outputs (§3.2) -- the
+ * grid B in, the iteration estimate r = (I_t, var_t) and the bin sums C out
+ * -- plus the refined grid.
+ *   grid_in (host, grid_len doubles): the grid to sample with; every row
+ *     must run from 0 to 1, finite and nondecreasing (MCUBES_E_ARG).
+ *   *I_t, *var_t (host): the iteration estimate and its variance, as
+ *     mcubes_reduce gives them.
+ *   bins_out (host, bins_len doubles, may be NULL): the bin sums C.
+ *   grid_out (host, grid_len doubles, may be NULL): the grid refined from
+ *     those bins (as mcubes_refine), whatever adapt_iters says.
+ * The samples are those of iteration `iteration` of mcubes_integrate with
+ * the same plan.  Runs on the plan's options stream and returns when done.
+ * The first call allocates a device workspace owned by the plan (freed by
+ * mcubes_plan_destroy); later calls allocate nothing.  Errors leave every
+ * output untouched: MCUBES_E_ARG, MCUBES_E_NONFINITE (I_t or var_t not
+ * finite), MCUBES_E_ALLOC, MCUBES_E_DEVICE.  The plan is used from one host
+ * thread at a time. */
+int mcubes_iterate(mcubes_plan *plan, const double *grid_in, uint32_t iteration, double *I_t,
+                   double *var_t, double *bins_out, double *grid_out);
 
 /* Microbenchmarks that attribute V-Sample's time (the analogue of the
  * integrand-invocation experiment of §5.1 of the paper).  Each of the
@@ -463,17 +526,26 @@ int mcubes_flow_vsample(mcubes_flow *flow, int precision, const mcubes_plan *pla
 /* Combination of flow-mapped iterations 0..iteration with the same flow and
  * plan (an extension: the paper combines only map-adapting iterations).
  * They are independent estimates of one distribution, so they are averaged
- * with equal weights:
- *   Ibar = sum(I_t) / T,  sigma = sqrt(sum var_t) / T,  T = iteration + 1,
- *   chi2/dof = sum over var_t > 0 of (I_t - Ibar)^2 / var_t, over T - 1.
+ * with equal weights, and the error is the standard deviation of that mean
+ * (the error model of §3.2), estimated both from the iterations' own
+ * variances and from the scatter of their estimates, the larger reported:
+ *   Ibar = sum(I_t) / T,  T = iteration + 1,
+ *   sigma = max(sqrt(sum var_t) / T, sqrt(sum (I_t - Ibar)^2 / (T (T - 1))))
+ *     (the second term only for T >= 2),
+ *   chi2/dof = sum over var_t > 0 of (I_t - Ibar)^2 / var_t, over T - 1,
+ *   converged (d_state[5]) = T >= min_iters and sigma <= rel_tol |Ibar|.
  * (Inverse-variance weighting, mcubes_combine, is biased low here: with a
  * long-tailed weight distribution an iteration that caught a large weight
- * also has a large variance estimate and is weighted down.)  d_est and
- * d_state as for mcubes_combine, same header layout; d_state must start
- * zeroed.  Stream-ordered; errors: MCUBES_E_ARG (NULL pointer, iteration >=
- * MCUBES_MAX_ITERATIONS, rel_tol not finite or < 0), MCUBES_E_HIP. */
+ * also has a large variance estimate and is weighted down; for the same
+ * reason an iteration's own variance is usually too small, while an
+ * iteration that caught a large weight stands out in the scatter.)  d_est
+ * and d_state as for mcubes_combine, same header layout (device,
+ * caller-owned); d_state must start zeroed.  Stream-ordered; errors:
+ * MCUBES_E_ARG (NULL pointer, iteration >= MCUBES_MAX_ITERATIONS, rel_tol
+ * not finite or < 0, min_iters outside [1, MCUBES_MAX_ITERATIONS]),
+ * MCUBES_E_DEVICE. */
 int mcubes_flow_combine(uint32_t iteration, const double *d_est, double *d_state, double rel_tol,
-                        void *stream);
+                        int min_iters, void *stream);
 
 /* Tail diagnostic of importance weights.  Each mcubes_flow_vsample call
  * histograms log2 of its weights w = f/q: MCUBES_WTAIL_BINS bins, bin b
@@ -517,14 +589,19 @@ int mcubes_flow_weight_tail(mcubes_flow *flow, double *shape, int64_t *tail_coun
  *      Kullback-Leibler objective, power 1, and the variance, power 2) at
  *      learning rate tail_lr;
  *   4. flow-mapped iterations (mcubes_flow_vsample, in `precision`) combined
- *      with equal weights (mcubes_flow_combine) until error <= rel_tol
- *      |estimate| or itmax of them.
+ *      with equal weights (mcubes_flow_combine) until, after at least
+ *      min_iters of them, error <= rel_tol |estimate| and the weight tail
+ *      allows trusting that error (below), or itmax of them.
  * Plain m-Cubes stays the judge: if the first flow iteration's variance is
  * not below the last plain iteration's, the flow is dropped and the
- * remaining iterations run plain (report->used_flow = 0).  A flow result
- * whose weight-tail shape (report->tail_shape, the largest over its
- * iterations) reaches 0.5 is never reported converged: its error bar has
- * no meaning (see mcubes_weight_tail_shape).  `flow` is trained
+ * remaining iterations run plain (report->used_flow = 0).  The weight
+ * histograms of the flow iterations are pooled; report->tail_shape is the
+ * weight-tail shape of the pooled histogram (see mcubes_weight_tail_shape).
+ * A flow result is reported converged only if that shape is below 0.25,
+ * or below 0.5 with the iterations agreeing within their stated errors
+ * (chi2/dof below its 99% point): at 0.5 and above the variance is
+ * infinite, and from 0.25 the variance estimates are themselves
+ * unreliable.  `flow` is trained
  * in place (start from an identity flow for a fresh run).  out receives the
  * combined result of the iterations that decide it (flow, or plain on
  * fallback).  Synchronous; allocates its buffers.
@@ -549,6 +626,8 @@ typedef struct {
     int32_t train_precision; /* training products: MCUBES_BF16 (default) or MCUBES_FP32 */
     int32_t anchor_rounds; /* default 2: how many of the first `rounds` also train on
                               the warm-up samples */
+    int32_t min_iters;     /* default 4: flow iterations before a result may count as
+                              converged (1..itmax) */
 } mcubes_flow_options;
 
 typedef struct {
@@ -557,7 +636,8 @@ typedef struct {
     double last_plain_var, first_flow_var; /* the judge's comparison */
     double final_loss;     /* mean batch loss of the last training epoch */
     int32_t flow_iterations, used_flow;
-    double tail_shape;     /* largest weight-tail shape of the flow iterations (NaN if none) */
+    double tail_shape;     /* weight-tail shape of the flow iterations' pooled weights
+                              (NaN if none) */
 } mcubes_flow_report;
 
 void mcubes_default_flow_options(mcubes_flow_options *opt);

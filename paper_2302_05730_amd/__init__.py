@@ -71,7 +71,8 @@ class mcubes_flow_options(ctypes.Structure):
                 ("round_epochs", ctypes.c_int32), ("tail_rounds", ctypes.c_int32),
                 ("batch", ctypes.c_int64), ("lr", ctypes.c_double), ("round_lr", ctypes.c_double),
                 ("tail_power", ctypes.c_double), ("tail_lr", ctypes.c_double),
-                ("train_precision", ctypes.c_int32), ("anchor_rounds", ctypes.c_int32)]
+                ("train_precision", ctypes.c_int32), ("anchor_rounds", ctypes.c_int32),
+                ("min_iters", ctypes.c_int32)]
 
 
 class mcubes_flow_report(ctypes.Structure):
@@ -135,6 +136,7 @@ _SIGNATURES = {
     "mcubes_refine": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "mcubes_iteration": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp, _vp,
                                         ctypes.c_double, _vp]),
+    "mcubes_iterate": (ctypes.c_int, [_vp, _dp, ctypes.c_uint32, _dp, _dp, _dp, _dp]),
     "mcubes_microbench": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _vp,
                                          ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                          _vp, _vp]),
@@ -165,7 +167,8 @@ _SIGNATURES = {
     "mcubes_vsample_dump": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, ctypes.c_int64,
                                            ctypes.c_int64, _vp, _vp, _vp]),
     "mcubes_flow_vsample": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_uint32, _vp, _vp]),
-    "mcubes_flow_combine": (ctypes.c_int, [ctypes.c_uint32, _vp, _vp, ctypes.c_double, _vp]),
+    "mcubes_flow_combine": (ctypes.c_int, [ctypes.c_uint32, _vp, _vp, ctypes.c_double,
+                                           ctypes.c_int, _vp]),
     "mcubes_flow_shuffle": (ctypes.c_int, [_vp, _vp, ctypes.c_int64, _vp, _vp, _vp]),
     "mcubes_flow_draw": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_uint32, ctypes.c_int64,
                                         _vp, _vp, _vp]),
@@ -263,11 +266,10 @@ def mcubes_integrate(family, params, dim, ncall, itmax, rel_tol, seed, options=N
     nb = opt.nbins
     g_buf = (ctypes.c_double * (dim * (nb + 1)))() if grid else None
     t_buf = (ctypes.c_double * (2 * itmax))() if trace else None
-    rc = lib().mcubes_integrate(int(family), pp, int(dim), int(ncall), int(itmax),
-                                float(rel_tol), int(seed) & (2**64 - 1), ctypes.byref(opt),
-                                ctypes.byref(res),
-                                ctypes.cast(g_buf, _dp) if grid else None,
-                                ctypes.cast(t_buf, _dp) if trace else None)
+    rc = lib().mcubes_integrate(int(family), pp, int(dim), int(ncall), int(itmax), float(rel_tol),
+            int(seed) & (2**64 - 1), ctypes.byref(opt), ctypes.byref(res),
+            ctypes.cast(g_buf, _dp) if grid else None,
+            ctypes.cast(t_buf, _dp) if trace else None)
     _check(rc, allow=(MCUBES_OK, MCUBES_NOT_CONVERGED))
     out = {f: getattr(res, f) for f, _ in mcubes_result._fields_}
     out["converged"] = bool(out["converged"])
@@ -344,10 +346,10 @@ def mcubes_combine(plan, iteration, d_est, d_state, rel_tol, stream=None):
                                 _stream(stream)))
 
 
-def mcubes_flow_combine(iteration, d_est, d_state, rel_tol, stream=None):
+def mcubes_flow_combine(iteration, d_est, d_state, rel_tol, min_iters=1, stream=None):
     _check(lib().mcubes_flow_combine(int(iteration), _dev(d_est, 2, "est"),
                                      _dev(d_state, MCUBES_STATE_LEN, "state"), float(rel_tol),
-                                     _stream(stream)))
+                                     int(min_iters), _stream(stream)))
 
 
 def mcubes_flow_shuffle(d_x, d_w, n, d_x_out, d_w_out, stream=None):
@@ -373,6 +375,25 @@ def mcubes_iteration(plan, iteration, d_grid, d_grid_out, d_bins, d_partials, d_
                                   _dev(d_partials, i["partials_len"], "partials"),
                                   _dev(d_est, 2, "est"), _dev(d_state, MCUBES_STATE_LEN, "state"),
                                   float(rel_tol), _stream(stream)))
+
+
+def mcubes_iterate(plan, grid_in, iteration, bins=True, refine=True):
+    """One iteration on host arrays: grid_in (dim x (nbins+1)) -> (I_t, var_t,
+    bins or None, refined grid or None)."""
+    import numpy as np
+    i = plan.info
+    g = np.ascontiguousarray(grid_in, dtype=np.float64).reshape(-1)
+    if g.size != i["grid_len"]:
+        raise ValueError(f"grid_in holds {g.size} values, the plan needs {i['grid_len']}")
+    I_t, var_t = ctypes.c_double(), ctypes.c_double()
+    b = np.zeros(i["bins_len"]) if bins else None
+    go = np.zeros(i["grid_len"]) if refine else None
+    ptr = lambda a: a.ctypes.data_as(_dp) if a is not None else None  # noqa: E731
+    _check(lib().mcubes_iterate(plan.handle, ptr(g), int(iteration), ctypes.byref(I_t),
+                                ctypes.byref(var_t), ptr(b), ptr(go)))
+    shape_b, shape_g = (i["dim"], i["nbins"]), (i["dim"], i["nbins"] + 1)
+    return (I_t.value, var_t.value, b.reshape(shape_b) if bins else None,
+            go.reshape(shape_g) if refine else None)
 
 
 def mcubes_microbench(kind, d_out, blocks, block, calls_per_thread, family=0, params=None, dim=1,

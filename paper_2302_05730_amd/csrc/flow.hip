@@ -461,7 +461,7 @@ __global__ void zero_u32_kernel(uint32_t *__restrict__ p, int64_t n) {
 // weights).  Ibar = sum I / T, sigma = sqrt(sum var) / T, chi2/dof over the
 // iterations with var > 0.  Header layout as for the plain combination.
 __global__ void flow_combine_kernel(const double *__restrict__ est, double *__restrict__ state,
-                                    uint32_t t, double rel_tol) {
+                                    uint32_t t, double rel_tol, int min_iters) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double *hist = state + MCUBES_STATE_HEADER;
     const double It = est[0], Vt = est[1];
@@ -475,21 +475,24 @@ __global__ void flow_combine_kernel(const double *__restrict__ est, double *__re
         sv = sv + hist[2 * q + 1];
     }
     const double Ibar = si / (double)T;
-    double chi2 = 0.0;
+    double chi2 = 0.0, ss = 0.0;
     for (int q = 0; q < T; ++q) {
+        const double dv = hist[2 * q] - Ibar;
+        ss = ss + dv * dv;
         const double v = hist[2 * q + 1];
-        if (v > 0.0) {
-            const double dv = hist[2 * q] - Ibar;
-            chi2 = chi2 + dv * dv / v;
-        }
+        if (v > 0.0) chi2 = chi2 + dv * dv / v;
     }
-    const double sigma = sqrt(sv) / (double)T;
+    // the standard deviation of the mean, from the iterations' own variances
+    // and from the scatter of their estimates; the larger is reported
+    const double s_w = sqrt(sv) / (double)T;
+    const double s_b = T > 1 ? sqrt(ss / ((double)T * (double)(T - 1))) : 0.0;
+    const double sigma = s_b > s_w ? s_b : s_w;
     state[0] = Ibar;
     state[1] = sigma;
     state[2] = T > 1 ? chi2 / (double)(T - 1) : 0.0;
     state[3] = (double)(T - 1);
     state[4] = (double)T;
-    state[5] = sigma <= rel_tol * fabs(Ibar) ? 1.0 : 0.0;
+    state[5] = (T >= min_iters && sigma <= rel_tol * fabs(Ibar)) ? 1.0 : 0.0;
 }
 
 // Row j of the output is row (a j) mod n of the input (x: 6 doubles per row,
@@ -901,9 +904,9 @@ hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s) {
 }
 
 hipError_t launch_flow_combine(const double *est, double *state, uint32_t iteration,
-                               double rel_tol, hipStream_t s) {
+                               double rel_tol, int min_iters, hipStream_t s) {
     hipLaunchKernelGGL(flow_combine_kernel, dim3(1), dim3(64), 0, s, est, state, iteration,
-                       rel_tol);
+                       rel_tol, min_iters);
     return hipGetLastError();
 }
 

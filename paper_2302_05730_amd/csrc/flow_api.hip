@@ -36,6 +36,30 @@ namespace {
 constexpr int64_t kMaxSamples = (int64_t)1 << 31;
 constexpr int kVsBlocks = 2048;  // workgroups of the flow-mapped iteration (grid-stride)
 constexpr double kTailLimit = 0.5;  // weight-tail shape from which the variance is infinite
+// from this shape on the variance estimates have no finite variance of their
+// own (no fourth moment): the error bar is trusted only when the iterations
+// agree with each other
+constexpr double kTailHeavy = 0.25;
+
+// Upper 99% point of chi^2 with k degrees of freedom per degree of freedom
+// (Wilson-Hilferty: chi^2_k / k is close to normal after a cube root).
+double chi2_dof_99(int k) {
+    if (k < 1) return INFINITY;
+    const double a = 2.0 / (9.0 * k), z = 2.3263478740408408;
+    const double c = 1.0 - a + z * sqrt(a);
+    return c * c * c;
+}
+
+// Whether the error bar of flow iterations with pooled weight-tail shape xi
+// and scatter chi2/dof (dof degrees of freedom) can be trusted: always
+// below kTailHeavy, never from kTailLimit on, in between when the
+// iterations agree within their stated errors (chi2/dof below its 99%
+// point).  An undetermined shape (too few weights) is not trusted.
+bool tail_trusted(double xi, double chi2_dof, int dof) {
+    if (!(xi < kTailLimit)) return false;
+    if (xi < kTailHeavy) return true;
+    return dof >= 1 && chi2_dof <= chi2_dof_99(dof);
+}
 
 void release(mcubes_flow *F) {
     if (!F) return;
@@ -410,13 +434,16 @@ int mcubes_flow_shuffle(const double *d_x, const double *d_w, int64_t n, double 
 }
 
 int mcubes_flow_combine(uint32_t iteration, const double *d_est, double *d_state, double rel_tol,
-                        void *stream) {
+                        int min_iters, void *stream) {
     if (!d_est || !d_state) return fail(MCUBES_E_ARG, "NULL argument");
     if (iteration >= MCUBES_MAX_ITERATIONS)
         return fail(MCUBES_E_ARG, "iteration %u >= %d", iteration, MCUBES_MAX_ITERATIONS);
     if (!(rel_tol >= 0.0) || !isfinite(rel_tol))
         return fail(MCUBES_E_ARG, "rel_tol must be finite and >= 0");
-    const hipError_t e = launch_flow_combine(d_est, d_state, iteration, rel_tol, as_stream(stream));
+    if (min_iters < 1 || min_iters > MCUBES_MAX_ITERATIONS)
+        return fail(MCUBES_E_ARG, "min_iters must be in [1, %d]", MCUBES_MAX_ITERATIONS);
+    const hipError_t e =
+        launch_flow_combine(d_est, d_state, iteration, rel_tol, min_iters, as_stream(stream));
     return e == hipSuccess ? MCUBES_OK : hip_fail(e, "flow combine launch");
 }
 
@@ -469,6 +496,7 @@ void mcubes_default_flow_options(mcubes_flow_options *o) {
     o->tail_lr = 8e-4;
     o->train_precision = MCUBES_BF16;
     o->anchor_rounds = 2;
+    o->min_iters = 4;
 }
 
 int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int64_t ncall,
@@ -487,7 +515,7 @@ int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int6
         fo.train_items < 1 || !(fo.tail_power >= 1.0 && fo.tail_power <= 4.0) ||
         !(fo.tail_lr > 0.0) ||
         (fo.train_precision != MCUBES_FP32 && fo.train_precision != MCUBES_BF16) ||
-        fo.anchor_rounds < 0 ||
+        fo.anchor_rounds < 0 || fo.min_iters < 1 || fo.min_iters > itmax ||
         fo.round_samples < 1 || fo.round_samples > ((int64_t)1 << 31) || !(fo.lr > 0.0) ||
         !(fo.round_lr > 0.0) || (fo.precision != MCUBES_FP32 && fo.precision != MCUBES_BF16))
         return fail(MCUBES_E_ARG, "invalid flow options");
@@ -520,6 +548,7 @@ int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int6
     mcubes_flow_report R;
     memset(&R, 0, sizeof R);
     int done = 0, used = 1, plain_t = fo.warmup_iters;
+    std::vector<uint32_t> hist(MCUBES_WTAIL_BINS), pooled(MCUBES_WTAIL_BINS, 0u);
     float ms = 0.0f;
     hipError_t e = hipMalloc(&buf, (size_t)total * sizeof(double));
     if (e != hipSuccess) {
@@ -610,12 +639,14 @@ int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int6
     R.plain_estimate = head[0];
     R.plain_error = head[1];
     R.plain_chi2_dof = head[2];
-    // 4. flow-mapped iterations, judged against the plain method
+    // 4. flow-mapped iterations, judged against the plain method.  Their
+    // weight histograms are pooled: the tail shape of all flow samples so far.
     for (int t = 0; t < itmax; ++t) {
         const uint32_t it = (uint32_t)(fo.warmup_iters + t);
         if (used) {
             FI_CALL(mcubes_flow_vsample(F, fo.precision, P, it, est, opt.stream));
-            FI_CALL(mcubes_flow_combine((uint32_t)t, est, st_flow, rel_tol, opt.stream));
+            FI_CALL(mcubes_flow_combine((uint32_t)t, est, st_flow, rel_tol, fo.min_iters,
+                                        opt.stream));
         } else {
             // plain iterations continue from the warm-up's grid and state
             FI_CALL(mcubes_iteration(P, (uint32_t)plain_t, grid[plain_t & 1],
@@ -628,11 +659,13 @@ int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int6
         double ev_var = 0.0;
         FI_CHECK(hipMemcpyAsync(&ev_var, est + 1, sizeof ev_var, hipMemcpyDeviceToHost, s),
                  "hipMemcpyAsync");
+        if (used)
+            FI_CHECK(hipMemcpyAsync(hist.data(), F->d_whist, hist.size() * sizeof(uint32_t),
+                                    hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
         FI_CHECK(hipStreamSynchronize(s), "hipStreamSynchronize");
         if (used) {
-            double xi = NAN;
-            FI_CALL(mcubes_flow_weight_tail(F, &xi, nullptr));
-            if (isnan(R.tail_shape) || xi > R.tail_shape) R.tail_shape = xi;
+            for (size_t b = 0; b < hist.size(); ++b) pooled[b] += hist[b];
+            FI_CALL(mcubes_weight_tail_shape(pooled.data(), &R.tail_shape, nullptr));
         }
         done = t + 1;
         if (used && t == 0) {
@@ -640,6 +673,7 @@ int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int6
             if (!(ev_var < R.last_plain_var)) {
                 used = 0;  // the flow lost: continue with plain iterations
                 state = st_plain;
+                R.tail_shape = NAN;
                 continue;
             }
         }
@@ -647,7 +681,7 @@ int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int6
             rc = fail(MCUBES_E_NONFINITE, "iteration %d produced a non-finite estimate", t);
             goto cleanup;
         }
-        if (head[5] != 0.0) break;
+        if (head[5] != 0.0 && (!used || tail_trusted(R.tail_shape, head[2], (int)head[3]))) break;
     }
     FI_CHECK(hipEventRecord(ev[3], s), "hipEventRecord");
     FI_CHECK(hipEventSynchronize(ev[3]), "hipEventSynchronize");
@@ -668,8 +702,9 @@ int mcubes_flow_integrate(mcubes_flow *F, int family, const double *params, int6
     out->dof = (int32_t)head[3];
     out->iterations = (int32_t)head[4];
     // the error bar of flow iterations whose weights have no finite
-    // variance (tail shape >= 1/2) means nothing: never call that converged
-    out->converged = head[5] != 0.0 && !(used && R.tail_shape >= kTailLimit);
+    // variance (tail shape >= 1/2) means nothing: never call that converged;
+    // between 1/4 and 1/2 only when the iterations agree with each other
+    out->converged = head[5] != 0.0 && (!used || tail_trusted(R.tail_shape, head[2], (int)head[3]));
     out->cube_side = P->g;
     out->ncubes = P->m;
     out->samples_per_cube = P->p;

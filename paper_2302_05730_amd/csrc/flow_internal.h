@@ -15,9 +15,10 @@ int64_t flow_scratch_floats(int64_t n);
 int64_t flow_transposed_floats();
 hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
 // Records flow-mapped iteration `iteration`'s (I_t, var_t) from est in the
-// combined state and recombines iterations 0..iteration with equal weights.
+// combined state and recombines iterations 0..iteration with equal weights;
+// converged only from min_iters iterations on.
 hipError_t launch_flow_combine(const double *est, double *state, uint32_t iteration,
-                               double rel_tol, hipStream_t s);
+                               double rel_tol, int min_iters, hipStream_t s);
 // Row j of (xo, wo) <- row (a j) mod n of (x, w); needs n < 2^32, a < 2^32
 // and gcd(a, n) = 1.
 hipError_t launch_flow_shuffle(const double *x, const double *w, int64_t n, uint64_t a,

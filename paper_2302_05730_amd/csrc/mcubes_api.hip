@@ -176,37 +176,9 @@ int check_sizes(int64_t m, int64_t p, int dim) {
     return MCUBES_OK;
 }
 
-}  // namespace mcubes
 
-extern "C" {
-
-void mcubes_default_options(mcubes_options *opt) {
-    if (!opt) return;
-    opt->nbins = 500;
-    opt->adapt_iters = -1;
-    opt->skip = 0;
-    opt->block_size = 0;
-    opt->blocks = 0;
-    opt->stream_id = 0;
-    opt->precision = MCUBES_FP64;
-    opt->alpha = 1.5;
-    opt->stream = nullptr;
-}
-
-const char *mcubes_last_error(void) { return g_error.c_str(); }
-
-int mcubes_plan_sizes(int dim, int64_t ncall, int64_t out[4]) {
-    if (!out) return fail(MCUBES_E_ARG, "out is NULL");
-    int64_t tmp[4];
-    const int rc = plan_sizes(dim, ncall, tmp);
-    if (rc != MCUBES_OK) return rc;
-    memcpy(out, tmp, sizeof tmp);
-    return MCUBES_OK;
-}
-
-int mcubes_plan_create(int family, const double *params, int dim, int64_t ncall, uint64_t seed,
-                       const mcubes_options *opt_in, mcubes_plan **plan_out) {
-    if (!plan_out) return fail(MCUBES_E_ARG, "plan is NULL");
+int plan_init(int family, const double *params, int dim, int64_t ncall, uint64_t seed,
+              const mcubes_options *opt_in, mcubes_plan *P) {
     mcubes_options opt;
     mcubes_default_options(&opt);
     if (opt_in) opt = *opt_in;
@@ -276,8 +248,6 @@ int mcubes_plan_create(int family, const double *params, int dim, int64_t ncall,
     if (blocks < 1) blocks = 1;
     if (blocks * block > 0x7FFFFFFFll) return fail(MCUBES_E_ARG, "too many threads");
 
-    mcubes_plan *P = new (std::nothrow) mcubes_plan();
-    if (!P) return fail(MCUBES_E_ALLOC, "out of host memory");
     P->family = family;
     P->precision = opt.precision;
     P->dim = dim;
@@ -295,9 +265,159 @@ int mcubes_plan_create(int family, const double *params, int dim, int64_t ncall,
     P->launch[0] = kern_set.launch[prec][1][variant];
     P->launch[1] = kern_set.launch[prec][0][variant];
     P->func = kfunc;
+    P->stream = opt.stream;
+    P->ws = nullptr;
+    P->ws_len = 0;
 
     make_args(family, params, dim, g, m, p, nb, seed, opt.stream_id, P->args);
     set_step(P->args, dim, (uint64_t)blocks * (uint64_t)block);
+    return MCUBES_OK;
+}
+
+
+// Device buffers of integrate_run, in doubles: two grids, the bins, the
+// block partials, the iteration estimate and the combined state.
+int64_t integrate_buffer_len(const mcubes_plan &P) {
+    const int64_t ng = (int64_t)P.dim * (P.nb + 1), nbn = (int64_t)P.dim * P.nb;
+    return 2 * ng + nbn + 2 * (int64_t)P.blocks + 2 + MCUBES_STATE_LEN;
+}
+
+int integrate_run(const mcubes_plan &Pr, double *buf, int itmax, double rel_tol, bool timed,
+                  mcubes_result *out, double *grid_out, double *trace) {
+    const mcubes_plan *P = &Pr;
+    hipStream_t s = as_stream(P->stream);
+    const int64_t ng = (int64_t)P->dim * (P->nb + 1), nbn = (int64_t)P->dim * P->nb;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double head[MCUBES_STATE_HEADER];
+    double kernel_ms = 0.0;
+    int done = 0, rc = MCUBES_OK;
+    hipError_t e = hipSuccess;
+    double *grid[2] = {buf, buf + ng};
+    double *bins = buf + 2 * ng;
+    double *partials = bins + nbn;
+    double *est = partials + 2 * (int64_t)P->blocks;
+    double *state = est + 2;
+    memset(head, 0, sizeof head);
+
+#define MC_CHECK(expr, what)                 \
+    do {                                     \
+        e = (expr);                          \
+        if (e != hipSuccess) {               \
+            rc = hip_fail(e, what);          \
+            goto cleanup;                    \
+        }                                    \
+    } while (0)
+#define MC_CALL(expr)                        \
+    do {                                     \
+        rc = (expr);                         \
+        if (rc != MCUBES_OK) goto cleanup;   \
+    } while (0)
+
+    if (timed) {
+        MC_CHECK(hipEventCreate(&ev0), "hipEventCreate");
+        MC_CHECK(hipEventCreate(&ev1), "hipEventCreate");
+    }
+    MC_CHECK(launch_init_grid(grid[0], P->dim, P->nb, s), "init_grid launch");
+    MC_CHECK(launch_fill(state, MCUBES_STATE_LEN, 0.0, s), "fill launch");
+    for (int t = 0; t < itmax; ++t) {
+        double *g_in = grid[t & 1], *g_out = grid[(t + 1) & 1];
+        const bool refine = P->adapt_iters < 0 || t < P->adapt_iters;
+        if (refine) MC_CHECK(launch_fill(bins, nbn, 0.0, s), "fill launch");
+        if (timed) MC_CHECK(hipEventRecord(ev0, s), "hipEventRecord");
+        MC_CALL(mcubes_vsample(P, (uint32_t)t, g_in, refine ? bins : nullptr, partials,
+                               P->stream));
+        if (timed) MC_CHECK(hipEventRecord(ev1, s), "hipEventRecord");
+        MC_CALL(mcubes_reduce(P, partials, est, P->stream));
+        MC_CALL(mcubes_combine(P, (uint32_t)t, est, state, rel_tol, P->stream));
+        if (refine)
+            MC_CALL(mcubes_refine(P, g_in, bins, g_out, P->stream));
+        else
+            MC_CHECK(launch_copy(g_in, g_out, ng, s), "copy launch");
+        MC_CHECK(hipMemcpyAsync(head, state, sizeof head, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+        MC_CHECK(hipStreamSynchronize(s), "hipStreamSynchronize");
+        if (timed) {
+            float ms = 0.0f;
+            MC_CHECK(hipEventElapsedTime(&ms, ev0, ev1), "hipEventElapsedTime");
+            kernel_ms += ms;
+        }
+        done = t + 1;
+        if (head[6] != 0.0) {
+            rc = fail(MCUBES_E_NONFINITE, "iteration %d produced a non-finite estimate", t);
+            goto cleanup;
+        }
+        if (head[5] != 0.0) break;
+    }
+    if (trace) {
+        MC_CHECK(hipMemcpyAsync(trace, state + MCUBES_STATE_HEADER,
+                                (size_t)(2 * done) * sizeof(double), hipMemcpyDeviceToHost, s),
+                 "hipMemcpyAsync trace");
+    }
+    if (grid_out) {
+        MC_CHECK(hipMemcpyAsync(grid_out, grid[done & 1], (size_t)ng * sizeof(double),
+                                hipMemcpyDeviceToHost, s),
+                 "hipMemcpyAsync grid");
+    }
+    MC_CHECK(hipStreamSynchronize(s), "hipStreamSynchronize");
+    out->estimate = head[0];
+    out->error = head[1];
+    out->chi2_dof = head[2];
+    out->dof = (int32_t)head[3];
+    out->iterations = done;
+    out->converged = head[5] != 0.0;
+    out->cube_side = P->g;
+    out->ncubes = P->m;
+    out->samples_per_cube = P->p;
+    out->samples_per_iter = P->n;
+    out->kernel_ms = kernel_ms;
+    rc = out->converged ? MCUBES_OK : MCUBES_NOT_CONVERGED;
+    out->status = rc;
+
+cleanup:
+#undef MC_CHECK
+#undef MC_CALL
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    return rc;
+}
+
+}  // namespace mcubes
+
+extern "C" {
+
+void mcubes_default_options(mcubes_options *opt) {
+    if (!opt) return;
+    opt->nbins = 500;
+    opt->adapt_iters = -1;
+    opt->skip = 0;
+    opt->block_size = 0;
+    opt->blocks = 0;
+    opt->stream_id = 0;
+    opt->precision = MCUBES_FP64;
+    opt->alpha = 1.5;
+    opt->stream = nullptr;
+}
+
+const char *mcubes_last_error(void) { return g_error.c_str(); }
+
+int mcubes_plan_sizes(int dim, int64_t ncall, int64_t out[4]) {
+    if (!out) return fail(MCUBES_E_ARG, "out is NULL");
+    int64_t tmp[4];
+    const int rc = plan_sizes(dim, ncall, tmp);
+    if (rc != MCUBES_OK) return rc;
+    memcpy(out, tmp, sizeof tmp);
+    return MCUBES_OK;
+}
+
+int mcubes_plan_create(int family, const double *params, int dim, int64_t ncall, uint64_t seed,
+                       const mcubes_options *opt_in, mcubes_plan **plan_out) {
+    if (!plan_out) return fail(MCUBES_E_ARG, "plan is NULL");
+    mcubes_plan *P = new (std::nothrow) mcubes_plan();
+    if (!P) return fail(MCUBES_E_ALLOC, "out of host memory");
+    const int rc = plan_init(family, params, dim, ncall, seed, opt_in, P);
+    if (rc != MCUBES_OK) {
+        delete P;
+        return rc;
+    }
     *plan_out = P;
     return MCUBES_OK;
 }
@@ -322,7 +442,11 @@ int mcubes_plan_get_info(const mcubes_plan *P, mcubes_plan_info *info) {
     return MCUBES_OK;
 }
 
-void mcubes_plan_destroy(mcubes_plan *P) { delete P; }
+void mcubes_plan_destroy(mcubes_plan *P) {
+    if (!P) return;
+    if (P->ws) (void)hipFree(P->ws);
+    delete P;
+}
 
 int mcubes_init_grid(const mcubes_plan *P, double *d_grid, void *stream) {
     if (!P || !d_grid) return fail(MCUBES_E_ARG, "NULL argument");
@@ -400,6 +524,61 @@ int mcubes_iteration(const mcubes_plan *P, uint32_t iteration, const double *d_g
     return e == hipSuccess ? MCUBES_OK : hip_fail(e, "copy launch");
 }
 
+int mcubes_iterate(mcubes_plan *P, const double *grid_in, uint32_t iteration, double *I_t,
+                   double *var_t, double *bins_out, double *grid_out) {
+    if (!P || !grid_in || !I_t || !var_t) return fail(MCUBES_E_ARG, "NULL argument");
+    const int nb = P->nb;
+    for (int j = 0; j < P->dim; ++j) {
+        const double *e = grid_in + (size_t)j * (nb + 1);
+        if (e[0] != 0.0 || e[nb] != 1.0)
+            return fail(MCUBES_E_ARG, "grid row %d does not run from 0 to 1", j);
+        for (int i = 0; i < nb; ++i)
+            if (!isfinite(e[i + 1]) || !(e[i + 1] >= e[i]))
+                return fail(MCUBES_E_ARG, "grid row %d is not nondecreasing at edge %d", j, i + 1);
+    }
+    const int64_t ng = (int64_t)P->dim * (nb + 1), nbn = (int64_t)P->dim * nb;
+    const int64_t need = 2 * ng + nbn + 2 * (int64_t)P->blocks + 2;
+    hipError_t e = hipSuccess;
+    if (!P->ws) {
+        e = hipMalloc(&P->ws, (size_t)need * sizeof(double));
+        if (e != hipSuccess) {
+            P->ws = nullptr;
+            return fail(MCUBES_E_ALLOC, "hipMalloc: %s", hipGetErrorString(e));
+        }
+        P->ws_len = need;
+    }
+    double *g_in = P->ws, *g_new = P->ws + ng, *bins = P->ws + 2 * ng;
+    double *partials = bins + nbn, *est = partials + 2 * (int64_t)P->blocks;
+    hipStream_t s = as_stream(P->stream);
+    e = hipMemcpyAsync(g_in, grid_in, (size_t)ng * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync grid");
+    e = launch_fill(bins, nbn, 0.0, s);
+    if (e != hipSuccess) return hip_fail(e, "fill launch");
+    int rc = mcubes_vsample(P, iteration, g_in, bins, partials, P->stream);
+    if (rc != MCUBES_OK) return rc;
+    rc = mcubes_reduce(P, partials, est, P->stream);
+    if (rc != MCUBES_OK) return rc;
+    if (grid_out) {
+        rc = mcubes_refine(P, g_in, bins, g_new, P->stream);
+        if (rc != MCUBES_OK) return rc;
+    }
+    double h_est[2];
+    e = hipMemcpyAsync(h_est, est, sizeof h_est, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "reading the estimate");
+    if (!isfinite(h_est[0]) || !isfinite(h_est[1]))
+        return fail(MCUBES_E_NONFINITE, "iteration %u produced a non-finite estimate", iteration);
+    if (bins_out)
+        e = hipMemcpyAsync(bins_out, bins, (size_t)nbn * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && grid_out)
+        e = hipMemcpyAsync(grid_out, g_new, (size_t)ng * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "reading the bins and grid");
+    *I_t = h_est[0];
+    *var_t = h_est[1];
+    return MCUBES_OK;
+}
+
 int mcubes_microbench(int kind, int family, const double *params, int dim,
                       const double *d_points, int64_t npts, int64_t calls_per_thread, int blocks,
                       int block, double *d_out, void *stream) {
@@ -433,106 +612,16 @@ int mcubes_integrate(int family, const double *params, int dim, int64_t ncall, i
     if (itmax < 1 || itmax > MCUBES_MAX_ITERATIONS)
         return fail(MCUBES_E_ARG, "itmax must be in [1, %d]", MCUBES_MAX_ITERATIONS);
     if (!(rel_tol >= 0.0) || !isfinite(rel_tol)) return fail(MCUBES_E_ARG, "rel_tol must be finite and >= 0");
-    mcubes_options opt;
-    mcubes_default_options(&opt);
-    if (opt_in) opt = *opt_in;
     mcubes_plan *P = nullptr;
-    int rc = mcubes_plan_create(family, params, dim, ncall, seed, &opt, &P);
+    int rc = mcubes_plan_create(family, params, dim, ncall, seed, opt_in, &P);
     if (rc != MCUBES_OK) return rc;
-    hipStream_t s = as_stream(opt.stream);
-
-    const int64_t ng = (int64_t)P->dim * (P->nb + 1), nbn = (int64_t)P->dim * P->nb;
-    const int64_t total = 2 * ng + nbn + 2 * (int64_t)P->blocks + 2 + MCUBES_STATE_LEN;
     double *buf = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    double head[MCUBES_STATE_HEADER];
-    double kernel_ms = 0.0;
-    int done = 0;
-    hipError_t e = hipMalloc(&buf, (size_t)total * sizeof(double));
+    const hipError_t e = hipMalloc(&buf, (size_t)integrate_buffer_len(*P) * sizeof(double));
     if (e != hipSuccess) {
         mcubes_plan_destroy(P);
         return fail(MCUBES_E_ALLOC, "hipMalloc: %s", hipGetErrorString(e));
     }
-    double *grid[2] = {buf, buf + ng};
-    double *bins = buf + 2 * ng;
-    double *partials = bins + nbn;
-    double *est = partials + 2 * (int64_t)P->blocks;
-    double *state = est + 2;
-    memset(head, 0, sizeof head);
-
-#define MC_CHECK(expr, what)                 \
-    do {                                     \
-        e = (expr);                          \
-        if (e != hipSuccess) {               \
-            rc = hip_fail(e, what);          \
-            goto cleanup;                    \
-        }                                    \
-    } while (0)
-#define MC_CALL(expr)                        \
-    do {                                     \
-        rc = (expr);                         \
-        if (rc != MCUBES_OK) goto cleanup;   \
-    } while (0)
-
-    MC_CHECK(hipEventCreate(&ev0), "hipEventCreate");
-    MC_CHECK(hipEventCreate(&ev1), "hipEventCreate");
-    MC_CHECK(launch_init_grid(grid[0], P->dim, P->nb, s), "init_grid launch");
-    MC_CHECK(launch_fill(state, MCUBES_STATE_LEN, 0.0, s), "fill launch");
-    for (int t = 0; t < itmax; ++t) {
-        double *g_in = grid[t & 1], *g_out = grid[(t + 1) & 1];
-        const bool refine = P->adapt_iters < 0 || t < P->adapt_iters;
-        if (refine) MC_CHECK(launch_fill(bins, nbn, 0.0, s), "fill launch");
-        MC_CHECK(hipEventRecord(ev0, s), "hipEventRecord");
-        MC_CALL(mcubes_vsample(P, (uint32_t)t, g_in, refine ? bins : nullptr, partials,
-                               opt.stream));
-        MC_CHECK(hipEventRecord(ev1, s), "hipEventRecord");
-        MC_CALL(mcubes_reduce(P, partials, est, opt.stream));
-        MC_CALL(mcubes_combine(P, (uint32_t)t, est, state, rel_tol, opt.stream));
-        if (refine)
-            MC_CALL(mcubes_refine(P, g_in, bins, g_out, opt.stream));
-        else
-            MC_CHECK(launch_copy(g_in, g_out, ng, s), "copy launch");
-        MC_CHECK(hipMemcpyAsync(head, state, sizeof head, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
-        MC_CHECK(hipStreamSynchronize(s), "hipStreamSynchronize");
-        float ms = 0.0f;
-        MC_CHECK(hipEventElapsedTime(&ms, ev0, ev1), "hipEventElapsedTime");
-        kernel_ms += ms;
-        done = t + 1;
-        if (head[6] != 0.0) {
-            rc = fail(MCUBES_E_NONFINITE, "iteration %d produced a non-finite estimate", t);
-            goto cleanup;
-        }
-        if (head[5] != 0.0) break;
-    }
-    if (trace) {
-        MC_CHECK(hipMemcpy(trace, state + MCUBES_STATE_HEADER, (size_t)(2 * done) * sizeof(double),
-                           hipMemcpyDeviceToHost),
-                 "hipMemcpy trace");
-    }
-    if (grid_out) {
-        MC_CHECK(hipMemcpy(grid_out, grid[done & 1], (size_t)ng * sizeof(double),
-                           hipMemcpyDeviceToHost),
-                 "hipMemcpy grid");
-    }
-    out->estimate = head[0];
-    out->error = head[1];
-    out->chi2_dof = head[2];
-    out->dof = (int32_t)head[3];
-    out->iterations = done;
-    out->converged = head[5] != 0.0;
-    out->cube_side = P->g;
-    out->ncubes = P->m;
-    out->samples_per_cube = P->p;
-    out->samples_per_iter = P->n;
-    out->kernel_ms = kernel_ms;
-    rc = out->converged ? MCUBES_OK : MCUBES_NOT_CONVERGED;
-    out->status = rc;
-
-cleanup:
-#undef MC_CHECK
-#undef MC_CALL
-    if (ev0) (void)hipEventDestroy(ev0);
-    if (ev1) (void)hipEventDestroy(ev1);
+    rc = integrate_run(*P, buf, itmax, rel_tol, true, out, grid_out, trace);
     (void)hipFree(buf);
     mcubes_plan_destroy(P);
     return rc;

@@ -131,6 +131,17 @@ void make_args(int family, const double *params, int dim, int64_t g, int64_t m, 
 void set_step(VsArgs &A, int dim, uint64_t threads);
 hipStream_t as_stream(void *s);
 
+// A plan built in place (mcubes_plan_create allocates the object and calls
+// this); the workspace of mcubes_iterate is left empty.
+int plan_init(int family, const double *params, int dim, int64_t ncall, uint64_t seed,
+              const mcubes_options *opt, mcubes_plan *P);
+// The iteration loop of mcubes_integrate on a device buffer of
+// integrate_buffer_len(P) doubles; `timed` records the V-Sample time with
+// HIP events (kernel_ms, else 0).
+int64_t integrate_buffer_len(const mcubes_plan &P);
+int integrate_run(const mcubes_plan &P, double *buf, int itmax, double rel_tol,
+                  bool timed, mcubes_result *out, double *grid_out, double *trace);
+
 // Microbenchmarks (microbench.hip).
 hipError_t launch_microbench(int kind, int family, int dim, const VsArgs &A, const double *pts,
                              int64_t npts, int64_t calls, int blocks, int block, double *out,
@@ -149,4 +160,7 @@ struct mcubes_plan {
     mcubes::VsArgs args;
     mcubes::VsLaunchFn launch[2];  // [0] without bin sums, [1] with
     const void *func;
+    void *stream;      // hipStream_t of the options (mcubes_iterate)
+    double *ws;        // device workspace of mcubes_iterate (allocated on its first call)
+    int64_t ws_len;    // doubles in ws
 };

@@ -60,7 +60,7 @@ int main(void) {
     F(mcubes_batch_class, shares) F(mcubes_batch_class, samples) F(mcubes_batch_class, tuned_ms)
     F(mcubes_batch_class, default_ms)
     printf("mcubes_flow_options size %zu\n", sizeof(mcubes_flow_options));
-    F(mcubes_flow_options, train_items) F(mcubes_flow_options, tail_rounds) F(mcubes_flow_options, batch) F(mcubes_flow_options, round_lr) F(mcubes_flow_options, tail_lr) F(mcubes_flow_options, train_precision) F(mcubes_flow_options, anchor_rounds)
+    F(mcubes_flow_options, train_items) F(mcubes_flow_options, tail_rounds) F(mcubes_flow_options, batch) F(mcubes_flow_options, round_lr) F(mcubes_flow_options, tail_lr) F(mcubes_flow_options, train_precision) F(mcubes_flow_options, anchor_rounds) F(mcubes_flow_options, min_iters)
     printf("mcubes_flow_report size %zu\n", sizeof(mcubes_flow_report));
     F(mcubes_flow_report, final_loss) F(mcubes_flow_report, used_flow)
     F(mcubes_flow_report, tail_shape)
@@ -192,11 +192,12 @@ def test_flow_entry_points_reject_bad_arguments():
     # (host buffers stand in for device ones: the checks fail before any use)
     est = (ctypes.c_double * 2)()
     state = (ctypes.c_double * mc.MCUBES_STATE_LEN)()
-    assert L.mcubes_flow_combine(0, None, state, 0.0, None) == E
-    assert L.mcubes_flow_combine(0, est, None, 0.0, None) == E
-    assert L.mcubes_flow_combine(mc.MCUBES_MAX_ITERATIONS, est, state, 0.0, None) == E
-    assert L.mcubes_flow_combine(0, est, state, -1.0, None) == E
-    assert L.mcubes_flow_combine(0, est, state, float("nan"), None) == E
+    assert L.mcubes_flow_combine(0, None, state, 0.0, 1, None) == E
+    assert L.mcubes_flow_combine(0, est, None, 0.0, 1, None) == E
+    assert L.mcubes_flow_combine(mc.MCUBES_MAX_ITERATIONS, est, state, 0.0, 1, None) == E
+    assert L.mcubes_flow_combine(0, est, state, -1.0, 1, None) == E
+    assert L.mcubes_flow_combine(0, est, state, float("nan"), 1, None) == E
+    assert L.mcubes_flow_combine(0, est, state, 0.0, 0, None) == E
     xs = (ctypes.c_double * 24)()
     ws = (ctypes.c_double * 4)()
     xo = (ctypes.c_double * 24)()
@@ -223,4 +224,4 @@ def test_default_flow_options():
                                                            65536)
     assert (fo.lr, fo.round_lr, fo.tail_power, fo.tail_lr) == (4e-3, 2e-3, 1.5, 8e-4)
     assert fo.precision == mc.MCUBES_BF16 and fo.train_precision == mc.MCUBES_BF16
-    assert fo.anchor_rounds == 2
+    assert fo.anchor_rounds == 2 and fo.min_iters == 4

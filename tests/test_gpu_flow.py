@@ -17,7 +17,9 @@ the same way (weights and product inputs rounded to bfloat16, biases FP32):
 a product input within the FP32-versus-FP64 difference of a rounding
 boundary may round the other way on the two sides (one bfloat16 ulp, 2^-8
 relative, moving the spline outputs by ~1e-3), so 99% of the samples must
-agree to |d log q| <= 2e-3, |dx| <= 2e-4 and all of them to ten times that."""
+agree to |d log q| <= 2e-3, |dx| <= 2e-4 and all of them to ten times that.
+The BF16 training gradient is compared component by component with the
+oracle's BF16 gradient (same rounded operands)."""
 import math
 import sys
 
@@ -166,16 +168,24 @@ def test_loss_gradient_and_adam_match_oracle(mc):
 
 
 @pytest.mark.parametrize("n", [4000, 3999])
-def test_bf16_loss_gradient_tracks_the_oracle(mc, n):
-    """The matrix-core form of the training pass (BF16 weights and product
-    inputs, 2^-9 relative rounding each; FP32 accumulation; splines and the
-    weight-gradient sums FP32) against the FP64 oracle at the same
-    parameters: the loss within 2e-3 relative (log q moves by ~1e-3 per
-    spline, its weighted mean less), the gradient's direction within
-    cosine 0.999 and its relative L2 error below 5e-2, and the sign of
-    every large component right.  n = 4000: many waves and a ragged last
-    one, rows read 16 bytes at a time; n = 3999: rows not 16-byte aligned
-    (read element by element) and a ragged last 16-sample step."""
+def test_bf16_loss_gradient_matches_the_bf16_oracle(mc, n):
+    """The matrix-core form of the training pass against the oracle's BF16
+    mode, which rounds the same operands to bfloat16 (weights, the one-blob
+    encoding, h1 and h2, the spline-parameter deltas and the deltas after
+    each ReLU) and sums their products exactly.  What is left between the
+    two is FP32 arithmetic on the GPU (splines, accumulation, the one-blob
+    recurrence; relative ~1e-6 per term) and the rounding flips it causes:
+    a value that lands on the other side of a bfloat16 rounding boundary
+    moves by one bfloat16 ulp (at most 2^-7 relative) with probability
+    ~2^8 times its relative difference, so a component's error is a few
+    1e-6 of the sum of its terms' magnitudes A_i (grad_abs), with rare
+    single flips of up to 2^-7 of one term.  Checked per component
+    against A_i (at most 1e-3 A_i + 1e-6 max|g|, 99% within 1e-4 A_i),
+    per parameter block (relative L2 below 1e-2: a block off by 2x reads
+    1.0), and against the FP64 gradient (the BF16 oracle must be the much
+    closer reference).  n = 4000: many waves and a ragged last one, rows
+    read 16 bytes at a time; n = 3999: rows not 16-byte aligned (read
+    element by element) and a ragged last 16-sample step."""
     import torch
     theta = _f32(workloads.flow_random(4, out_scale=0.4))
     fl = mc.Flow(theta)
@@ -187,17 +197,29 @@ def test_bf16_loss_gradient_tracks_the_oracle(mc, n):
     fl.loss_grad(_dev(xs), _dev(ws), n, d_grad, d_loss, precision=mc.MCUBES_BF16)
     torch.cuda.synchronize()
     g = d_grad.cpu().numpy()
-    loss_ref, g_ref = oracle.flow_loss_grad(theta, xs, ws)
     loss = float(d_loss.cpu()[0])
-    cos = g @ g_ref / (np.linalg.norm(g) * np.linalg.norm(g_ref))
-    rel = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
-    scale = np.abs(g_ref).max()
-    big = np.abs(g_ref) > 1e-1 * scale
-    _say(f"bf16 loss {loss} vs {loss_ref}; gradient cosine {cos:.6f}, rel L2 {rel:.2e}, "
-         f"max err {np.abs(g - g_ref).max() / scale:.2e} of scale")
-    assert loss == pytest.approx(loss_ref, rel=2e-3)
-    assert cos > 0.999 and rel < 5e-2
-    assert np.all(np.sign(g[big]) == np.sign(g_ref[big]))
+    loss16, g16, A = oracle.flow_loss_grad(theta, xs, ws, bf16=True, with_abs=True)
+    loss64, g64 = oracle.flow_loss_grad(theta, xs, ws)
+    err = np.abs(g - g16)
+    gmax = np.abs(g16).max()
+    ratio = err / (A + 1e-300)
+    rel16 = np.linalg.norm(g - g16) / np.linalg.norm(g16)
+    rel64 = np.linalg.norm(g - g64) / np.linalg.norm(g64)
+    _say(f"bf16 loss {loss} vs bf16 oracle {loss16} (fp64 {loss64}); err/A median "
+         f"{np.median(ratio):.2e} p99 {np.percentile(ratio, 99):.2e} max {ratio.max():.2e}; "
+         f"rel L2 vs bf16 oracle {rel16:.2e}, vs fp64 oracle {rel64:.2e}")
+    assert loss == pytest.approx(loss16, rel=1e-5)
+    assert np.all(err <= 1e-3 * A + 1e-6 * gmax), np.argmax(err - 1e-3 * A)
+    assert np.mean(ratio <= 1e-4) >= 0.99
+    lp = oracle.FLOW_LAYER_PARAMS
+    i, h, o = oracle.FLOW_IN, oracle.FLOW_HID, oracle.FLOW_OUT
+    bounds = np.cumsum([0, i * h, h, h * h, h, h * o, o])
+    for l in range(4):
+        for a, b in zip(bounds[:-1], bounds[1:]):
+            blk = slice(l * lp + a, l * lp + b)
+            rel = np.linalg.norm(g[blk] - g16[blk]) / np.linalg.norm(g16[blk])
+            assert rel < 1e-2, (l, a, rel)
+    assert rel16 < 0.1 * rel64
 
 
 def test_flow_iteration_weight_tail(mc):
@@ -377,7 +399,10 @@ def test_flow_combine_matches_oracle(mc):
     """The equal-weight combination of flow-mapped iterations, fed one
     iteration at a time through the C-ABI, against the oracle on every
     prefix: the same FP64 sums in the same order, so 1e-14 relative (one
-    zero-variance iteration, which adds nothing to chi2)."""
+    zero-variance iteration, which adds nothing to chi2).  The error is the
+    larger of the within-iteration and the scatter estimate; the scatter
+    wins on some prefixes and loses on others here.  Converged only from
+    the third iteration on (min_iters = 3)."""
     import torch
     rng = np.random.default_rng(21)
     T = 12
@@ -388,14 +413,14 @@ def test_flow_combine_matches_oracle(mc):
     d_state = torch.zeros(mc.MCUBES_STATE_LEN, dtype=torch.float64, device="cuda")
     for t in range(T):
         d_est.copy_(torch.tensor([I[t], V[t]], dtype=torch.float64))
-        mc.mcubes_flow_combine(t, d_est, d_state, 2e-5)
+        mc.mcubes_flow_combine(t, d_est, d_state, 2e-5, min_iters=3)
         st = d_state.cpu().numpy()
         Ibar, sigma, chi2, dof = oracle.flow_combine(I[:t + 1], V[:t + 1])
         assert st[0] == pytest.approx(Ibar, rel=1e-14)
         assert st[1] == pytest.approx(sigma, rel=1e-14)
         assert st[2] == pytest.approx(chi2, rel=1e-13, abs=1e-300)
         assert (st[3], st[4], st[6]) == (dof, t + 1, 0.0)
-        assert st[5] == (1.0 if sigma <= 2e-5 * abs(Ibar) else 0.0)
+        assert st[5] == (1.0 if t + 1 >= 3 and sigma <= 2e-5 * abs(Ibar) else 0.0)
         assert (st[8 + 2 * t], st[9 + 2 * t]) == (I[t], V[t])
     _say(f"flow combine of {T} iterations: {st[0]!r} +- {st[1]:.3e}, chi2/dof {st[2]:.3f}, "
          f"converged {st[5]}")
@@ -491,20 +516,11 @@ def test_flow_pipeline_beats_plain_mcubes_on_the_mixture(mc):
     """The whole pipeline with its default recipe on the correlated mixture
     (6-D, 2^22 samples per iteration; integral 1 to 1.6e-10).  The separable
     VEGAS map cannot follow the correlated peaks: after the warm-up its
-    estimate is off by several percent.  The flow-mapped iterations, on the
-    BF16 matrix cores and in FP32, land within 1.5e-3 of the integral, with
+    estimate is off by several percent.  Four flow-mapped iterations, on
+    the BF16 matrix cores and in FP32, land at least ten times closer, with
     a per-iteration variance typically ten thousand times below the plain
-    method's, unless they catch one of the rare large weights: then the
-    estimate moves by a few 1e-3 and its error bar grows with it (measured
-    1.0048 +- 4.9e-3 for this seed once).  Over 32 seeds every run was
-    within 1.5e-3 or within 3 of its own error bars (median error 2.2e-4,
-    88% within 1e-3).  Training is not bit-reproducible (the warm-up's
-    histogram atomics), so either case can occur here.  The error bar is
-    otherwise not asserted: where the flow is thinner than f (the outer
-    slopes of the peaks along the diagonal) rare samples carry weights of
-    1e3 to 1e4, so the error estimated from a few million samples is often
-    a few times too small (a known limit of importance sampling with a
-    lighter-tailed proposal)."""
+    method's.  Whether the error bars cover the integral is a statement
+    over seeds (test_flow_pipeline_error_bars_cover_the_integral)."""
     pr = workloads.mixture_6d(ncall=1 << 22)
     for prec in (mc.MCUBES_BF16, mc.MCUBES_FP32):
         fl = mc.Flow(workloads.flow_init(7))
@@ -519,11 +535,41 @@ def test_flow_pipeline_beats_plain_mcubes_on_the_mixture(mc):
         assert rep["used_flow"] == 1 and res["iterations"] == 4
         assert math.isfinite(rep["tail_shape"])
         dev = abs(res["estimate"] - 1.0)
-        assert dev <= 1.5e-3 or dev <= 3 * res["error"]
         assert dev < abs(rep["plain_estimate"] - 1.0) / 10
         # typically 1e4 times lower; one of the rare weights of 1e4 adds
         # (1e4 / 2^22)^2 ~ 6e-6 to a single iteration's variance
         assert rep["first_flow_var"] < rep["last_plain_var"] / 10
+
+
+def test_flow_pipeline_error_bars_cover_the_integral(mc):
+    """Coverage over seeds, the error model of m-Cubes (the error is the
+    standard deviation of the estimate): eight pipelines with the default
+    recipe on the mixture at 2^22 samples per iteration, run to a relative
+    error of 1e-3 (at least four flow iterations).  A correct error bar
+    covers the integral within 2 sigma about 95% of the time and within
+    3 sigma almost always; asked here: at least 7 of 8 within 2 sigma, all
+    8 within 3 sigma, and every estimate within 2e-3.  Runs the pipeline
+    refuses to call converged (heavy weight tail with disagreeing
+    iterations) still count: their error bars must cover too."""
+    pr = workloads.mixture_6d(ncall=1 << 22)
+    pulls, devs = [], []
+    for seed in range(101, 109):
+        fl = mc.Flow(workloads.flow_init(7))
+        res, rep = fl.integrate(pr.family, pr.params, pr.ncall, 50, 1e-3, seed,
+                                mc.mcubes_default_options(nbins=500))
+        dev = res["estimate"] - 1.0
+        pull = dev / res["error"]
+        _say(f"seed {seed}: {res['estimate']:.6f} +- {res['error']:.2e} (pull {pull:+.2f}), "
+             f"{res['iterations']} flow iterations, chi2/dof {res['chi2_dof']:.2f}, "
+             f"tail {rep['tail_shape']:.3f}, converged {res['converged']}, "
+             f"used {rep['used_flow']}")
+        assert rep["used_flow"] == 1 and res["iterations"] >= 4
+        pulls.append(pull)
+        devs.append(abs(dev))
+    pulls = np.abs(np.array(pulls))
+    assert np.sum(pulls <= 2.0) >= 7, pulls
+    assert np.all(pulls <= 3.0), pulls
+    assert max(devs) <= 2e-3, devs
 
 
 def test_pipeline_falls_back_to_plain_when_the_flow_loses(mc):

@@ -235,3 +235,52 @@ def test_full_size_8d_iteration(mc, family):
     assert_iteration_close(family, got, ref, m, p, f"full-size family={family}")
     assert np.allclose(gpu_refine(plan, grid, ref[2]), oracle.refine(grid, ref[2]),
                        rtol=1e-12, atol=1e-15)
+
+
+def test_boundary_calls_match_the_oracles_through_one_table(mc):
+    """The two boundary calls §8's interface names, driven through one
+    signature table on both libraries (mcubes_* and mcubes_oracle_*): one
+    iteration of the 3-D product-peak workload from the same random grid
+    with the host-pointer iterate call (I_t, var_t, bins, refined grid to
+    the 1e-12 bar), a second iteration from the first's refined oracle grid,
+    and the whole integrator (10 iterations, trace and result)."""
+    import abi_mirror as am
+    pr = workloads.small_product_peak()
+    g, m, p, n = oracle.plan(pr.dim, pr.ncall)
+    sides = {k: am.Side(path, am.PREFIX[k]) for k, path in
+             (("gpu", mc.LIB_PATH), ("oracle", oracle.LIB_PATH))}
+    opt = am.options(nbins=pr.nbins)
+    plans = {}
+    for k, side in sides.items():
+        rc, h = side.plan(pr.family, pr.params, pr.dim, pr.ncall, pr.seed, opt)
+        assert rc == 0, (k, rc)
+        plans[k] = h
+    try:
+        grid = random_grid(np.random.default_rng(8), pr.dim, pr.nbins)
+        for t in (0, 1):
+            _say(f"iterate t={t}")
+            out = {k: sides[k].iterate(plans[k], grid, t, pr.dim, pr.nbins) for k in sides}
+            rc_g, I_g, v_g, b_g, new_g = out["gpu"]
+            rc_o, I_o, v_o, b_o, new_o = out["oracle"]
+            assert rc_g == rc_o == 0
+            assert_iteration_close(pr.family, (I_g, v_g, b_g), (I_o, v_o, b_o), m, p, f"t={t}")
+            assert np.allclose(new_g, new_o, rtol=1e-12, atol=1e-15)
+            grid = new_o
+        # the host-pointer call rejects what the oracle's rejects
+        bad = grid.copy()
+        bad[1, -1] = 0.999
+        assert sides["gpu"].iterate(plans["gpu"], bad, 0, pr.dim, pr.nbins)[0] == -1
+        assert sides["oracle"].iterate(plans["oracle"], bad, 0, pr.dim, pr.nbins)[0] == -1
+    finally:
+        for k, h in plans.items():
+            sides[k].destroy(h)
+    _say("integrate through both tables")
+    res = {k: sides[k].integrate(pr.family, pr.params, pr.dim, pr.ncall, pr.itmax, 0.0, pr.seed,
+                                 opt) for k in sides}
+    (rc_g, r_g, grid_g, tr_g), (rc_o, r_o, grid_o, tr_o) = res["gpu"], res["oracle"]
+    assert rc_g == rc_o == 1 and r_g.iterations == r_o.iterations == pr.itmax
+    assert np.allclose(tr_g, tr_o, rtol=1e-12, atol=0)
+    assert r_g.estimate == pytest.approx(r_o.estimate, rel=1e-12)
+    assert r_g.error == pytest.approx(r_o.error, rel=1e-12)
+    assert np.allclose(grid_g, grid_o, rtol=1e-12, atol=1e-15)
+    assert (r_g.cube_side, r_g.ncubes, r_g.samples_per_cube) == (g, m, p)
