@@ -30,7 +30,8 @@
  *     (cube id, stream id, sample * ceil(d/4) + block, iteration), so the
  *     samples, and therefore the results, do not depend on launch geometry.
  *   - Limits: 1 <= dim <= MCUBES_MAX_DIM, 2 <= nbins <= MCUBES_MAX_BINS,
- *     ncall >= 2, number of cubes m < 2^32.
+ *     ncall >= 2, number of cubes m < 2^32, strata per axis g <=
+ *     MCUBES_MAX_SIDE.
  *   - Threading: a plan may be used from one host thread / one stream at a
  *     time.  Calls on different plans are independent.
  */
@@ -45,6 +46,9 @@ extern "C" {
 
 #define MCUBES_MAX_DIM 10
 #define MCUBES_MAX_BINS 500
+/* Largest number of strata per axis, g (so that c_j + u, with c_j < g and u
+ * carrying 32 random bits, is exact in FP64; matters only for dim = 1). */
+#define MCUBES_MAX_SIDE 1048576
 /* The learned proposal: dimension and number of parameters (see below). */
 #define MCUBES_FLOW_DIM 6
 #define MCUBES_FLOW_PARAMS 67212
@@ -126,7 +130,7 @@ typedef struct mcubes_plan mcubes_plan;
 
 typedef struct {
     int32_t family, dim, nbins, block_size, blocks;
-    int32_t lds_bytes;     /* dynamic LDS per V-Sample block */
+    int32_t lds_bytes;     /* LDS per V-Sample block (static) */
     int32_t precision;     /* mcubes_precision */
     int64_t cube_side, ncubes, samples_per_cube, samples_per_iter;
     int64_t grid_len;      /* dim * (nbins + 1) */
@@ -147,8 +151,8 @@ const char *mcubes_last_error(void);
 
 /* Stratification.  Passage: §3.2 (m-Cubes splits the domain into m equal
  * sub-cubes and runs a 2-point Monte Carlo in each, about ncall samples in
- * all).  Reading: g = largest integer with g^dim <= floor(ncall/2),
- * m = g^dim, p = max(2, floor(ncall/m)), N = m p.  out (host, 4 int64,
+ * all).  Reading: g = largest integer with g^dim <= floor(ncall/2), at
+ * most MCUBES_MAX_SIDE, m = g^dim, p = max(2, floor(ncall/m)), N = m p.  out (host, 4 int64,
  * caller-owned) = [g, m, p, N].  Host only.  Errors: MCUBES_E_ARG (out NULL,
  * dim outside [1, MCUBES_MAX_DIM], ncall < 2, m >= 2^32); out untouched. */
 int mcubes_plan_sizes(int dim, int64_t ncall, int64_t out[4]);

@@ -101,6 +101,7 @@ int mco_plan(int dim, int64_t ncall, int64_t out[4])
     if (g < 1) g = 1;
     while (g > 1 && pow_capped(g, dim, half) > half) --g;
     while (pow_capped(g + 1, dim, half) <= half) ++g;
+    if (g > MCO_MAX_SIDE) g = MCO_MAX_SIDE;
     int64_t m = pow_capped(g, dim, half);
     int64_t p = ncall / m;
     if (p < 2) p = 2;

@@ -10,6 +10,9 @@
 
 #define MCO_MAX_DIM 10
 #define MCO_MAX_BINS 500
+/* At most 2^20 strata per axis: then digit + u (u with 32 random bits below
+ * 2^-32 ... 2^-33) is exact in FP64.  Only a 1-D plan reaches it. */
+#define MCO_MAX_SIDE 1048576
 
 enum {
     MCO_OSCILLATORY = 0,

@@ -1,6 +1,7 @@
 // Host runtime of the batched form (declared in include/mcubes.h): work
-// split into per-class tile lists, graph capture and replay, re-splitting as
-// integrands finish, and the autotuner.
+// split into per-class tile lists (batch_plan.h), graph capture and replay
+// with per-integrand device done flags (the plan stays fixed during a call),
+// and the autotuner.
 #include <math.h>
 #include <string.h>
 
@@ -56,7 +57,7 @@ constexpr int64_t kMaxShares = 1 << 20;
 struct mcubes_batch {
     int n = 0, nb = 0, adapt_iters = -1, skip = 0, forced_block = 0;
     double alpha = 1.5;
-    int cus = 0, max_lds = 0;
+    int cus = 0;
     void *user_stream = nullptr;
     std::vector<BatchItem> items;
     std::vector<int> family, dim;
@@ -141,65 +142,21 @@ int device_alloc(mcubes_batch *B, T **ptr, size_t count) {
 // Blocks of `block` threads of the class kernel resident on the whole device.
 int resident_blocks(const mcubes_batch *B, const ClassPlan &c, int block) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, c.func, block, c.lds) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, c.func, block, 0) != hipSuccess)
         return 0;
     return per_cu * B->cus;
 }
 
-// Splits the class's samples into `shares` equal contiguous shares (in item
-// order, a share ending inside an item at a cube boundary) and appends one
-// tile per (share, item) pair with work.  A tile's partial slot is its index
-// in the batch's tile list; the tiles of an item are consecutive.
+// Splits the class's samples into `shares` tiles (split_tiles).
 void split_class(const mcubes_batch *B, const ClassPlan &c, int shares,
                  std::vector<BatchTile> &tiles) {
-    const int k = (int)c.items.size();
-    std::vector<int64_t> off(k + 1, 0);
-    for (int q = 0; q < k; ++q) off[q + 1] = off[q] + B->m[c.items[q]] * B->p[c.items[q]];
-    const int64_t S = off[k];
-    // position of sample offset T: (item slot, first cube starting at or after T)
-    auto position = [&](int64_t T) {
-        int q = (int)(std::upper_bound(off.begin(), off.end(), T) - off.begin()) - 1;
-        if (q >= k) return std::make_pair(k, (int64_t)0);
-        const int i = c.items[q];
-        int64_t w = (T - off[q] + B->p[i] - 1) / B->p[i];
-        if (w >= B->m[i]) return std::make_pair(q + 1, (int64_t)0);
-        return std::make_pair(q, w);
-    };
-    auto lo = position(0);
-    for (int b = 0; b < shares; ++b) {
-        const int64_t Tb = (int64_t)(((unsigned __int128)S * (uint64_t)(b + 1)) / (uint64_t)shares);
-        const auto hi = position(Tb);
-        for (int q = lo.first; q <= hi.first && q < k; ++q) {
-            const int64_t wb = q == lo.first ? lo.second : 0;
-            const int64_t we = q == hi.first ? hi.second : B->m[c.items[q]];
-            if (we > wb) {
-                BatchTile t;
-                t.item = (uint32_t)c.items[q];
-                t.w_begin = (uint32_t)wb;
-                t.w_end = (uint32_t)we;
-                t.partial = (uint32_t)tiles.size();
-                tiles.push_back(t);
-            }
-        }
-        lo = hi;
-    }
+    mcubes::split_tiles(c.items, B->m.data(), B->p.data(), shares, tiles);
 }
 
-// Shares (workgroups before the split at item boundaries) for a class: the
-// configured count, else kSharesPerSlot per workgroup slot of the device but
-// at most one per `block` cubes; never more than the cubes.
+// Shares of a class for workgroups of `block` threads (class_shares).
 int class_shares(const mcubes_batch *B, const ClassPlan &c, int block, int want) {
-    const int R = resident_blocks(B, c, block);
-    if (R < 1) return 0;
-    int64_t shares = want;
-    if (shares <= 0) {
-        shares = (c.cubes + block - 1) / block;
-        if (shares > kSharesPerSlot * R) shares = kSharesPerSlot * R;
-    }
-    if (shares > kMaxShares) shares = kMaxShares;
-    if (shares > c.cubes) shares = c.cubes;
-    if (shares < 1) shares = 1;
-    return (int)shares;
+    return mcubes::class_shares(c.cubes, block, resident_blocks(B, c, block), want,
+                                kSharesPerSlot, kMaxShares);
 }
 
 // Default workgroup size: small for low dimensions, where the LDS tables are
@@ -224,37 +181,26 @@ ClassPlan make_class(const mcubes_batch *B, const ClassKey &key) {
     c.func = K.tiles_func[0][key.p2];
     c.launch[0] = K.tiles_launch[0][key.p2];
     c.launch[1] = K.tiles_launch[1][key.p2];
-    c.lds = (size_t)(3 * key.dim * B->nb) * sizeof(double);
     hipFuncAttributes fa;
-    c.max_block = hipFuncGetAttributes(&fa, c.func) == hipSuccess ? fa.maxThreadsPerBlock : 0;
+    const bool ok = hipFuncGetAttributes(&fa, c.func) == hipSuccess;
+    c.max_block = ok ? fa.maxThreadsPerBlock : 0;
+    c.lds = ok ? fa.sharedSizeBytes : 0;  // static: tables for kMaxBins bins per axis
     return c;
 }
 
-// Spreads the classes over B->streams branches, longest first onto the least
-// loaded branch; the cost of a class is its tuned time, else its samples
-// weighted by dimension.
+// Spreads the classes over B->streams branches (assign_branches); the cost
+// of a class is its tuned time, else its samples weighted by dimension.
 void assign_branches(mcubes_batch *B) {
-    std::vector<std::pair<double, int>> cost;
-    for (int k = 0; k < (int)B->plan.size(); ++k) {
-        const ClassPlan &c = B->plan[k];
+    std::vector<double> cost;
+    for (const ClassPlan &c : B->plan) {
         auto it = B->cfg.find(c.key);
-        const double t = (it != B->cfg.end() && it->second.tuned_ms > 0.0)
-                             ? it->second.tuned_ms
-                             : (double)c.samples * (c.key.dim + 4) * 1e-9;
-        cost.push_back({t, k});
+        cost.push_back((it != B->cfg.end() && it->second.tuned_ms > 0.0)
+                           ? it->second.tuned_ms
+                           : (double)c.samples * (c.key.dim + 4) * 1e-9);
     }
-    std::sort(cost.begin(), cost.end(), [](const std::pair<double, int> &a,
-                                           const std::pair<double, int> &b) {
-        return a.first > b.first || (a.first == b.first && a.second < b.second);
-    });
-    // never more branches than classes: a captured branch without work is not wanted
-    B->branches = std::max(1, std::min(B->streams, (int)B->plan.size()));
-    std::vector<double> load(B->branches, 0.0);
-    for (const auto &ck : cost) {
-        const int br = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        B->plan[ck.second].branch = br;
-        load[br] += ck.first;
-    }
+    std::vector<int> branch;
+    B->branches = mcubes::assign_branches(cost, B->streams, branch);
+    for (size_t k = 0; k < B->plan.size(); ++k) B->plan[k].branch = branch[k];
 }
 
 // (Re)builds the plan over the items not yet done: classes, geometry, tiles,
@@ -298,18 +244,14 @@ int build_plan(mcubes_batch *B, const std::vector<char> &active) {
         plan.push_back(std::move(c));
     }
     // per-item partial ranges (the tiles of an item are consecutive)
-    for (int i = 0; i < B->n; ++i) B->items[i].part_begin = B->items[i].part_end = 0;
-    std::vector<char> seen(B->n, 0);
-    for (size_t t = 0; t < tiles.size(); ++t) {
-        BatchItem &it = B->items[tiles[t].item];
-        if (!seen[tiles[t].item]) {
-            seen[tiles[t].item] = 1;
-            it.part_begin = tiles[t].partial;
-        } else if (it.part_end != tiles[t].partial) {
-            return fail(MCUBES_E_DEVICE, "internal: tiles of item %u are not consecutive",
-                        tiles[t].item);
-        }
-        it.part_end = tiles[t].partial + 1;
+    std::vector<uint32_t> pb(B->n), pe(B->n);
+    const int64_t bad = part_ranges(tiles, B->n, pb.data(), pe.data());
+    if (bad >= 0)
+        return fail(MCUBES_E_DEVICE, "internal: tiles of item %u are not consecutive",
+                    tiles[bad].item);
+    for (int i = 0; i < B->n; ++i) {
+        B->items[i].part_begin = pb[i];
+        B->items[i].part_end = pe[i];
     }
     if (tiles.size() > B->cap_tiles) {
         (void)hipFree(B->d_tiles);
@@ -341,8 +283,7 @@ int build_plan(mcubes_batch *B, const std::vector<char> &active) {
 
 hipError_t launch_class(const mcubes_batch *B, const ClassPlan &c, bool frozen, hipStream_t s) {
     return c.launch[frozen ? 1 : 0](B->d_items, B->d_tiles + c.tile_off, c.ntiles, B->d_grids,
-                                    B->d_bins, B->d_partials, B->d_iter, B->d_done, c.block, c.lds,
-                                    s);
+                                    B->d_bins, B->d_partials, B->d_iter, B->d_done, c.block, s);
 }
 
 // One iteration: [zero bins] -> V-Sample per class -> reduce -> combine ->
@@ -441,8 +382,6 @@ int mcubes_batch_create(const mcubes_batch_item *items, int n, uint64_t seed,
     mcubes_batch *B = new (std::nothrow) mcubes_batch();
     if (!B) return fail(MCUBES_E_ALLOC, "out of host memory");
     e = hipDeviceGetAttribute(&B->cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess)
-        e = hipDeviceGetAttribute(&B->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (e != hipSuccess) {
         release(B);
         return hip_fail(e, "hipDeviceGetAttribute");
@@ -485,27 +424,6 @@ int mcubes_batch_create(const mcubes_batch_item *items, int n, uint64_t seed,
     }
     B->grids_len = goff;
     B->bins_len = boff;
-    // LDS: every class needs 3 dim nb doubles per block
-    for (int i = 0; i < n; ++i) {
-        const size_t lds = (size_t)(3 * B->dim[i] * B->nb) * sizeof(double);
-        if (lds + 2 * (kMaxBlock / 64) * sizeof(double) > (size_t)B->max_lds) {
-            const int d = B->dim[i];
-            release(B);
-            return fail(MCUBES_E_ARG, "item %d: dim %d with %d bins needs %zu bytes of LDS", i, d,
-                        opt.nbins, lds);
-        }
-        if (lds > 65536) {
-            const VsKernel &K = family_table(B->family[i])[B->dim[i]];
-            for (int nob = 0; nob < 2 && e == hipSuccess; ++nob)
-                for (int p2 = 0; p2 < 2 && e == hipSuccess; ++p2)
-                    e = hipFuncSetAttribute(K.tiles_func[nob][p2],
-                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (e != hipSuccess) {
-                release(B);
-                return hip_fail(e, "hipFuncSetAttribute");
-            }
-        }
-    }
     int rc = device_alloc(B, &B->d_items, (size_t)n);
     if (rc == MCUBES_OK) rc = device_alloc(B, &B->d_grids, (size_t)B->grids_len);
     if (rc == MCUBES_OK) rc = device_alloc(B, &B->d_bins, (size_t)B->bins_len);
@@ -698,7 +616,7 @@ int mcubes_batch_autotune(mcubes_batch *B) {
             if (r == 1) x = hipEventRecord(B->ev[0], B->stream);
             if (x == hipSuccess)
                 x = c.launch[0](d_items, d_tiles, nt, B->d_grids, B->d_bins, d_part, B->d_iter,
-                                B->d_done, block, c.lds, B->stream);
+                                B->d_done, block, B->stream);
         }
         if (x == hipSuccess) x = hipEventRecord(B->ev[1], B->stream);
         if (x == hipSuccess) x = hipEventSynchronize(B->ev[1]);

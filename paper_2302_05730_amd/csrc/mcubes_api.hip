@@ -63,6 +63,7 @@ int plan_sizes(int dim, int64_t ncall, int64_t out[4]) {
     if (g < 1) g = 1;
     while (g > 1 && pow_capped(g, dim, half) > half) --g;
     while (pow_capped(g + 1, dim, half) <= half) ++g;
+    if (g > MCUBES_MAX_SIDE) g = MCUBES_MAX_SIDE;  // dim = 1 only: keeps c_j + u exact
     const int64_t m = pow_capped(g, dim, half);
     int64_t p = ncall / m;
     if (p < 2) p = 2;
@@ -206,40 +207,27 @@ int plan_init(int family, const double *params, int dim, int64_t ncall, uint64_t
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    int cus = 0, max_lds = 0;
+    int cus = 0;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute(CUs)");
-    e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute(LDS)");
 
     const int prec = opt.precision == MCUBES_FP32 ? 1 : 0;
     const VsKernel &kern_set = family_table(family)[dim];
     const int variant = (p == 2) ? 1 : 0;
     const void *kfunc = kern_set.func[prec][0][variant];
-    const void *kfunc_nobins = kern_set.func[prec][1][variant];
     const int nb = opt.nbins;
-    // (edge, width) pairs (FP64, or FP32 in the FP32 form) and bin sums of every axis
-    const size_t lds = (size_t)((prec ? 2 : 3) * dim * nb) * sizeof(double);
-    if (lds + 2 * (kMaxBlock / 64) * sizeof(double) > (size_t)max_lds)
-        return fail(MCUBES_E_ARG, "dim %d with %d bins needs %zu bytes of LDS, device has %d", dim,
-                    nb, lds, max_lds);
-    if (lds > 65536) {
-        e = hipFuncSetAttribute(kfunc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute(kfunc_nobins, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)lds);
-        if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
-    }
+    // the kernel's LDS is static: its tables have room for kMaxBins bins per axis
     hipFuncAttributes fattr;
     e = hipFuncGetAttributes(&fattr, kfunc);
     if (e != hipSuccess) return hip_fail(e, "hipFuncGetAttributes");
+    const size_t lds = fattr.sharedSizeBytes;
     const int max_block = fattr.maxThreadsPerBlock;
     if (opt.block_size > max_block)
         return fail(MCUBES_E_ARG, "block_size %d exceeds this kernel's limit %d", opt.block_size,
                     max_block);
     const int block = opt.block_size ? opt.block_size : max_block;
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfunc, block, lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfunc, block, 0);
     if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
     if (per_cu < 1) return fail(MCUBES_E_ARG, "V-Sample does not fit: block %d, LDS %zu", block, lds);
     int64_t blocks = opt.blocks ? opt.blocks : (int64_t)per_cu * cus;
@@ -466,7 +454,7 @@ int mcubes_vsample(const mcubes_plan *P, uint32_t iteration, const double *d_gri
     VsArgs A = P->args;
     A.iteration = iteration;
     const hipError_t e = P->launch[d_bins ? 1 : 0](A, d_grid, d_bins, d_partials, P->blocks,
-                                                   P->block, P->lds, as_stream(stream));
+                                                   P->block, as_stream(stream));
     return e == hipSuccess ? MCUBES_OK : hip_fail(e, "V-Sample launch");
 }
 

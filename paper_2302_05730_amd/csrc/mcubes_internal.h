@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "batch_plan.h"
 #include "mcubes.h"
 
 namespace mcubes {
@@ -41,8 +42,7 @@ struct VsArgs {
 };
 
 typedef hipError_t (*VsLaunchFn)(const VsArgs &args, const double *grid, double *bins,
-                                 double *partials, int blocks, int block, size_t lds,
-                                 hipStream_t stream);
+                                 double *partials, int blocks, int block, hipStream_t stream);
 
 // Batched form: one integrand of a batch (device-resident descriptor) and one
 // tile of work (a range of permuted work items of one integrand).
@@ -56,16 +56,11 @@ struct BatchItem {
     double n_samples, var_denom;         // N = m p and p m^2
 };
 
-// Work items [w_begin, w_end) of integrand `item`; its (sum S_c, sum var_c)
-// go to partials[2 partial], [2 partial + 1].
-struct BatchTile {
-    uint32_t item, w_begin, w_end, partial;
-};
 
 typedef hipError_t (*VsTilesLaunchFn)(const BatchItem *items, const BatchTile *tiles, int ntiles,
                                       const double *grids, double *bins, double *partials,
                                       const uint32_t *iter, const uint32_t *done, int block,
-                                      size_t lds, hipStream_t stream);
+                                      hipStream_t stream);
 
 // Eight variants per (family, dim): [fp32][nobins][p2] with fp32 = 1 for the
 // FP32 map/integrand form, nobins = 1 when the bin sums are not wanted (no
@@ -153,7 +148,7 @@ hipError_t launch_microbench(int kind, int family, int dim, const VsArgs &A, con
 struct mcubes_plan {
     int family, dim, nb, precision;
     int block, blocks;
-    size_t lds;
+    size_t lds;        // static LDS of the V-Sample kernel (bytes per block)
     int adapt_iters, skip;
     double alpha;
     int64_t g, m, p, n;

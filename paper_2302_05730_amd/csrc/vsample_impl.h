@@ -268,9 +268,27 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// One sample k of cube c: Philox words -> bin coordinates -> x through the
-// (edge, width) table -> weight w = f(x) J; bin[j] receives the bin index on
-// axis j.  cb[j] = c_j 2^32 + 1/2 (see below).
+// LDS of one V-Sample block.  Every table holds one row of kMaxBins entries
+// of 8 bytes per axis, so the offset of each row is a constant of the
+// instantiation: one value, the bin index times 8, then addresses the bin in
+// every table of its axis (the row offsets fold into the immediate offsets of
+// the LDS instructions), and the same value is the byte offset of the bin's
+// left edge in the axis's row of the global grid.
+//   FP64 form: bin sums of every axis, and the edges E_i and widths W_i of the
+//   staged axes (the even axes; odd axes read (E_i, E_i+1) from the global
+//   grid through the vector L1 cache; d = 1 stages its one axis).
+//   FP32 form: bin sums, and (E_i, W_i) as a pair of floats for every axis.
+template <int D, bool BINS, bool F32>
+struct VsLds {
+    static constexpr int kRow = kMaxBins * 8;
+    static constexpr int kStaged = F32 ? D : (D >= 2 ? (D + 1) / 2 : 1);
+    static constexpr int kH = 0;                                   // FP64 sums, axis j
+    static constexpr int kE = kH + (BINS ? D : 0) * kRow;         // FP64 E_i, staged axis l
+    static constexpr int kW = kE + (F32 ? 0 : kStaged) * kRow;     // FP64 W_i, staged axis l
+    static constexpr int kEW32 = kW + (F32 ? 0 : kStaged) * kRow;  // FP32 (E_i, W_i), axis j
+    static constexpr int kBytes = kEW32 + (F32 ? D : 0) * kRow;
+};
+
 // Grid-table reads of odd axes go through the vector L1 cache (two adjacent
 // edges of the global grid row, 4 KB per axis at 500 bins), those of even
 // axes through LDS, so that the two memory paths share the random reads and
@@ -280,31 +298,51 @@ constexpr bool table_from_l1(int j) {
     return D >= 2 && (j & 1);
 }
 
-template <int F, int D>
+// Staged-table index of axis j (FP64 form).
+template <int D>
+constexpr int staged_axis(int j) {
+    return D >= 2 ? j / 2 : 0;
+}
+
+// The bin coordinate of axis j: z = (c_j + u) fl(nb/g) with u = (r + 1/2) 2^-32,
+// evaluated as (c_j 2^32 + r + 1/2) (fl(nb/g) 2^-32).  The double whose high
+// word is 0x43300000 + c_j and low word is r equals 2^52 + c_j 2^32 + r
+// (c_j < 2^20); subtracting 2^52 - 1/2 leaves c_j 2^32 + r + 1/2 exactly (below
+// 2^52 with one fractional bit), so the one rounding is that of the product,
+// as in the plain definition.  hb = 0x43300000 + c_j is formed once per cube.
+constexpr uint32_t kStratumHi = 0x43300000u;
+
+__device__ __forceinline__ double bin_coordinate(uint32_t hb, uint32_t r, double zscale) {
+    const double v = __hiloint2double((int)hb, (int)r);
+    return (v - 0x1.fffffffffffffp+51) * zscale;
+}
+
+// One sample k of cube c: Philox words -> bin coordinates -> x through the
+// grid tables -> weight w = f(x) J.  o8[j] receives 8 times the bin index on
+// axis j (the byte offset of the bin in every table of the axis).
+template <int F, int D, bool BINS>
 __device__ __forceinline__ double draw(const VsArgs &A, uint32_t iteration, const double *ca,
-                                       const double *cu, uint32_t c, uint32_t k, const double *cb,
-                                       const double2 *sEW, const double *__restrict__ grid,
-                                       int nb, int *bin) {
+                                       const double *cu, uint32_t c, uint32_t k, const uint32_t *hb,
+                                       const unsigned char *lds, const char *const *row, int nb,
+                                       uint32_t *o8) {
+    using L = VsLds<D, BINS, false>;
     constexpr int NBLK = (D + 3) / 4;  // Philox blocks (4 words each) per sample
     // Axes in groups of four, one Philox block per group: the group's bin
     // indices and in-bin fractions first, then its table reads back to back,
     // then their uses, so that the reads are in flight together instead of
-    // each one stalling the wave for a full LDS round trip.
+    // each one stalling the wave for a full round trip.
     Acc acc = Family<F, D>::begin(A.phase);
     double prod = 1.0;
 #pragma unroll
     for (int b = 0; b < NBLK; ++b) {
         uint32_t r[4];
         philox10(c, A.stream_id, k * NBLK + b, iteration, A.key0, A.key1, r);
-        double phi[4];
-        double2 ew[4];
+        double phi[4], e0[4], e1[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int j = 4 * b + q;
             if (j < D) {
-                // z = (c_j + u_j) * fl(nb/g): c_j 2^32 + r + 1/2 is exact (< 2^53)
-                // and scaling fl(nb/g) by 2^-32 is exact, so this rounds once.
-                const double z = ((double)r[q] + cb[j]) * A.zscale;
+                const double z = bin_coordinate(hb[j], r[q], A.zscale);
                 int i = (int)z;
                 if constexpr (D >= 2) {
                     // g < 2^16 here, so z < nb and the bin clamp never fires:
@@ -314,7 +352,7 @@ __device__ __forceinline__ double draw(const VsArgs &A, uint32_t iteration, cons
                     i = i < nb - 1 ? i : nb - 1;
                     phi[q] = z - (double)i;
                 }
-                bin[j] = i;
+                o8[j] = (uint32_t)i << 3;
             }
         }
 #pragma unroll
@@ -322,10 +360,15 @@ __device__ __forceinline__ double draw(const VsArgs &A, uint32_t iteration, cons
             const int j = 4 * b + q;
             if (j < D) {
                 if (table_from_l1<D>(j)) {
-                    const double *e = grid + j * (nb + 1) + bin[j];
-                    ew[q] = make_double2(e[0], e[1]);
+                    // (E_i, E_i+1) of the global row; the width is formed below
+                    // exactly as the staging loop forms the staged widths
+                    const double2 e = *reinterpret_cast<const double2 *>(row[j] + o8[j]);
+                    e0[q] = e.x;
+                    e1[q] = e.y;
                 } else {
-                    ew[q] = sEW[j * nb + bin[j]];
+                    const int l = staged_axis<D>(j);
+                    e0[q] = *reinterpret_cast<const double *>(lds + L::kE + l * L::kRow + o8[j]);
+                    e1[q] = *reinterpret_cast<const double *>(lds + L::kW + l * L::kRow + o8[j]);
                 }
             }
         }
@@ -333,10 +376,8 @@ __device__ __forceinline__ double draw(const VsArgs &A, uint32_t iteration, cons
         for (int q = 0; q < 4; ++q) {
             const int j = 4 * b + q;
             if (j < D) {
-                // L1 axes carry (E_i, E_{i+1}); the width is formed here exactly as
-                // when the LDS table is staged
-                const double W = table_from_l1<D>(j) ? ew[q].y - ew[q].x : ew[q].y;
-                const double x = __fma_rn(W, phi[q], ew[q].x);
+                const double W = table_from_l1<D>(j) ? e1[q] - e0[q] : e1[q];
+                const double x = __fma_rn(W, phi[q], e0[q]);
                 prod = prod * W;
                 Family<F, D>::axis(acc, ca[j], cu[j], x);
             }
@@ -352,11 +393,12 @@ __device__ __forceinline__ double draw(const VsArgs &A, uint32_t iteration, cons
 // FP32 on an FP32 (edge, width) table.  The Jacobian fl(nb^d) prod W is formed
 // in FP64 from the same FP32 widths the map uses, and the weight is returned
 // in FP64.
-template <int F, int D>
+template <int F, int D, bool BINS>
 __device__ __forceinline__ double draw32(const VsArgs &A, uint32_t iteration, const float *ca,
                                          const float *cu, float phase, uint32_t c, uint32_t k,
-                                         const double *cb,
-                                         const float2 *sEW, int nb, int *bin) {
+                                         const uint32_t *hb, const unsigned char *lds, int nb,
+                                         uint32_t *o8) {
+    using L = VsLds<D, BINS, true>;
     constexpr int NBLK = (D + 3) / 4;
     Acc32 acc = Family32<F, D>::begin(phase);
     double prod = 1.0;
@@ -370,7 +412,7 @@ __device__ __forceinline__ double draw32(const VsArgs &A, uint32_t iteration, co
         for (int q = 0; q < 4; ++q) {
             const int j = 4 * b + q;
             if (j < D) {
-                const double z = ((double)r[q] + cb[j]) * A.zscale;
+                const double z = bin_coordinate(hb[j], r[q], A.zscale);
                 int i = (int)z;
                 double ph;
                 if constexpr (D >= 2) {
@@ -380,12 +422,15 @@ __device__ __forceinline__ double draw32(const VsArgs &A, uint32_t iteration, co
                     ph = z - (double)i;
                 }
                 phi[q] = (float)ph;
-                bin[j] = i;
+                o8[j] = (uint32_t)i << 3;
             }
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (4 * b + q < D) ew[q] = sEW[(4 * b + q) * nb + bin[4 * b + q]];
+        for (int q = 0; q < 4; ++q) {
+            const int j = 4 * b + q;
+            if (j < D)
+                ew[q] = *reinterpret_cast<const float2 *>(lds + L::kEW32 + j * L::kRow + o8[j]);
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int j = 4 * b + q;
@@ -399,14 +444,32 @@ __device__ __forceinline__ double draw32(const VsArgs &A, uint32_t iteration, co
     return (double)Family32<F, D>::end(acc, A) * (A.nbd * prod);
 }
 
+// Adds w^2 to the bin of the sample on every axis (LDS FP64 atomics).
+template <int D, bool F32>
+__device__ __forceinline__ void add_bins(unsigned char *lds, const uint32_t *o8, double w2) {
+    using L = VsLds<D, true, F32>;
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+        atomicAdd(reinterpret_cast<double *>(lds + L::kH + j * L::kRow + o8[j]), w2);
+}
+
 // Largest block of a V-Sample instantiation.  The LDS tables allow one block
-// per CU, so the block size sets the waves per SIMD and the register budget:
-// 1024 threads -> 4 waves, 128 VGPRs; 768 -> 3 waves, 168 VGPRs for the
-// instantiations whose live state does not fit 128 registers.
+// per CU at 8-D, so the block size sets the waves per SIMD and the register
+// budget: 1024 threads -> 4 waves, 128 VGPRs; 768 -> 3 waves, 168 VGPRs for
+// the instantiations whose live state does not fit 128 registers.
 template <int F, int D>
 constexpr int vs_max_block() {
     return (D >= 9 || (F == MCUBES_DISCONTINUOUS && D >= 8)) ? 768 : 1024;
 }
+
+// Shared memory of a V-Sample kernel: the grid tables and bin sums, the
+// per-wave partial sums and the integrand coefficients.
+template <int D, bool BINS, bool F32>
+struct VsShared {
+    alignas(16) unsigned char tables[VsLds<D, BINS, F32>::kBytes];
+    double red[2][kMaxBlock / 64];
+    double coef[2 * kMaxDim];
+};
 
 // The work of one block on a set of work items of one integrand: thread t
 // handles `count` work items w0, w0 + stride, ... (cube (w * mult) mod m each;
@@ -419,30 +482,29 @@ __device__ __forceinline__ void vs_block(const VsArgs &A, const double *__restri
                                          double *__restrict__ bins, double *__restrict__ partial,
                                          uint32_t w0, uint32_t stride, uint32_t count,
                                          uint32_t step, const uint32_t *step_digit,
-                                         uint32_t iteration, double *smem,
-                                         double (*red)[kMaxBlock / 64], double *scoef) {
+                                         uint32_t iteration, VsShared<D, BINS, F32> &sh) {
+    using L = VsLds<D, BINS, F32>;
     __syncthreads();  // a previous call may still read the LDS tables
     const int nb = (int)A.nb;
     const int nh = D * nb;
+    unsigned char *lds = sh.tables;
     if (threadIdx.x < D) {
-        scoef[threadIdx.x] = A.ca[threadIdx.x];
-        scoef[kMaxDim + threadIdx.x] = A.cu[threadIdx.x];
+        sh.coef[threadIdx.x] = A.ca[threadIdx.x];
+        sh.coef[kMaxDim + threadIdx.x] = A.cu[threadIdx.x];
     }
-    // LDS: (edge, width) pairs of every axis (FP64 pairs, 16 bytes, or FP32
-    // pairs, 8 bytes, in the FP32 form), then the FP64 bin sums.
-    double2 *sEW = reinterpret_cast<double2 *>(smem);  // axis j at [j*nb, (j+1)*nb)
-    float2 *sEW32 = reinterpret_cast<float2 *>(smem);  // FP32 form
-    double *sH = smem + (F32 ? nh : 2 * nh);             // axis j at [j*nb, (j+1)*nb)
-
     for (int q = threadIdx.x; q < nh; q += blockDim.x) {
         const int j = q / nb, i = q - j * nb;
         const double e0 = grid[j * (nb + 1) + i];
         const double e1 = grid[j * (nb + 1) + i + 1];
-        if constexpr (F32)
-            sEW32[q] = make_float2((float)e0, (float)(e1 - e0));
-        else
-            sEW[q] = make_double2(e0, e1 - e0);
-        if constexpr (BINS) sH[q] = 0.0;
+        if constexpr (F32) {
+            *reinterpret_cast<float2 *>(lds + L::kEW32 + j * L::kRow + 8 * i) =
+                make_float2((float)e0, (float)(e1 - e0));
+        } else if (!table_from_l1<D>(j)) {
+            const int l = staged_axis<D>(j);
+            *reinterpret_cast<double *>(lds + L::kE + l * L::kRow + 8 * i) = e0;
+            *reinterpret_cast<double *>(lds + L::kW + l * L::kRow + 8 * i) = e1 - e0;
+        }
+        if constexpr (BINS) *reinterpret_cast<double *>(lds + L::kH + j * L::kRow + 8 * i) = 0.0;
     }
     __syncthreads();
 
@@ -451,12 +513,14 @@ __device__ __forceinline__ void vs_block(const VsArgs &A, const double *__restri
     // register file (and spill) at high dimension.
     double ca[D], cu[D];
     float ca32[D], cu32[D];
+    const char *row[D];  // global grid row of every axis (uniform)
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-        ca[j] = scoef[j];
-        cu[j] = scoef[kMaxDim + j];
+        ca[j] = sh.coef[j];
+        cu[j] = sh.coef[kMaxDim + j];
         ca32[j] = (float)ca[j];
         cu32[j] = (float)cu[j];
+        row[j] = reinterpret_cast<const char *>(grid + j * (nb + 1));
     }
     const float phase32 = (float)A.phase;
 
@@ -473,71 +537,67 @@ __device__ __forceinline__ void vs_block(const VsArgs &A, const double *__restri
                 rest = rest / A.g;
             }
         }
+        // add-with-carry constants: 2^32 - g detects a digit's wrap in the
+        // carry of t + (2^32 - g); 2^32 - m does the same for the cube id
+        const uint32_t neg_g = 0u - A.g;
+        const uint32_t step_wrap = step - A.m;
         for (uint32_t n = 0; n < count; ++n) {
-            double cb[D];
+            uint32_t hb[D];
 #pragma unroll
-            for (int j = 0; j < D; ++j) cb[j] = __fma_rn((double)dig[j], 0x1p32, 0.5);
-
+            for (int j = 0; j < D; ++j) hb[j] = kStratumHi + dig[j];
+            uint32_t o8[D];
             if constexpr (P2) {
                 // p = 2: both samples in straight-line code (independent chains
                 // for the scheduler).  With w0 = wa the shifted sums are D1 = dlt,
                 // D2 = dlt^2, and var_c = D2 - D1^2/2 = dlt^2 / 2.
-                int bin[D];
                 const double wa =
-                    F32 ? draw32<F, D>(A, iteration, ca32, cu32, phase32, c, 0, cb, sEW32, nb, bin)
-                        : draw<F, D>(A, iteration, ca, cu, c, 0, cb, sEW, grid, nb, bin);
-                if constexpr (BINS) {
-                    const double w2a = wa * wa;
-#pragma unroll
-                    for (int j = 0; j < D; ++j) atomicAdd(sH + j * nb + bin[j], w2a);
-                }
+                    F32 ? draw32<F, D, BINS>(A, iteration, ca32, cu32, phase32, c, 0, hb, lds, nb, o8)
+                        : draw<F, D, BINS>(A, iteration, ca, cu, c, 0, hb, lds, row, nb, o8);
+                if constexpr (BINS) add_bins<D, F32>(lds, o8, wa * wa);
                 // keep the two samples' register live ranges apart (128 VGPRs at
                 // 1024 threads per block)
                 __builtin_amdgcn_sched_barrier(0);
                 const double wb =
-                    F32 ? draw32<F, D>(A, iteration, ca32, cu32, phase32, c, 1, cb, sEW32, nb, bin)
-                        : draw<F, D>(A, iteration, ca, cu, c, 1, cb, sEW, grid, nb, bin);
-                if constexpr (BINS) {
-                    const double w2b = wb * wb;
-#pragma unroll
-                    for (int j = 0; j < D; ++j) atomicAdd(sH + j * nb + bin[j], w2b);
-                }
+                    F32 ? draw32<F, D, BINS>(A, iteration, ca32, cu32, phase32, c, 1, hb, lds, nb, o8)
+                        : draw<F, D, BINS>(A, iteration, ca, cu, c, 1, hb, lds, row, nb, o8);
+                if constexpr (BINS) add_bins<D, F32>(lds, o8, wb * wb);
                 const double dlt = wb - wa;
                 const double d2 = dlt * dlt;
                 tS += wa + wb;
                 tV += d2 - d2 * 0.5;
             } else {
-                double S = 0.0, D1 = 0.0, D2 = 0.0, w0 = 0.0;
+                double S = 0.0, D1 = 0.0, D2 = 0.0, ws = 0.0;
                 for (uint32_t k = 0; k < A.p; ++k) {
-                    int bin[D];
                     const double w =
-                        F32 ? draw32<F, D>(A, iteration, ca32, cu32, phase32, c, k, cb, sEW32, nb, bin)
-                            : draw<F, D>(A, iteration, ca, cu, c, k, cb, sEW, grid, nb, bin);
+                        F32 ? draw32<F, D, BINS>(A, iteration, ca32, cu32, phase32, c, k, hb, lds, nb, o8)
+                            : draw<F, D, BINS>(A, iteration, ca, cu, c, k, hb, lds, row, nb, o8);
                     S = S + w;
-                    if (k == 0) w0 = w;
-                    const double dlt = w - w0;
+                    if (k == 0) ws = w;
+                    const double dlt = w - ws;
                     D1 = D1 + dlt;
                     D2 = D2 + dlt * dlt;
-                    if constexpr (BINS) {
-                        const double w2 = w * w;
-#pragma unroll
-                        for (int j = 0; j < D; ++j) atomicAdd(sH + j * nb + bin[j], w2);
-                    }
+                    if constexpr (BINS) add_bins<D, F32>(lds, o8, w * w);
                 }
                 tS += S;
                 tV += (D2 - D1 * D1 * A.inv_p) * A.inv_pm1;
             }
 
-            // advance to the next work item: linear id and digits by `step`
-            uint32_t cn = c + step;
-            if (cn < c || cn >= A.m) cn -= A.m;
-            c = cn;
-            uint32_t carry = 0;
+            // advance to the next work item: the cube id by `step` modulo m, and
+            // its digits by the digits of `step` with carries (t = digit +
+            // step digit + carry < 2g; t wraps exactly when t + (2^32 - g)
+            // carries out, and then t - g is the smaller of the two)
+            {
+                uint32_t wrap;
+                const uint32_t cw = __builtin_addc(c, step_wrap, 0u, &wrap);
+                c = wrap ? cw : c + step;
+            }
+            uint32_t carry = 0u;
 #pragma unroll
             for (int j = 0; j < D; ++j) {
-                const uint32_t t = dig[j] + step_digit[j] + carry;
-                carry = t >= A.g ? 1u : 0u;
-                dig[j] = carry ? t - A.g : t;
+                uint32_t ignored;
+                const uint32_t t = __builtin_addc(dig[j], step_digit[j], carry, &ignored);
+                const uint32_t u = __builtin_addc(t, neg_g, 0u, &carry);
+                dig[j] = u < t ? u : t;
             }
         }
     }
@@ -548,25 +608,26 @@ __device__ __forceinline__ void vs_block(const VsArgs &A, const double *__restri
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     if (lane == 0) {
-        red[0][wave] = tS;
-        red[1][wave] = tV;
+        sh.red[0][wave] = tS;
+        sh.red[1][wave] = tV;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         const int nw = (blockDim.x + 63) >> 6;
         double s = 0.0, v = 0.0;
         for (int q = 0; q < nw; ++q) {
-            s += red[0][q];
-            v += red[1][q];
+            s += sh.red[0][q];
+            v += sh.red[1][q];
         }
         partial[0] = s;
         partial[1] = v;
     }
     // flush the block's histogram: one global atomic per non-empty bin
     if constexpr (BINS) {
-        for (int i = threadIdx.x; i < nh; i += blockDim.x) {
-            const double v = sH[i];
-            if (v != 0.0) unsafeAtomicAdd(bins + i, v);
+        for (int q = threadIdx.x; q < nh; q += blockDim.x) {
+            const int j = q / nb, i = q - j * nb;
+            const double v = *reinterpret_cast<const double *>(lds + L::kH + j * L::kRow + 8 * i);
+            if (v != 0.0) unsafeAtomicAdd(bins + q, v);
         }
     }
 }
@@ -576,15 +637,13 @@ __global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_kernel(const V
                                                            const double *__restrict__ grid,
                                                            double *__restrict__ bins,
                                                            double *__restrict__ partials) {
-    extern __shared__ double smem[];
-    __shared__ double red[2][kMaxBlock / 64];
-    __shared__ double scoef[2 * kMaxDim];
+    __shared__ VsShared<D, BINS, F32> sh;
     // persistent grid: thread tid walks work items tid, tid + T, ... < m
     const uint32_t T = gridDim.x * blockDim.x;
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t count = tid < A.m ? (A.m - 1u - tid) / T + 1u : 0u;
     vs_block<F, D, P2, BINS, F32>(A, grid, bins, partials + 2 * blockIdx.x, tid, T, count, A.step,
-                                  A.step_digit, A.iteration, smem, red, scoef);
+                                  A.step_digit, A.iteration, sh);
 }
 
 // Batched form: one launch per (family, dim, p = 2?) class of a batch, one
@@ -598,9 +657,7 @@ __global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_tiles_kernel(
     const BatchItem *__restrict__ items, const BatchTile *__restrict__ tiles,
     const double *__restrict__ grids, double *__restrict__ bins, double *__restrict__ partials,
     const uint32_t *__restrict__ iter, const uint32_t *__restrict__ done) {
-    extern __shared__ double smem[];
-    __shared__ double red[2][kMaxBlock / 64];
-    __shared__ double scoef[2 * kMaxDim];
+    __shared__ VsShared<D, BINS, false> sh;
     const BatchTile tile = tiles[blockIdx.x];
     if (done[tile.item] != 0u) return;
     const BatchItem &B = items[tile.item];
@@ -608,23 +665,23 @@ __global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_tiles_kernel(
     const uint32_t count = w0 < tile.w_end ? (tile.w_end - 1u - w0) / blockDim.x + 1u : 0u;
     vs_block<F, D, P2, BINS, false>(B.args, grids + B.grid_off, bins + B.bins_off,
                                     partials + 2 * (size_t)tile.partial, w0, blockDim.x, count,
-                                    B.step_block, B.step_digit_block, *iter, smem, red, scoef);
+                                    B.step_block, B.step_digit_block, *iter, sh);
 }
 
 template <int F, int D, bool P2, bool BINS>
 hipError_t launch_vsample_tiles(const BatchItem *items, const BatchTile *tiles, int ntiles,
                                 const double *grids, double *bins, double *partials,
-                                const uint32_t *iter, const uint32_t *done, int block, size_t lds,
+                                const uint32_t *iter, const uint32_t *done, int block,
                                 hipStream_t stream) {
-    hipLaunchKernelGGL((vsample_tiles_kernel<F, D, P2, BINS>), dim3(ntiles), dim3(block), lds,
+    hipLaunchKernelGGL((vsample_tiles_kernel<F, D, P2, BINS>), dim3(ntiles), dim3(block), 0,
                        stream, items, tiles, grids, bins, partials, iter, done);
     return hipGetLastError();
 }
 
 template <int F, int D, bool P2, bool BINS, bool F32>
 hipError_t launch_vsample(const VsArgs &args, const double *grid, double *bins, double *partials,
-                          int blocks, int block, size_t lds, hipStream_t stream) {
-    hipLaunchKernelGGL((vsample_kernel<F, D, P2, BINS, F32>), dim3(blocks), dim3(block), lds,
+                          int blocks, int block, hipStream_t stream) {
+    hipLaunchKernelGGL((vsample_kernel<F, D, P2, BINS, F32>), dim3(blocks), dim3(block), 0,
                        stream, args, grid, bins, partials);
     return hipGetLastError();
 }

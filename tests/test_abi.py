@@ -95,6 +95,14 @@ def test_plan_sizes_match_oracle(dim, ncall):
     assert mc.mcubes_plan_sizes(dim, ncall) == oracle.plan(dim, ncall)
 
 
+def test_plan_caps_strata_per_axis():
+    # 1-D plans stop at MCUBES_MAX_SIDE = 2^20 strata (so c + u stays exact in
+    # FP64) and put the rest of the budget into samples per cube
+    assert mc.mcubes_plan_sizes(1, 2**21 + 1) == (2**20, 2**20, 2, 2**21)
+    assert mc.mcubes_plan_sizes(1, 2**22 + 3) == (2**20, 2**20, 4, 2**22)
+    assert mc.mcubes_plan_sizes(1, 2 * 2**32 + 4) == (2**20, 2**20, 8192, 2**33)
+
+
 def _create(family=3, params=None, dim=2, ncall=1000, **opt):
     if params is None:
         params = [1.0] * (2 * dim)
@@ -121,7 +129,7 @@ def _create(family=3, params=None, dim=2, ncall=1000, **opt):
     (dict(block_size=100), mc.MCUBES_E_ARG),
     (dict(block_size=2048), mc.MCUBES_E_ARG),
     (dict(precision=2), mc.MCUBES_E_ARG),
-    (dict(dim=1, ncall=2 * 2**32 + 4), mc.MCUBES_E_ARG),  # m >= 2^32 cubes
+    (dict(dim=2, ncall=2 * 2**32 + 4), mc.MCUBES_E_ARG),  # m = 2^32 cubes
 ])
 def test_plan_create_rejects(kwargs, code):
     with pytest.raises(mc.MCubesError) as ei:
@@ -155,7 +163,7 @@ _GOOD = (3, 2, 1000, [1.0, 1.0, 0.5, 0.5])
     ([(3, 2, 1, [1.0] * 4)], {}, mc.MCUBES_E_ARG),
     ([_GOOD, _GOOD, (1, 2, 1000, [0.0, 1.0, 0.5, 0.5])], {}, mc.MCUBES_E_INTEGRAND),
     ([(0, 2, 1000, [float("nan"), 1.0, 0.5, 0.5])], {}, mc.MCUBES_E_INTEGRAND),
-    ([(3, 1, 2 * 2**32 + 4, [1.0, 0.5])], {}, mc.MCUBES_E_ARG),
+    ([(3, 2, 2 * 2**32 + 4, [1.0, 1.0, 0.5, 0.5])], {}, mc.MCUBES_E_ARG),
     ([_GOOD], dict(precision=mc.MCUBES_FP32), mc.MCUBES_E_ARG),
     ([_GOOD], dict(nbins=501), mc.MCUBES_E_ARG),
     ([_GOOD], dict(block_size=96), mc.MCUBES_E_ARG),
