@@ -28,25 +28,62 @@ import workloads  # noqa: E402
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 
 
-def flops_per_sample(family, d, p):
-    """Algorithmic FP64 operations of one sample as the method defines them
-    (FMA = 2; exp, cos and a division count 1 each).
+def flops_per_sample(family, d, p=2):
+    """Algorithmic FP64 flops of one sample, 9 d + 7 + F_f (FMA = 2; exp, cos
+    and a division count 1 each): per axis the uniform from the random word
+    (fma: 2), the stratified coordinate (add, mul: 2) and the map through the
+    grid (bin fraction, width, fma, Jacobian factor: 5); per sample the
+    Jacobian scale, the weight, the cube statistics and w^2 (7); F_f the
+    integrand:
+      oscillatory 2 d + 2 + cos, product peak 3 d + d divisions, corner peak
+      2 d + 1 + d (power chain) + 1 division, Gaussian 4 d + exp, C0 3 d + exp,
+      discontinuous 2 d + exp, addition d, mixture 8 d + 12 (two quadratic
+      forms, two exp).
+    The count does not depend on p."""
+    f = {0: 2 * d + 3, 1: 4 * d, 2: 3 * d + 2, 3: 4 * d + 1, 4: 3 * d + 1, 5: 2 * d + 1,
+         6: d, 7: 8 * d + 12}[family]
+    return 9 * d + 7 + f
 
-    Per axis: uniform from the random word (fma: 2), stratum offset (add: 1),
-    bin coordinate (mul: 1), in-bin fraction (sub: 1), bin width (sub: 1),
-    mapped point (fma: 2), Jacobian factor (mul: 1), bin update (add: 1)
-    -> 10 d.  Per sample: Jacobian scale, weight, cube sum, shift, two shifted
-    sums (add; mul + add), w^2 -> 8.  Per cube, amortised over p: variance (4)
-    and the two running sums (2) -> 6/p.  Plus the integrand.
-    """
-    f = {0: 2 * d + 1,          # fma per axis, cos
-         1: 4 * d + 1,          # sub, fma, mul per axis, one division
-         2: 3 * d + 1,          # fma per axis, d multiplications of the power, one division
-         3: 4 * d + 2,          # sub, mul, fma per axis, negation, exp
-         4: 3 * d + 2,          # sub, fma per axis (|.| free), negation, exp
-         5: 2 * d + 1,          # fma per axis, exp
-         6: d}[family]
+
+def fp64_ops_per_sample(family, d, p):
+    """Every FP64 operation the kernel issues for one sample, in the same units:
+    per axis the uniform (2), stratum offset (1), bin coordinate (1), in-bin
+    fraction (1), width (1), mapped point (2), Jacobian factor (1) and the
+    bin update (1) -> 10 d; per sample the Jacobian scale, weight, cube sum,
+    shift, the two shifted sums and w^2 -> 8; per cube the variance and two
+    running sums -> 6/p; plus the integrand as evaluated (the product peak's
+    divisions are folded into its coefficients)."""
+    f = {0: 2 * d + 1, 1: 4 * d + 1, 2: 3 * d + 1, 3: 4 * d + 2, 4: 3 * d + 2, 5: 2 * d + 1,
+         6: d, 7: 8 * d + 12}[family]
     return 10 * d + 8 + 6.0 / p + f
+
+
+CLOSED_FORMS = os.path.join(ROOT, "tests", "golden", "bench_closed_forms.json")
+
+
+def closed_forms():
+    """Exact integrals of the benchmark integrands (a stored fixture written from
+    the closed forms; see tests/golden/make_bench_closed_forms.py)."""
+    with open(CLOSED_FORMS) as fh:
+        return json.load(fh)
+
+
+def host_cpu():
+    """Model name of the host CPU and the logical CPUs this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
 
 
 def source_digest():
@@ -105,7 +142,12 @@ def stored_valu_busy():
 
 
 def cpu_baseline(problems, ncall):
-    """The oracle, single-threaded, one iteration of each integrand at `ncall`."""
+    """The oracle, single-threaded, one iteration of each integrand at `ncall`;
+    then the same work split over contiguous cube ranges on every usable host
+    CPU (one thread each; the C oracle runs without the interpreter lock) as a
+    timing-only all-cores figure."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import oracle
     total = 0
     t0 = time.perf_counter()
@@ -114,10 +156,27 @@ def cpu_baseline(problems, ncall):
         oracle.iteration(pr.family, pr.params, pr.dim, pr.nbins, ncall, pr.seed, 0, grid)
         total += oracle.plan(pr.dim, ncall)[3]
     dt = time.perf_counter() - t0
+    cpu = host_cpu()
+    threads = max(1, cpu["usable_cpus"] or 1)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        for pr in problems:
+            grid = oracle.uniform_grid(pr.dim, pr.nbins)
+            g, m, p, _ = oracle.plan(pr.dim, ncall)
+            cut = [m * k // (4 * threads) for k in range(4 * threads + 1)]
+            list(ex.map(lambda ab: oracle.sample_range(pr.family, pr.params, pr.dim, pr.nbins,
+                                                       g, m, p, pr.seed, 0, grid, ab[0], ab[1]),
+                        zip(cut[:-1], cut[1:])))
+    dt_all = time.perf_counter() - t0
     return {"value": total / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
             "sample": (f"one iteration of each of the three 8-D integrands at {ncall} samples "
                        f"requested ({total} evaluated), 500 bins, uniform grid, "
-                       f"{dt:.1f} s single-threaded")}
+                       f"{dt:.1f} s single-threaded"),
+            "cpu_model": cpu["model"], "logical_cpus": cpu["logical_cpus"],
+            "usable_cpus": cpu["usable_cpus"],
+            "all_cores_timing_only": {"value": total / dt_all, "unit": "evals/s",
+                                      "threads": threads, "seconds": round(dt_all, 3),
+                                      "kind": "oracle over cube ranges, one thread per usable CPU"}}
 
 
 def bench_batch(mc, n, iters, full=True):
@@ -131,7 +190,7 @@ def bench_batch(mc, n, iters, full=True):
     b = mc.Batch(items, seed=0)
     t_b = time.perf_counter()
     plans = [mc.mcubes_plan_sizes(p.dim, p.ncall) for p in problems]
-    flops_iter = sum(flops_per_sample(p.family, p.dim, pl[2]) * pl[3]
+    flops_iter = sum(flops_per_sample(p.family, p.dim) * pl[3]
                      for p, pl in zip(problems, plans))
 
     def run(use_graph, itmax=iters, rel_tol=0.0):
@@ -176,6 +235,99 @@ def bench_batch(mc, n, iters, full=True):
                 "tuned_streams": info["streams"], "fixed_iterations_tuned_graph": tuned,
                 "to_1e-3_tuned_graph": to_tol})
     return out
+
+
+def bench_time_to_tol(mc, problems, reps=3, rel_tol=1e-3):
+    """Wall time of mcubes_integrate (plan, iterations, stop test) until the
+    error estimate reaches rel_tol of the estimate, FP64 and FP32 forms of each
+    8-D integrand.  One untimed call per form first (first-call set-up); the
+    forms are interleaved and every entry is the median of `reps` runs (the
+    runs are bit-identical: same samples).  The true error comes from the
+    stored closed forms, read outside the timed region."""
+    cf = closed_forms()
+    forms = (("fp64", mc.MCUBES_FP64), ("fp32", mc.MCUBES_FP32))
+    pr0 = problems[0]
+    for _, prec in forms:
+        mc.mcubes_integrate(pr0.family, pr0.params, pr0.dim, pr0.ncall, 1, rel_tol, pr0.seed,
+                            mc.mcubes_default_options(nbins=500, precision=prec))
+    times, res = {}, {}
+    for _ in range(reps):
+        for pr in problems:
+            for name, prec in forms:
+                key = f"{workloads.FAMILY_NAMES[pr.family]}_{name}"
+                opts = mc.mcubes_default_options(nbins=500, precision=prec)
+                t_a = time.perf_counter()
+                r = mc.mcubes_integrate(pr.family, pr.params, pr.dim, pr.ncall, 50, rel_tol,
+                                        pr.seed, opts)
+                times.setdefault(key, []).append(time.perf_counter() - t_a)
+                res[key] = r
+    out = {}
+    for pr in problems:
+        fam = workloads.FAMILY_NAMES[pr.family]
+        exact = cf[pr.name]["integral"]
+        for name, _ in forms:
+            key = f"{fam}_{name}"
+            r = res[key]
+            t = sorted(times[key])
+            dev = abs(r["estimate"] - exact)
+            out[key] = {"seconds": round(t[len(t) // 2], 4), "runs": [round(v, 4) for v in t],
+                        "iterations": r["iterations"], "converged": r["converged"],
+                        "estimate": r["estimate"], "error": r["error"],
+                        "rel_error": (r["error"] / abs(r["estimate"]) if r["estimate"] else None),
+                        "closed_form": exact, "true_rel_error": dev / abs(exact),
+                        "error_in_sigma": dev / r["error"] if r["error"] else None,
+                        "within_3_sigma": bool(dev <= 3 * r["error"])}
+        a, b = out[f"{fam}_fp32"], out[f"{fam}_fp64"]
+        # same samples in both forms: the difference is the FP32 rounding of the
+        # map and the integrand, stated relative to the FP64 estimate and its error
+        a["diff_vs_fp64"] = a["estimate"] - b["estimate"]
+        a["diff_vs_fp64_in_sigma"] = (abs(a["diff_vs_fp64"]) / b["error"] if b["error"] else None)
+    return out
+
+
+# The paper's mean V100 CUDA times of the m-Cubes kernel (ms): Table 2 (§5.2),
+# f1-f6 at 8-D, and Table 4 (§5.3), the addition integrand at 5-8-D.  The
+# paper does not say which of its launch sizes (1e8 to 3e9 samples) a mean
+# belongs to: context only.
+PAPER_V100_CUDA_MS = {1: 286.7, 2: 402.1, 3: 284.5, 4: 385.7, 5: 284.3, 6: 283.8}
+PAPER_V100_CUDA_SUM_MS = {5: 206.1, 6: 214.1, 7: 234.1, 8: 284.7}
+
+
+def bench_paper_standin(mc, reps=3, sizes=(10**8, 3 * 10**9)):
+    """V-Sample (with bin sums, uniform grid, 500 bins) on the paper's own
+    integrands with its printed constants, at the smallest and largest
+    samples per iteration of its kernel timings: mean launch time (HIP events
+    on the launch stream) over `reps` launches after one untimed launch."""
+    import torch
+    stream = torch.cuda.current_stream()
+    out = {}
+    cases = [(f"f{k}_8d", k, 8) for k in range(1, 7)] + [(f"sum_{d}d", 7, d) for d in range(5, 9)]
+    for ncall in sizes:
+        for name, k, d in cases:
+            fam, params = workloads.paper_integrand(k, d)
+            pl = mc.mcubes_plan_create(fam, params, d, ncall, 0,
+                                       mc.mcubes_default_options(nbins=500))
+            b = mc.Buffers(pl)
+            mc.mcubes_init_grid(pl, b.grid[0])
+            mc.mcubes_vsample(pl, 0, b.grid[0], b.bins, b.partials)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for t in range(reps):
+                mc.mcubes_vsample(pl, t, b.grid[0], b.bins, b.partials)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            n = pl.info["samples_per_iter"]
+            entry = {"samples_per_iter": n, "vsample_ms": round(ms, 4),
+                     "evals_per_s": n / (ms * 1e-3),
+                     "fp64_tflops": flops_per_sample(fam, d) * n / (ms * 1e-3) / 1e12}
+            entry["v100_cuda_ms"] = (PAPER_V100_CUDA_MS[k] if k <= 6
+                                     else PAPER_V100_CUDA_SUM_MS[d])
+            out[f"{name}_{ncall:.0e}".replace("+", "")] = entry
+    return {"workload": ("the paper's f1-f6 (eqs. 1-6, printed constants) at 8-D and sum x_i "
+                         "at 5-8-D, uniform grid, 500 bins, one V-Sample launch with bin sums"),
+            "note": ("V100 means from Tables 2 and 4 are context: the paper does not say "
+                     "which launch size each belongs to"), "cases": out}
 
 
 # network multiply-adds per flow sample: 4 coupling layers, each 96x64 + 64x64 + 64x99
@@ -263,6 +415,8 @@ def main():
     ap.add_argument("--cpu-ncall", type=int, default=1 << 25)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ttt", action="store_true")
+    ap.add_argument("--no-standin", action="store_true",
+                    help="skip the V-Sample timings on the paper's own integrands")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--blocks", type=int, default=0)
     ap.add_argument("--batch-n", type=int, default=512,
@@ -352,7 +506,7 @@ def main():
 
     # dominant kernel: V-Sample; algorithmic FP64 flops per launch / mean launch time
     per_family = {}
-    tot_flops, tot_ms = 0.0, 0.0
+    tot_flops, tot_ops, tot_ms = 0.0, 0.0, 0.0
     for pr, ms in zip(problems, vs_ms):
         mean_ms = sum(ms) / len(ms)
         fl = flops_per_sample(pr.family, pr.dim, p) * n_eval
@@ -360,11 +514,15 @@ def main():
             "vsample_ms": round(mean_ms, 4), "evals_per_s": n_eval / (mean_ms * 1e-3),
             "tflops": fl / (mean_ms * 1e-3) / 1e12}
         tot_flops += fl
+        tot_ops += fp64_ops_per_sample(pr.family, pr.dim, p) * n_eval
         tot_ms += mean_ms
     achieved = tot_flops / (tot_ms * 1e-3) / 1e12
+    achieved_ops = tot_ops / (tot_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
                 "traffic": stored_traffic(), "kernel": "vsample_kernel<family, 8, p=2>",
+                "work_model": "9d + 7 + F_f algorithmic FP64 flops per sample",
+                "frac_counting_every_fp64_op": round(achieved_ops / FP64_VECTOR_PEAK_TFLOPS, 4),
                 "valu_busy_profiled": stored_valu_busy(), "per_family": per_family}
 
     # iterations after the grid has stopped adapting need no bin sums
@@ -400,28 +558,8 @@ def main():
         fp32[workloads.FAMILY_NAMES[pr.family]] = {"vsample_ms": round(ms, 4),
                                                    "evals_per_s": n_eval / (ms * 1e-3)}
 
-    ttt = None
-    if not args.no_ttt:
-        ttt = {}
-        for prec_name, prec in (("fp64", mc.MCUBES_FP64), ("fp32", mc.MCUBES_FP32)):
-            for pr in problems:
-                t_a = time.perf_counter()
-                r = mc.mcubes_integrate(pr.family, pr.params, pr.dim, pr.ncall, 50, 1e-3, pr.seed,
-                                        mc.mcubes_default_options(nbins=500, precision=prec))
-                t_b = time.perf_counter()
-                ttt[f"{workloads.FAMILY_NAMES[pr.family]}_{prec_name}"] = {
-                    "seconds": round(t_b - t_a, 4), "iterations": r["iterations"],
-                    "converged": r["converged"], "estimate": r["estimate"], "error": r["error"],
-                    "rel_error": (r["error"] / abs(r["estimate"]) if r["estimate"] else None)}
-        for pr in problems:
-            name = workloads.FAMILY_NAMES[pr.family]
-            a, b = ttt[f"{name}_fp32"], ttt[f"{name}_fp64"]
-            # same samples in both forms: the difference is the FP32 rounding of the
-            # map and the integrand, stated relative to the FP64 estimate and its error
-            a["diff_vs_fp64"] = a["estimate"] - b["estimate"]
-            a["diff_vs_fp64_in_sigma"] = (abs(a["estimate"] - b["estimate"]) / b["error"]
-                                          if b["error"] else None)
-
+    ttt = None if args.no_ttt else bench_time_to_tol(mc, problems)
+    standin = None if args.no_standin else bench_paper_standin(mc)
     batched = bench_batch(mc, args.batch_n, args.batch_iters) if args.batch_n > 0 else None
     flow = bench_flow(mc, args.flow_ncall) if args.flow_ncall > 0 else None
     cpu = None if args.no_cpu else cpu_baseline(problems, args.cpu_ncall)
@@ -438,6 +576,7 @@ def main():
                    "samples_per_cube": p, "block": plans[0].info["block_size"],
                    "blocks": plans[0].info["blocks"], "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "time_to_1e-3": ttt,
+        "paper_standin": standin,
         "frozen_grid_vsample": frozen, "fp32_vsample": fp32, "batched": batched,
         "learned_proposal": flow,
     }

@@ -33,13 +33,38 @@ def test_stored_profiles_follow_the_kernel_sources(monkeypatch):
 
 
 def test_fp64_work_per_sample():
-    # 8-D Gaussian, p = 2: 10 per axis (80), 8 per sample, 6/p per cube (3),
-    # integrand 4 per axis + negation + exp (34)
-    assert bench.flops_per_sample(3, 8, 2) == 80 + 8 + 3 + 34
-    # addition integrand in 1-D with p = 6: 10 + 8 + 1 + 1
-    assert bench.flops_per_sample(6, 1, 6) == 20
-    for fam in range(7):
-        assert bench.flops_per_sample(fam, 9, 2) > bench.flops_per_sample(fam, 8, 2)
+    # 9 d + 7 + F_f: 8-D Gaussian 72 + 7 + (32 + exp) = 112, oscillatory
+    # 72 + 7 + (16 + 2 + cos) = 98, corner peak 72 + 7 + (16 + 1 + 8 + 1) = 105
+    assert bench.flops_per_sample(3, 8) == 112
+    assert bench.flops_per_sample(0, 8) == 98
+    assert bench.flops_per_sample(2, 8) == 105
+    # addition integrand in 1-D: 9 + 7 + 1
+    assert bench.flops_per_sample(6, 1) == 17
+    for fam in range(8):
+        assert bench.flops_per_sample(fam, 9) > bench.flops_per_sample(fam, 8)
+        assert bench.flops_per_sample(fam, 8, 2) == bench.flops_per_sample(fam, 8, 7)
+    # every FP64 operation the kernel issues: 10 per axis, 8 per sample, 6/p per
+    # cube, and the integrand as evaluated (8-D Gaussian, p = 2: 80 + 8 + 3 + 34)
+    assert bench.fp64_ops_per_sample(3, 8, 2) == 80 + 8 + 3 + 34
+    assert bench.fp64_ops_per_sample(6, 1, 6) == 20
+
+
+def test_closed_form_fixture_matches_the_workloads():
+    # the stored exact integrals belong to the benchmark's parameters
+    import workloads
+    cf = bench.closed_forms()
+    for pr in workloads.large_8d_set():
+        assert cf[pr.name]["params"] == pr.params and cf[pr.name]["family"] == pr.family
+    for k in range(1, 7):
+        fam, params = workloads.paper_integrand(k, 8)
+        assert cf[f"paper_f{k}_8d"]["params"] == params
+    assert abs(cf["mixture_6d"]["integral"] - 1.0) < 1e-9
+    assert cf["paper_sum_8d"]["integral"] == 4.0
+
+
+def test_host_cpu_description():
+    c = bench.host_cpu()
+    assert c["logical_cpus"] >= 1 and 1 <= c["usable_cpus"] <= c["logical_cpus"]
 
 
 def test_flow_work_models():
