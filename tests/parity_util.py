@@ -36,16 +36,18 @@ def host_threads():
     return max(1, min(16, n))
 
 
-def oracle_iteration_parallel(family, params, dim, nb, ncall, seed, it, grid, threads=None):
+def oracle_iteration_parallel(family, params, dim, nb, ncall, seed, it, grid, threads=None,
+                              stream=0):
     """The oracle's iteration, split over contiguous cube ranges run in threads
-    (the C oracle releases the GIL); partial sums are combined with fsum."""
+    (the C oracle releases the GIL); partial sums are combined with fsum.
+    `stream` is the Philox stream word (the integrand's index in a batch)."""
     g, m, p, n = oracle.plan(dim, ncall)
     threads = threads or host_threads()
     chunks = min(threads * 4, max(1, m))
     cut = [m * k // chunks for k in range(chunks + 1)]
     with ThreadPoolExecutor(max_workers=threads) as ex:
         parts = list(ex.map(lambda ab: oracle.sample_range(family, params, dim, nb, g, m, p, seed,
-                                                           it, grid, ab[0], ab[1]),
+                                                           it, grid, ab[0], ab[1], stream),
                             zip(cut[:-1], cut[1:])))
     s = math.fsum(x[0] for x in parts)
     v = math.fsum(x[1] for x in parts)

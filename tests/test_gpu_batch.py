@@ -342,21 +342,25 @@ def test_autotune_and_geometry_are_result_neutral(mc):
     _compare_runs(probs, [tuned, odd], base, ref, "geometry")
 
 
-def test_full_size_batch_against_single_integrand_path(mc):
+def test_full_size_batch_against_oracle(mc):
     """The 512-integrand workload (budgets 1e6-1e8, 9.4e9 samples/iteration).
-    Lock-step: one iteration of the whole batch from fixed random grids
-    against sampled integrands (the largest, a 10-D one, a p > 2 one and a few
-    more) run alone through a plan with the same Philox stream and grid, to
-    1e-12.  Free-running: three iterations of the whole batch against the same
-    integrands run alone through mcubes_integrate."""
-    import torch  # noqa: F401  (device memory of the single-integrand path)
-    from parity_util import gpu_iteration, gpu_refine
+    Lock-step: one iteration of the whole batch from fixed random grids; for
+    sampled integrands (the largest, the largest with p = 2, a 10-D one, a
+    p > 2 one, a 2-D one and four more) I_t, var_t and the refined grid against the oracle run on the
+    same grid with the integrand's Philox stream, over cube ranges on the host
+    threads, to the 1e-12 tolerances.  Free-running: three iterations of the
+    whole batch against the same integrands run alone through
+    mcubes_integrate."""
+    from parity_util import oracle_iteration_parallel
     probs = workloads.batch_problems()
     plans = [oracle.plan(p.dim, p.ncall) for p in probs]
-    pick = {int(np.argmax([pl[3] for pl in plans])),
+    by_size = np.argsort([-pl[3] for pl in plans])
+    pick = {int(by_size[0]),                                   # the largest (10-D, p = 10)
+            next(int(i) for i in by_size if plans[i][2] == 2),  # the largest with p = 2
             next(i for i, p in enumerate(probs) if p.dim == 10),
-            next(i for i, pl in enumerate(plans) if pl[2] > 2)}
-    pick |= {0, 101, 257, 511}
+            next(i for i, pl in enumerate(plans) if pl[2] > 2),
+            next(i for i, p in enumerate(probs) if p.dim == 2),
+            0, 101, 257, len(probs) - 1}
     _say("full batch: create, 512 integrands")
     b = mc.Batch(_items(probs), seed=0)
     rng = np.random.default_rng(2024)
@@ -364,15 +368,15 @@ def test_full_size_batch_against_single_integrand_path(mc):
     est, new = b.step(2, grids)
     for i in sorted(pick):
         pr = probs[i]
-        _say(f"full batch lock-step: item {i} {pr.name} ncall {pr.ncall}")
-        plan = mc.mcubes_plan_create(pr.family, pr.params, pr.dim, pr.ncall, 0,
-                                     mc.mcubes_default_options(stream_id=i))
-        sI, sV, sB = gpu_iteration(plan, 2, grids[i])
         g, m, p, n = plans[i]
-        scale = max(abs(sI), math.sqrt(float(sB[0].sum()) / n)) if pr.family == 0 else abs(sI)
-        assert abs(est[i][0] - sI) <= 1e-12 * scale + 1e-300, (i, est[i][0], sI)
-        assert abs(est[i][1] - sV) <= 1e-12 * abs(sV) + 1e-300, (i, est[i][1], sV)
-        assert np.allclose(np.array(new[i]), gpu_refine(plan, grids[i], sB), rtol=1e-12,
+        _say(f"full batch lock-step: item {i} {pr.name} dim {pr.dim} ncall {pr.ncall} p {p}")
+        rI, rV, rB = oracle_iteration_parallel(pr.family, pr.params, pr.dim, 500, pr.ncall, 0, 2,
+                                               grids[i], stream=i)
+        scale = max(abs(rI), math.sqrt(float(rB[0].sum()) / n)) if pr.family == 0 else abs(rI)
+        assert abs(est[i][0] - rI) <= 1e-12 * scale + 1e-300, (i, est[i][0], rI)
+        tol = var_tolerance(pr.family, rV, rB, m, p)
+        assert abs(est[i][1] - rV) <= tol * abs(rV) + 1e-300, (i, est[i][1], rV, tol)
+        assert np.allclose(np.array(new[i]), oracle.refine(grids[i], rB), rtol=1e-12,
                            atol=1e-15), i
     _say("full batch: integrate, 3 iterations")
     rc, got = b.integrate(3, 0.0, grids=True, traces=True)
