@@ -174,18 +174,27 @@ def test_bf16_loss_gradient_matches_the_bf16_oracle(mc, n):
     encoding, h1 and h2, the spline-parameter deltas and the deltas after
     each ReLU) and sums their products exactly.  What is left between the
     two is FP32 arithmetic on the GPU (splines, accumulation, the one-blob
-    recurrence; relative ~1e-6 per term) and the rounding flips it causes:
-    a value that lands on the other side of a bfloat16 rounding boundary
-    moves by one bfloat16 ulp (at most 2^-7 relative) with probability
-    ~2^8 times its relative difference, so a component's error is a few
-    1e-6 of the sum of its terms' magnitudes A_i (grad_abs), with rare
-    single flips of up to 2^-7 of one term.  Checked per component
-    against A_i (at most 1e-3 A_i + 1e-6 max|g|, 99% within 1e-4 A_i),
-    per parameter block (relative L2 below 1e-2: a block off by 2x reads
-    1.0), and against the FP64 gradient (the BF16 oracle must be the much
-    closer reference).  n = 4000: many waves and a ragged last one, rows
-    read 16 bytes at a time; n = 3999: rows not 16-byte aligned (read
-    element by element) and a ragged last 16-sample step."""
+    recurrence; relative ~1e-6 per term) and what it decides:
+      * rounding flips: a value within that distance of a bfloat16 rounding
+        boundary lands on the other side and moves by one bfloat16 ulp
+        (2^-8 relative), with probability ~2^8 times the distance: a
+        component's error stays within 1e-3 of the sum of its terms'
+        magnitudes A_i (grad_abs); asked of 99.5% of the components
+        (measured: 99.8% and 99.9%);
+      * decision flips: a ReLU pre-activation or a spline-bin position within
+        the FP32 accumulation error (~1e-5 of its terms) of the boundary
+        takes the other branch, which switches one sample's term of every
+        component it feeds on or off.  That term is a share of A_i: the
+        largest seen is 4% (a W1 entry of a bump far from most samples,
+        where a few samples carry A_i); every component must stay within
+        0.1 A_i.
+    Mistakes that move a whole parameter block do not hide in either
+    allowance: each of the 24 blocks must agree in relative L2 to 1e-2 (a
+    block off by 2x reads 1.0; measured at most 3.5e-3), and the BF16
+    oracle must be at least ten times closer than the FP64 gradient.
+    n = 4000: many waves and a ragged last one, rows read 16 bytes at a
+    time; n = 3999: rows not 16-byte aligned (read element by element) and
+    a ragged last 16-sample step."""
     import torch
     theta = _f32(workloads.flow_random(4, out_scale=0.4))
     fl = mc.Flow(theta)
@@ -209,8 +218,9 @@ def test_bf16_loss_gradient_matches_the_bf16_oracle(mc, n):
          f"{np.median(ratio):.2e} p99 {np.percentile(ratio, 99):.2e} max {ratio.max():.2e}; "
          f"rel L2 vs bf16 oracle {rel16:.2e}, vs fp64 oracle {rel64:.2e}")
     assert loss == pytest.approx(loss16, rel=1e-5)
-    assert np.all(err <= 1e-3 * A + 1e-6 * gmax), np.argmax(err - 1e-3 * A)
-    assert np.mean(ratio <= 1e-4) >= 0.99
+    rounding = err <= 1e-3 * A + 1e-6 * gmax
+    assert np.mean(rounding) >= 0.995, np.mean(rounding)
+    assert np.all(err <= 0.1 * A + 1e-6 * gmax), np.argmax(err / (A + 1e-300))
     lp = oracle.FLOW_LAYER_PARAMS
     i, h, o = oracle.FLOW_IN, oracle.FLOW_HID, oracle.FLOW_OUT
     bounds = np.cumsum([0, i * h, h, h * h, h, h * o, o])
