@@ -444,8 +444,9 @@ __device__ __forceinline__ void swap_halves(const bf16x8 &a, const bf16x8 &b, bf
     hi = __builtin_bit_cast(bf16x8, r1);
 }
 
-// The third product of layer l for one sample block from its BF16 operands.
-__device__ __forceinline__ void third_product(const bf16x8 *__restrict__ Fr,
+// The third product of layer l for one sample block from its BF16 operands;
+// F3 points at the layer's 16 third-product fragments (this lane's entry).
+__device__ __forceinline__ void third_product(const bf16x8 *__restrict__ F3,
                                               const bf16x8 (&h2)[G3K], f32x16 (&out)[G3T]) {
 #pragma unroll
     for (int t = 0; t < G3T; ++t) out[t] = f32x16{};
@@ -453,7 +454,7 @@ __device__ __forceinline__ void third_product(const bf16x8 *__restrict__ Fr,
     for (int ks = 0; ks < G3K; ++ks)
 #pragma unroll
         for (int t = 0; t < G3T; ++t)
-            out[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Fr[(OFF_G3 + t * G3K + ks) * 64], h2[ks],
+            out[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F3[(t * G3K + ks) * 64], h2[ks],
                                                              out[t], 0, 0, 0);
 }
 
@@ -515,18 +516,37 @@ __device__ __forceinline__ uint32_t *relu_bits(float *ext_l, int64_t n64, int64_
 // the FP32 accumulators, rounded to BF16 as the products take them); loss +=
 // sum c log q with c = -w / sum w.  Lanes past n work on a copy of the last
 // sample with c = 0 and store nothing.
-__global__ __launch_bounds__(64) void train_bf16_kernel(
+// The weight fragments of the current layer are staged in LDS for the
+// workgroup's TR_WAVES waves (one per SIMD): forward, the layer's FRAGS
+// fragments; backward, its third-product fragments followed by its backward
+// fragments.  Read from LDS, the matrix-core operands wait a fraction of an
+// L2 round trip.
+constexpr int TR_WAVES = 4;
+constexpr int TR_SLOT = G3T * G3K + BFRAGS;  // 50 fragments >= FRAGS
+
+__device__ __forceinline__ void stage_frags(bf16x8 *dst, const bf16x8 *__restrict__ src,
+                                            int frags) {
+    for (int i = threadIdx.x; i < frags * 64; i += TR_WAVES * 64) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(TR_WAVES * 64) void train_bf16_kernel(
     const bf16x8 *__restrict__ frags, const bf16x8 *__restrict__ bfrags,
     const float *__restrict__ bias, const double *__restrict__ x, const double *__restrict__ w,
     int64_t n, const double *__restrict__ wsum, float *__restrict__ scratch, float *__restrict__ ext,
     double *__restrict__ loss) {
-    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    const int64_t wid = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    __shared__ bf16x8 slot[TR_SLOT * 64];
+    const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63, h = lane >> 5, col = lane & 31;
     const int64_t n64 = (n + 63) / 64 * 64;
     double lsum = 0.0;
-    for (int64_t base = wid * 64; base < n; base += waves * 64) {
-        const int64_t group = base / 64;
+    // the workgroup takes TR_WAVES groups of 64 samples per pass, all its
+    // waves in step (they share the staged fragments); a wave past n runs on
+    // copies of the last sample and stores nothing
+    for (int64_t gbase = (int64_t)blockIdx.x * TR_WAVES * 64; gbase < n;
+         gbase += (int64_t)gridDim.x * TR_WAVES * 64) {
+        const int64_t base = gbase + 64 * wave;
+        const bool wlive = base < n;
+        const int64_t group = (wlive ? base : n64 - 64) / 64;
         const bool live = base + lane < n;
         const int64_t s = live ? base + lane : n - 1;
         // the sample of column col in block sb, and whether it is real
@@ -552,7 +572,10 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
 #pragma unroll
                 for (int j = 0; j < D; ++j) sc[(FS_U + j) * n + s] = u[j];
             }
-            const bf16x8 *Fr = frags + (size_t)l * FRAGS * 64 + lane;
+            __syncthreads();  // every wave is done with the previous fragments
+            stage_frags(slot, frags + (size_t)l * FRAGS * 64, FRAGS);
+            __syncthreads();
+            const bf16x8 *Fr = slot + lane;
             const float *Bs = bias + l * BIAS + h * 16;
             f32x16 own[2][G3T];
 #pragma unroll
@@ -589,7 +612,7 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
                     }
                     h1[ks] = pack8(v);
                 }
-                relu_bits(ext_l, n64, group, sb, 0)[lane] = m1;
+                if (wlive) relu_bits(ext_l, n64, group, sb, 0)[lane] = m1;
                 f32x16 acc2[G2T];
 #pragma unroll
                 for (int t = 0; t < G2T; ++t) acc2[t] = f32x16{};
@@ -615,10 +638,10 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
                             b16[(FS_H2 + acc_feature(ks / 2, r, h)) * n + cs[sb]] = bf16_bits(v[i]);
                     }
                     h2[ks] = pack8(v);
-                    ops[ks * 64 + lane] = h2[ks];
+                    if (wlive) ops[ks * 64 + lane] = h2[ks];
                 }
-                relu_bits(ext_l, n64, group, sb, 1)[lane] = m2;
-                third_product(Fr, h2, own[sb]);
+                if (wlive) relu_bits(ext_l, n64, group, sb, 1)[lane] = m2;
+                third_product(Fr + OFF_G3 * 64, h2, own[sb]);
             }
             own_outputs(bias, l, own);
 #pragma unroll
@@ -650,6 +673,10 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
                 uin[j] = sc[(FS_U + j) * n + s];
                 gprev[j] = g[j];
             }
+            __syncthreads();  // every wave is done with the previous fragments
+            stage_frags(slot, frags + ((size_t)l * FRAGS + OFF_G3) * 64, G3T * G3K);
+            stage_frags(slot + G3T * G3K * 64, bfrags + (size_t)l * BFRAGS * 64, BFRAGS);
+            __syncthreads();
             // the spline parameters again, from the stored operands
             f32x16 own[2][G3T];
 #pragma unroll
@@ -658,7 +685,7 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
                 bf16x8 h2[G3K];
 #pragma unroll
                 for (int ks = 0; ks < G3K; ++ks) h2[ks] = ops[ks * 64 + lane];
-                third_product(frags + (size_t)l * FRAGS * 64 + lane, h2, own[sb]);
+                third_product(slot + lane, h2, own[sb]);
             }
             own_outputs(bias, l, own);
             // spline deltas of the own sample, natural order padded to 112,
@@ -693,7 +720,7 @@ __global__ __launch_bounds__(64) void train_bf16_kernel(
             bf16x8 X[2][B3K];
 #pragma unroll
             for (int ks = 0; ks < B3K; ++ks) swap_halves(oct[2 * ks], oct[2 * ks + 1], X[0][ks], X[1][ks]);
-            const bf16x8 *Br = bfrags + (size_t)l * BFRAGS * 64 + lane;
+            const bf16x8 *Br = slot + G3T * G3K * 64 + lane;
             float tot[NA];
 #pragma unroll
             for (int sb = 0; sb < 2; ++sb) {
@@ -943,13 +970,13 @@ hipError_t launch_flow_train_bf16(const float *theta, void *frags, void *bfrags,
     const int nf = L * FRAGS * 64, nb = L * BFRAGS * 64;
     hipLaunchKernelGGL(pack_train_kernel, dim3((nf + nb + 255) / 256), dim3(256), 0, s, theta,
                        (bf16x8 *)frags, bias, (bf16x8 *)bfrags, nf);
-    // one single-wave workgroup per 64 samples (spread over every CU), at
-    // most 8 per CU
-    int64_t blocks = (n + 63) / 64;
-    const int64_t cap = 8 * (int64_t)(cus > 0 ? cus : 256);
+    // one workgroup of TR_WAVES waves per TR_WAVES x 64 samples, at most one
+    // per CU (a wave fills a SIMD's registers)
+    int64_t blocks = (n + TR_WAVES * 64 - 1) / (TR_WAVES * 64);
+    const int64_t cap = cus > 0 ? cus : 256;
     if (blocks > cap) blocks = cap;
     float *ext = scratch + (int64_t)L * FS * n + (int64_t)kWgradSlices * PARAMS;
-    hipLaunchKernelGGL(train_bf16_kernel, dim3((unsigned)blocks), dim3(64), 0, s,
+    hipLaunchKernelGGL(train_bf16_kernel, dim3((unsigned)blocks), dim3(TR_WAVES * 64), 0, s,
                        (const bf16x8 *)frags, (const bf16x8 *)bfrags, bias, x, w, n, wsum, scratch,
                        ext, loss);
     return hipGetLastError();
