@@ -176,6 +176,23 @@ int mcubes_integrate(int family, const double *params, int dim, int64_t ncall, i
                      double rel_tol, uint64_t seed, const mcubes_options *opt,
                      mcubes_result *out, double *grid_out, double *trace);
 
+/* mcubes_integrate for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and errors as mcubes_integrate
+ * (kernel_ms is 0: no timing events), but every device buffer lives in one
+ * library-owned array of MCUBES_NOALLOC_SCRATCH doubles per GPU, created with
+ * the library and held until the process ends; no hipMalloc, hipFree or
+ * allocating library call is made.  The scratch must hold 2 dim (nbins + 1)
+ * + dim nbins + 2 blocks + 2 + MCUBES_STATE_LEN doubles; a larger problem
+ * returns MCUBES_E_ARG before any device work.  All calls on one GPU share
+ * its array, and every call initialises what it reads: calls that overlap
+ * on one GPU (several host threads, or several streams) race and must be
+ * serialised by the caller. */
+#define MCUBES_NOALLOC_SCRATCH 32768
+int mcubes_integrate_noalloc(int family, const double *params, int dim, int64_t ncall,
+                             int itmax, double rel_tol, uint64_t seed, const mcubes_options *opt,
+                             mcubes_result *out, double *grid_out, double *trace);
+
 /* Plan: validated problem, stratification (§3.2, as mcubes_plan_sizes) and
  * V-Sample launch geometry for the entry points below.  params: host,
  * copied.  opt may be NULL (defaults).  *plan receives a plan owned by the

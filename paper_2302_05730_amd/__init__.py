@@ -123,6 +123,10 @@ _SIGNATURES = {
                                         ctypes.c_int, ctypes.c_double, ctypes.c_uint64,
                                         ctypes.POINTER(mcubes_options),
                                         ctypes.POINTER(mcubes_result), _dp, _dp]),
+    "mcubes_integrate_noalloc": (ctypes.c_int, [ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int64,
+                                                ctypes.c_int, ctypes.c_double, ctypes.c_uint64,
+                                                ctypes.POINTER(mcubes_options),
+                                                ctypes.POINTER(mcubes_result), _dp, _dp]),
     "mcubes_plan_create": (ctypes.c_int, [ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int64,
                                           ctypes.c_uint64, ctypes.POINTER(mcubes_options),
                                           ctypes.POINTER(_vp)]),
@@ -260,13 +264,26 @@ def mcubes_integrate(family, params, dim, ncall, itmax, rel_tol, seed, options=N
                      grid=True, trace=True):
     """Whole integrator.  Returns a dict with the mcubes_result fields plus the
     final grid (list of dim rows) and the per-iteration (I_t, var_t) trace."""
+    return _integrate("mcubes_integrate", family, params, dim, ncall, itmax, rel_tol, seed,
+                      options, grid, trace)
+
+
+def mcubes_integrate_noalloc(family, params, dim, ncall, itmax, rel_tol, seed, options=None,
+                             grid=True, trace=True):
+    """mcubes_integrate on the library's static device scratch (no device
+    allocation); same return value."""
+    return _integrate("mcubes_integrate_noalloc", family, params, dim, ncall, itmax, rel_tol,
+                      seed, options, grid, trace)
+
+
+def _integrate(name, family, params, dim, ncall, itmax, rel_tol, seed, options, grid, trace):
     keep, pp = _params(params, dim)
     opt = options if options is not None else mcubes_default_options()
     res = mcubes_result()
     nb = opt.nbins
     g_buf = (ctypes.c_double * (dim * (nb + 1)))() if grid else None
     t_buf = (ctypes.c_double * (2 * itmax))() if trace else None
-    rc = lib().mcubes_integrate(int(family), pp, int(dim), int(ncall), int(itmax), float(rel_tol),
+    rc = getattr(lib(), name)(int(family), pp, int(dim), int(ncall), int(itmax), float(rel_tol),
             int(seed) & (2**64 - 1), ctypes.byref(opt), ctypes.byref(res),
             ctypes.cast(g_buf, _dp) if grid else None,
             ctypes.cast(t_buf, _dp) if trace else None)

@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -370,6 +371,40 @@ cleanup:
 
 }  // namespace mcubes
 
+// Scratch of mcubes_integrate_noalloc: grids, bins, block partials, estimate
+// and combined state of one integration, in the layout of integrate_run.  Each
+// GPU holds its own copy for the life of the process.  In host code the name
+// is not a device address: kernels and copies get the pointer that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double scratch[MCUBES_NOALLOC_SCRATCH];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+double *g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// The current device's copy of `scratch` (looked up once per device).
+int noalloc_scratch(double **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(MCUBES_E_DEVICE, "device %d is beyond the %d this library tracks", dev,
+                    kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch[dev];
+    return MCUBES_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void mcubes_default_options(mcubes_options *opt) {
@@ -591,6 +626,29 @@ int mcubes_microbench(int kind, int family, const double *params, int dim,
     const hipError_t e = launch_microbench(kind, family, dim, A, d_points, npts, calls_per_thread,
                                            blocks, block, d_out, as_stream(stream));
     return e == hipSuccess ? MCUBES_OK : hip_fail(e, "microbenchmark launch");
+}
+
+int mcubes_integrate_noalloc(int family, const double *params, int dim, int64_t ncall,
+                             int itmax, double rel_tol, uint64_t seed,
+                             const mcubes_options *opt_in, mcubes_result *out, double *grid_out,
+                             double *trace) {
+    if (!out) return fail(MCUBES_E_ARG, "out is NULL");
+    if (itmax < 1 || itmax > MCUBES_MAX_ITERATIONS)
+        return fail(MCUBES_E_ARG, "itmax must be in [1, %d]", MCUBES_MAX_ITERATIONS);
+    if (!(rel_tol >= 0.0) || !isfinite(rel_tol)) return fail(MCUBES_E_ARG, "rel_tol must be finite and >= 0");
+    mcubes_plan P;  // built in place: no workspace, nothing to free
+    int rc = plan_init(family, params, dim, ncall, seed, opt_in, &P);
+    if (rc != MCUBES_OK) return rc;
+    const int64_t need = integrate_buffer_len(P);
+    if (need > MCUBES_NOALLOC_SCRATCH)
+        return fail(MCUBES_E_ARG,
+                    "this problem needs %lld doubles of scratch (dim %d, %d bins, %d blocks); "
+                    "mcubes_integrate_noalloc holds %d",
+                    (long long)need, P.dim, P.nb, P.blocks, MCUBES_NOALLOC_SCRATCH);
+    double *buf = nullptr;
+    rc = noalloc_scratch(&buf);
+    if (rc != MCUBES_OK) return rc;
+    return integrate_run(P, buf, itmax, rel_tol, false, out, grid_out, trace);
 }
 
 int mcubes_integrate(int family, const double *params, int dim, int64_t ncall, int itmax,

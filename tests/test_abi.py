@@ -138,10 +138,11 @@ def test_plan_create_rejects(kwargs, code):
     assert mc.mcubes_last_error()
 
 
-def test_integrate_rejects_bad_arguments():
+@pytest.mark.parametrize("fn", ["mcubes_integrate", "mcubes_integrate_noalloc"])
+def test_integrate_rejects_bad_arguments(fn):
     for itmax, tol in ((0, 0.1), (2000, 0.1), (3, float("nan")), (3, -1.0)):
         with pytest.raises(mc.MCubesError) as ei:
-            mc.mcubes_integrate(3, [1.0, 0.5], 1, 1000, itmax, tol, 0)
+            getattr(mc, fn)(3, [1.0, 0.5], 1, 1000, itmax, tol, 0)
         assert ei.value.code == mc.MCUBES_E_ARG
 
 
