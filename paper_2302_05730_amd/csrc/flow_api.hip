@@ -485,10 +485,10 @@ void mcubes_default_flow_options(mcubes_flow_options *o) {
     o->precision = MCUBES_BF16;
     o->train_items = (int64_t)1 << 20;
     o->epochs = 10;
-    o->rounds = 6;
-    o->round_samples = (int64_t)1 << 22;
-    o->round_epochs = 2;
-    o->tail_rounds = 2;
+    o->rounds = 4;
+    o->round_samples = (int64_t)1 << 24;
+    o->round_epochs = 3;
+    o->tail_rounds = 4;
     o->batch = 65536;
     o->lr = 4e-3;
     o->round_lr = 2e-3;

@@ -529,13 +529,46 @@ __device__ __forceinline__ void stage_frags(bf16x8 *dst, const bf16x8 *__restric
     for (int i = threadIdx.x; i < frags * 64; i += TR_WAVES * 64) dst[i] = src[i];
 }
 
+// The BF16 fields leave the pass through a per-wave LDS tile T[f][c] (nf
+// features of NC consecutive samples, bf16 bits): a lane holds one sample's
+// features, but a row of the field-major scratch wants samples side by side,
+// so the tile turns the lane's one-element stores (one per feature) into
+// 16-byte stores of 8 samples of one feature, eight times fewer.  (On this
+// chip stores and loads share the vector-memory counter, so fewer stores in
+// flight also shorten every later wait for a load.)  Rows start 16-byte
+// aligned when n is a multiple of 8 (s0 is); otherwise, and for an octet
+// reaching past n, element stores.  Tile writes and reads of one wave are
+// executed in order by the LDS.
+constexpr int TILE = NB * RAW * 64;  // the largest block: 99 spline deltas of 64 samples
+
+template <int NC>
+__device__ __forceinline__ void flush_tile(const uint16_t *T, int nf, uint16_t *__restrict__ b16,
+                                           int F0, int64_t n, int64_t s0, int lane) {
+    constexpr int OCT = NC / 8;
+    const bool aligned = (n & 7) == 0;
+    for (int q = lane; q < nf * OCT; q += 64) {
+        const int f = q / OCT, k = q - f * OCT;
+        const int64_t s = s0 + 8 * k;
+        if (s >= n) continue;
+        uint16_t *dst = b16 + (int64_t)(F0 + f) * n + s;
+        const uint16_t *src = T + f * NC + 8 * k;
+        if (aligned && s + 8 <= n) {
+            *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(src);
+        } else {
+            for (int e = 0; e < 8 && s + e < n; ++e) dst[e] = src[e];
+        }
+    }
+}
+
 __global__ __launch_bounds__(TR_WAVES * 64) void train_bf16_kernel(
     const bf16x8 *__restrict__ frags, const bf16x8 *__restrict__ bfrags,
     const float *__restrict__ bias, const double *__restrict__ x, const double *__restrict__ w,
     int64_t n, const double *__restrict__ wsum, float *__restrict__ scratch, float *__restrict__ ext,
     double *__restrict__ loss) {
     __shared__ bf16x8 slot[TR_SLOT * 64];
+    __shared__ __align__(16) uint16_t tiles[TR_WAVES][TILE];
     const int wave = threadIdx.x >> 6;
+    uint16_t *tile = tiles[wave];
     const int lane = threadIdx.x & 63, h = lane >> 5, col = lane & 31;
     const int64_t n64 = (n + 63) / 64 * 64;
     double lsum = 0.0;
@@ -607,11 +640,11 @@ __global__ __launch_bounds__(TR_WAVES * 64) void train_bf16_kernel(
                         const int r = 8 * (ks % 2) + i;
                         v[i] = fmaxf(acc1[ks / 2][r] + bb[i], 0.0f);
                         m1 |= (v[i] > 0.0f ? 1u : 0u) << (8 * ks + i);
-                        if (clive[sb])
-                            b16[(FS_H1 + acc_feature(ks / 2, r, h)) * n + cs[sb]] = bf16_bits(v[i]);
+                        tile[acc_feature(ks / 2, r, h) * 32 + col] = bf16_bits(v[i]);
                     }
                     h1[ks] = pack8(v);
                 }
+                flush_tile<32>(tile, HID, b16, FS_H1, n, base + 32 * sb, lane);
                 if (wlive) relu_bits(ext_l, n64, group, sb, 0)[lane] = m1;
                 f32x16 acc2[G2T];
 #pragma unroll
@@ -634,12 +667,12 @@ __global__ __launch_bounds__(TR_WAVES * 64) void train_bf16_kernel(
                         const int r = 8 * (ks % 2) + i;
                         v[i] = fmaxf(acc2[ks / 2][r] + bb[i], 0.0f);
                         m2 |= (v[i] > 0.0f ? 1u : 0u) << (8 * ks + i);
-                        if (clive[sb])
-                            b16[(FS_H2 + acc_feature(ks / 2, r, h)) * n + cs[sb]] = bf16_bits(v[i]);
+                        tile[acc_feature(ks / 2, r, h) * 32 + col] = bf16_bits(v[i]);
                     }
                     h2[ks] = pack8(v);
                     if (wlive) ops[ks * 64 + lane] = h2[ks];
                 }
+                flush_tile<32>(tile, HID, b16, FS_H2, n, base + 32 * sb, lane);
                 if (wlive) relu_bits(ext_l, n64, group, sb, 1)[lane] = m2;
                 third_product(Fr + OFF_G3 * 64, h2, own[sb]);
             }
@@ -709,13 +742,14 @@ __global__ __launch_bounds__(TR_WAVES * 64) void train_bf16_kernel(
 #pragma unroll
                 for (int k = 0; k < RAW; ++k) {
                     gr[b * RAW + k] = graw[k];
-                    if (live) b16[(FS_DOUT + b * RAW + k) * n + s] = bf16_bits(graw[k]);
+                    tile[(b * RAW + k) * 64 + lane] = bf16_bits(graw[k]);
                 }
                 const int from = (b * RAW) / 8, to = b == NB - 1 ? 2 * B3K : ((b + 1) * RAW) / 8;
 #pragma unroll
                 for (int o = 0; o < 2 * B3K; ++o)
                     if (o >= from && o < to) oct[o] = pack8(&gr[8 * o]);
             }
+            flush_tile<64>(tile, NB * RAW, b16, FS_DOUT, n, base, lane);
             // operands of the two sample blocks
             bf16x8 X[2][B3K];
 #pragma unroll
@@ -744,10 +778,11 @@ __global__ __launch_bounds__(TR_WAVES * 64) void train_bf16_kernel(
                     for (int i = 0; i < 8; ++i) {
                         const int r = 8 * (ks % 2) + i, f = acc_feature(ks / 2, r, h);
                         v[i] = ((m2 >> (8 * ks + i)) & 1u) ? a3[ks / 2][r] : 0.0f;
-                        if (clive[sb]) b16[(FS_D2 + f) * n + cs[sb]] = bf16_bits(v[i]);
+                        tile[f * 32 + col] = bf16_bits(v[i]);
                     }
                     Y[ks] = pack8(v);
                 }
+                flush_tile<32>(tile, HID, b16, FS_D2, n, base + 32 * sb, lane);
                 // through W2 and the first ReLU
                 f32x16 a2[B2T];
 #pragma unroll
@@ -766,10 +801,11 @@ __global__ __launch_bounds__(TR_WAVES * 64) void train_bf16_kernel(
                     for (int i = 0; i < 8; ++i) {
                         const int r = 8 * (ks % 2) + i, f = acc_feature(ks / 2, r, h);
                         v[i] = ((m1 >> (8 * ks + i)) & 1u) ? a2[ks / 2][r] : 0.0f;
-                        if (clive[sb]) b16[(FS_D1 + f) * n + cs[sb]] = bf16_bits(v[i]);
+                        tile[f * 32 + col] = bf16_bits(v[i]);
                     }
                     Z[ks] = pack8(v);
                 }
+                flush_tile<32>(tile, HID, b16, FS_D1, n, base + 32 * sb, lane);
                 // through W1 to the one-blob inputs, then through the encoding:
                 // row tile t holds the 32 bumps of conditioning coordinate t
 #pragma unroll
