@@ -636,8 +636,8 @@ typedef struct {
     int64_t train_items;   /* default 2^20 over all warm-up iterations (each gives p samples) */
     int32_t epochs;        /* default 10 */
     int32_t rounds;        /* default 4 */
-    int64_t round_samples; /* default 2^24 */
-    int32_t round_epochs;  /* default 3 */
+    int64_t round_samples; /* default 2^25 */
+    int32_t round_epochs;  /* default 2 */
     int32_t tail_rounds;   /* default 4 */
     int64_t batch;         /* default 65536 */
     double lr;             /* default 4e-3 */

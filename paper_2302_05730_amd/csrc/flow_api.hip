@@ -486,8 +486,8 @@ void mcubes_default_flow_options(mcubes_flow_options *o) {
     o->train_items = (int64_t)1 << 20;
     o->epochs = 10;
     o->rounds = 4;
-    o->round_samples = (int64_t)1 << 24;
-    o->round_epochs = 3;
+    o->round_samples = (int64_t)1 << 25;
+    o->round_epochs = 2;
     o->tail_rounds = 4;
     o->batch = 65536;
     o->lr = 4e-3;

@@ -275,13 +275,14 @@ __device__ __forceinline__ double wave_sum(double v) {
 // the LDS instructions), and the same value is the byte offset of the bin's
 // left edge in the axis's row of the global grid.
 //   FP64 form: bin sums of every axis, and the edges E_i and widths W_i of the
-//   staged axes (the even axes; odd axes read (E_i, E_i+1) from the global
-//   grid through the vector L1 cache; d = 1 stages its one axis).
+//   staged axes (with bin sums, axes 0, 4, 8, the others reading (E_i, E_i+1)
+//   from the global grid through the vector L1 cache; without bin sums, and
+//   for d = 1, every axis).
 //   FP32 form: bin sums, and (E_i, W_i) as a pair of floats for every axis.
 template <int D, bool BINS, bool F32>
 struct VsLds {
     static constexpr int kRow = kMaxBins * 8;
-    static constexpr int kStaged = F32 ? D : (D >= 2 ? (D + 1) / 2 : 1);
+    static constexpr int kStaged = F32 ? D : (D >= 2 && BINS ? (D + 3) / 4 : D);
     static constexpr int kH = 0;                                   // FP64 sums, axis j
     static constexpr int kE = kH + (BINS ? D : 0) * kRow;         // FP64 E_i, staged axis l
     static constexpr int kW = kE + (F32 ? 0 : kStaged) * kRow;     // FP64 W_i, staged axis l
@@ -289,19 +290,22 @@ struct VsLds {
     static constexpr int kBytes = kEW32 + (F32 ? D : 0) * kRow;
 };
 
-// Grid-table reads of odd axes go through the vector L1 cache (two adjacent
-// edges of the global grid row, 4 KB per axis at 500 bins), those of even
-// axes through LDS, so that the two memory paths share the random reads and
-// the LDS keeps its bandwidth for the bin updates.
-template <int D>
+// Grid-table reads are split between the vector L1 cache (two adjacent edges
+// of the global grid row, 4 KB per axis at 500 bins) and LDS, so that the two
+// memory paths share the random reads.  With bin sums the LDS also takes d
+// FP64 atomics per sample and is the busier path: three axes in four read
+// through L1 (measured 6% faster over the three 8-D integrands than every
+// other axis, and than all through L1).  Without bin sums the LDS is free
+// and every axis reads it (3% faster than every other axis).
+template <int D, bool BINS>
 constexpr bool table_from_l1(int j) {
-    return D >= 2 && (j & 1);
+    return BINS && D >= 2 && (j & 3) != 0;
 }
 
 // Staged-table index of axis j (FP64 form).
-template <int D>
+template <int D, bool BINS>
 constexpr int staged_axis(int j) {
-    return D >= 2 ? j / 2 : 0;
+    return BINS && D >= 2 ? j / 4 : j;
 }
 
 // The bin coordinate of axis j: z = (c_j + u) fl(nb/g) with u = (r + 1/2) 2^-32,
@@ -359,14 +363,14 @@ __device__ __forceinline__ double draw(const VsArgs &A, uint32_t iteration, cons
         for (int q = 0; q < 4; ++q) {
             const int j = 4 * b + q;
             if (j < D) {
-                if (table_from_l1<D>(j)) {
+                if (table_from_l1<D, BINS>(j)) {
                     // (E_i, E_i+1) of the global row; the width is formed below
                     // exactly as the staging loop forms the staged widths
                     const double2 e = *reinterpret_cast<const double2 *>(row[j] + o8[j]);
                     e0[q] = e.x;
                     e1[q] = e.y;
                 } else {
-                    const int l = staged_axis<D>(j);
+                    const int l = staged_axis<D, BINS>(j);
                     e0[q] = *reinterpret_cast<const double *>(lds + L::kE + l * L::kRow + o8[j]);
                     e1[q] = *reinterpret_cast<const double *>(lds + L::kW + l * L::kRow + o8[j]);
                 }
@@ -376,7 +380,7 @@ __device__ __forceinline__ double draw(const VsArgs &A, uint32_t iteration, cons
         for (int q = 0; q < 4; ++q) {
             const int j = 4 * b + q;
             if (j < D) {
-                const double W = table_from_l1<D>(j) ? e1[q] - e0[q] : e1[q];
+                const double W = table_from_l1<D, BINS>(j) ? e1[q] - e0[q] : e1[q];
                 const double x = __fma_rn(W, phi[q], e0[q]);
                 prod = prod * W;
                 Family<F, D>::axis(acc, ca[j], cu[j], x);
@@ -499,8 +503,8 @@ __device__ __forceinline__ void vs_block(const VsArgs &A, const double *__restri
         if constexpr (F32) {
             *reinterpret_cast<float2 *>(lds + L::kEW32 + j * L::kRow + 8 * i) =
                 make_float2((float)e0, (float)(e1 - e0));
-        } else if (!table_from_l1<D>(j)) {
-            const int l = staged_axis<D>(j);
+        } else if (!table_from_l1<D, BINS>(j)) {
+            const int l = staged_axis<D, BINS>(j);
             *reinterpret_cast<double *>(lds + L::kE + l * L::kRow + 8 * i) = e0;
             *reinterpret_cast<double *>(lds + L::kW + l * L::kRow + 8 * i) = e1 - e0;
         }

@@ -133,6 +133,23 @@ def test_launch_geometry_does_not_change_results(mc, block, blocks):
     assert_iteration_close(family, got, ref, m, p, f"block={block} blocks={blocks}")
 
 
+@pytest.mark.parametrize("family", [0, 3, 5])
+def test_many_samples_per_cube_on_one_workgroup(mc, family):
+    """p > 2 (10-D, g = 3, p = 17) on a grid of one workgroup, so that every
+    thread walks many cubes."""
+    dim, nb, ncall = 10, 50, 1 << 20
+    g, m, p, n = oracle.plan(dim, ncall)
+    assert p > 2
+    rng = np.random.default_rng(101 + family)
+    params = list(rng.uniform(0.2, 1.0, dim)) + list(rng.uniform(0.2, 0.8, dim))
+    grid = random_grid(rng, dim, nb)
+    ref = oracle.iteration(family, params, dim, nb, ncall, 4, 1, grid)
+    plan = mc.mcubes_plan_create(family, params, dim, ncall, 4,
+                                 mc.mcubes_default_options(nbins=nb, block_size=256, blocks=1))
+    got = gpu_iteration(plan, 1, grid)
+    assert_iteration_close(family, got, ref, m, p, f"family={family}")
+
+
 def test_repeatable(mc):
     family, dim, nb, ncall = 3, 5, 200, 500_000
     rng = np.random.default_rng(5)
