@@ -193,9 +193,10 @@ def bench_batch(mc, n, iters, full=True):
     flops_iter = sum(flops_per_sample(p.family, p.dim) * pl[3]
                      for p, pl in zip(problems, plans))
 
-    def run(use_graph, itmax=iters, rel_tol=0.0):
-        rc, res = b.integrate(itmax, rel_tol, use_graph=use_graph)
-        info = b.info()
+    def run(use_graph, itmax=iters, rel_tol=0.0, batch=None):
+        bb = batch if batch is not None else b
+        rc, res = bb.integrate(itmax, rel_tol, use_graph=use_graph)
+        info = bb.info()
         ms = info["last_ms"]
         return {"ms": round(ms, 3), "iterations": info["last_iterations"],
                 "samples": info["last_samples"],
@@ -218,6 +219,11 @@ def bench_batch(mc, n, iters, full=True):
            "device_mib": round(info["device_bytes"] / 2**20, 1), "create_s": round(t_b - t_a, 3),
            "fixed_iterations_default_graph": default_graph,
            "fixed_iterations_default_eager": default_eager}
+    # the same workload with the FP32 map and integrand (default split, graph)
+    b32 = mc.Batch(items, seed=0, options=mc.mcubes_default_options(precision=mc.MCUBES_FP32))
+    b32.integrate(1, 0.0)
+    out["fixed_iterations_fp32_default_graph"], _ = run(True, batch=b32)
+    b32.destroy()
     if not full:
         return out
     t_c = time.perf_counter()

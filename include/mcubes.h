@@ -341,8 +341,11 @@ int mcubes_microbench(int kind, int family, const double *params, int dim,
  * 8 * (2 * sum dim_i * (nbins + 1) + n * MCUBES_STATE_LEN) bytes plus the
  * tile lists) and one internal HIP stream; mcubes_batch_integrate and
  * mcubes_batch_autotune order themselves after earlier work on opt->stream
- * and return when done.  Only MCUBES_FP64 is supported.  opt->block_size,
- * when not 0, fixes the block size of every class; opt->blocks is ignored.
+ * and return when done.  opt->precision is MCUBES_FP64 or MCUBES_FP32 (the
+ * FP32 map and integrand of mcubes_integrate, for every integrand of the
+ * batch; its results then agree with the single-integrand FP32 path up to
+ * the rounding of the sums).  opt->block_size, when not 0, fixes the block
+ * size of every class; opt->blocks is ignored.
  * A batch may be used from one host thread at a time.
  * ---------------------------------------------------------------------- */
 typedef struct {
@@ -362,7 +365,7 @@ typedef struct {
     int32_t nbins;
     int32_t tuned;          /* 1 after mcubes_batch_autotune */
     int32_t streams;        /* streams the class launches are spread over */
-    int32_t reserved;
+    int32_t precision;      /* mcubes_precision of every integrand's map and integrand */
     int64_t grids_len;      /* sum over i of dim_i * (nbins + 1): packed grids, item order */
     int64_t samples_per_iter; /* sum of N_i over the integrands still running */
     int64_t device_bytes;   /* device memory held by the batch */

@@ -94,7 +94,7 @@ class mcubes_batch_info(ctypes.Structure):
     _fields_ = [("items", ctypes.c_int32), ("classes", ctypes.c_int32),
                 ("tiles", ctypes.c_int32), ("launches", ctypes.c_int32),
                 ("nbins", ctypes.c_int32), ("tuned", ctypes.c_int32),
-                ("streams", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("streams", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("grids_len", ctypes.c_int64), ("samples_per_iter", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("last_iterations", ctypes.c_int32),
                 ("last_replans", ctypes.c_int32), ("last_samples", ctypes.c_int64),

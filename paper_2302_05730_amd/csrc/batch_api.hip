@@ -56,6 +56,7 @@ constexpr int64_t kMaxShares = 1 << 20;
 
 struct mcubes_batch {
     int n = 0, nb = 0, adapt_iters = -1, skip = 0, forced_block = 0;
+    int prec = 0;  // 1: the FP32 map and integrand (MCUBES_FP32)
     double alpha = 1.5;
     int cus = 0;
     void *user_stream = nullptr;
@@ -178,9 +179,9 @@ ClassPlan make_class(const mcubes_batch *B, const ClassKey &key) {
     ClassPlan c;
     c.key = key;
     const VsKernel &K = family_table(key.family)[key.dim];
-    c.func = K.tiles_func[0][key.p2];
-    c.launch[0] = K.tiles_launch[0][key.p2];
-    c.launch[1] = K.tiles_launch[1][key.p2];
+    c.func = K.tiles_func[B->prec][0][key.p2];
+    c.launch[0] = K.tiles_launch[B->prec][0][key.p2];
+    c.launch[1] = K.tiles_launch[B->prec][1][key.p2];
     hipFuncAttributes fa;
     const bool ok = hipFuncGetAttributes(&fa, c.func) == hipSuccess;
     c.max_block = ok ? fa.maxThreadsPerBlock : 0;
@@ -362,8 +363,8 @@ int mcubes_batch_create(const mcubes_batch_item *items, int n, uint64_t seed,
     if (opt.block_size != 0 &&
         (opt.block_size < 64 || opt.block_size > kMaxBlock || opt.block_size % 64 != 0))
         return fail(MCUBES_E_ARG, "block_size must be 0 or a multiple of 64 in [64, %d]", kMaxBlock);
-    if (opt.precision != MCUBES_FP64)
-        return fail(MCUBES_E_ARG, "the batched form supports MCUBES_FP64 only");
+    if (opt.precision != MCUBES_FP64 && opt.precision != MCUBES_FP32)
+        return fail(MCUBES_E_ARG, "precision must be MCUBES_FP64 or MCUBES_FP32");
     // validate every item before touching the device
     std::vector<int64_t> sizes(4 * (size_t)n);
     for (int i = 0; i < n; ++i) {
@@ -392,6 +393,7 @@ int mcubes_batch_create(const mcubes_batch_item *items, int n, uint64_t seed,
     B->skip = opt.skip;
     B->alpha = opt.alpha;
     B->forced_block = opt.block_size;
+    B->prec = opt.precision == MCUBES_FP32 ? 1 : 0;
     B->user_stream = opt.stream;
     B->items.resize(n);
     B->family.resize(n);
@@ -495,6 +497,7 @@ int mcubes_batch_get_info(const mcubes_batch *B, mcubes_batch_info *info) {
     info->streams = B->streams;
     info->nbins = B->nb;
     info->tuned = B->tuned ? 1 : 0;
+    info->precision = B->prec ? MCUBES_FP32 : MCUBES_FP64;
     info->grids_len = B->grids_len;
     info->samples_per_iter = B->planned_samples;
     info->device_bytes = (int64_t)B->device_bytes;

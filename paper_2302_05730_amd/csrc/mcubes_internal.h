@@ -69,8 +69,8 @@ typedef hipError_t (*VsTilesLaunchFn)(const BatchItem *items, const BatchTile *t
 struct VsKernel {
     VsLaunchFn launch[2][2][2];
     const void *func[2][2][2];  // kernel symbols, for occupancy queries and attributes
-    VsTilesLaunchFn tiles_launch[2][2];  // batched form, [nobins][p2]
-    const void *tiles_func[2][2];
+    VsTilesLaunchFn tiles_launch[2][2][2];  // batched form, [fp32][nobins][p2]
+    const void *tiles_func[2][2][2];
 };
 
 // Per-family tables, index = dim (1..kMaxDim); defined in vsample_f<family>.hip.

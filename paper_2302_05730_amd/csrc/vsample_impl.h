@@ -655,29 +655,30 @@ __global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_kernel(const V
 // items of one integrand; the hardware dispatcher hands out the tiles as
 // workgroups finish).  Tiles of integrands marked done exit at once.  The
 // iteration number is read from device memory so that one captured graph
-// serves every iteration.
-template <int F, int D, bool P2, bool BINS>
+// serves every iteration.  F32 selects the FP32 map and integrand, as in
+// the single form.
+template <int F, int D, bool P2, bool BINS, bool F32>
 __global__ __launch_bounds__((vs_max_block<F, D>())) void vsample_tiles_kernel(
     const BatchItem *__restrict__ items, const BatchTile *__restrict__ tiles,
     const double *__restrict__ grids, double *__restrict__ bins, double *__restrict__ partials,
     const uint32_t *__restrict__ iter, const uint32_t *__restrict__ done) {
-    __shared__ VsShared<D, BINS, false> sh;
+    __shared__ VsShared<D, BINS, F32> sh;
     const BatchTile tile = tiles[blockIdx.x];
     if (done[tile.item] != 0u) return;
     const BatchItem &B = items[tile.item];
     const uint32_t w0 = tile.w_begin + threadIdx.x;
     const uint32_t count = w0 < tile.w_end ? (tile.w_end - 1u - w0) / blockDim.x + 1u : 0u;
-    vs_block<F, D, P2, BINS, false>(B.args, grids + B.grid_off, bins + B.bins_off,
+    vs_block<F, D, P2, BINS, F32>(B.args, grids + B.grid_off, bins + B.bins_off,
                                     partials + 2 * (size_t)tile.partial, w0, blockDim.x, count,
                                     B.step_block, B.step_digit_block, *iter, sh);
 }
 
-template <int F, int D, bool P2, bool BINS>
+template <int F, int D, bool P2, bool BINS, bool F32>
 hipError_t launch_vsample_tiles(const BatchItem *items, const BatchTile *tiles, int ntiles,
                                 const double *grids, double *bins, double *partials,
                                 const uint32_t *iter, const uint32_t *done, int block,
                                 hipStream_t stream) {
-    hipLaunchKernelGGL((vsample_tiles_kernel<F, D, P2, BINS>), dim3(ntiles), dim3(block), 0,
+    hipLaunchKernelGGL((vsample_tiles_kernel<F, D, P2, BINS, F32>), dim3(ntiles), dim3(block), 0,
                        stream, items, tiles, grids, bins, partials, iter, done);
     return hipGetLastError();
 }
@@ -698,17 +699,15 @@ hipError_t launch_vsample(const VsArgs &args, const double *grid, double *bins, 
         {M(F, D, false, true, F32), M(F, D, true, true, F32)},                 \
         {M(F, D, false, false, F32), M(F, D, true, false, F32)}                \
     }
-#define MCUBES_VS_ENTRY(F, D)                                                          \
-    VsKernel {                                                                         \
-        {MCUBES_VS_SET(MCUBES_VS_FN, F, D, false), MCUBES_VS_SET(MCUBES_VS_FN, F, D, true)}, \
+#define MCUBES_VS_TFN(F, D, P2, BINS, F32) &launch_vsample_tiles<F, D, P2, BINS, F32>
+#define MCUBES_VS_TSYM(F, D, P2, BINS, F32) \
+    reinterpret_cast<const void *>(&vsample_tiles_kernel<F, D, P2, BINS, F32>)
+#define MCUBES_VS_ENTRY(F, D)                                                              \
+    VsKernel {                                                                             \
+        {MCUBES_VS_SET(MCUBES_VS_FN, F, D, false), MCUBES_VS_SET(MCUBES_VS_FN, F, D, true)},   \
         {MCUBES_VS_SET(MCUBES_VS_SYM, F, D, false), MCUBES_VS_SET(MCUBES_VS_SYM, F, D, true)}, \
-        {{&launch_vsample_tiles<F, D, false, true>, &launch_vsample_tiles<F, D, true, true>}, \
-         {&launch_vsample_tiles<F, D, false, false>,                                   \
-          &launch_vsample_tiles<F, D, true, false>}},                                  \
-        {{reinterpret_cast<const void *>(&vsample_tiles_kernel<F, D, false, true>),    \
-          reinterpret_cast<const void *>(&vsample_tiles_kernel<F, D, true, true>)},    \
-         {reinterpret_cast<const void *>(&vsample_tiles_kernel<F, D, false, false>),   \
-          reinterpret_cast<const void *>(&vsample_tiles_kernel<F, D, true, false>)}}   \
+        {MCUBES_VS_SET(MCUBES_VS_TFN, F, D, false), MCUBES_VS_SET(MCUBES_VS_TFN, F, D, true)}, \
+        {MCUBES_VS_SET(MCUBES_VS_TSYM, F, D, false), MCUBES_VS_SET(MCUBES_VS_TSYM, F, D, true)} \
     }
 
 // A host function returning the table of one family (a namespace-scope const

@@ -54,7 +54,7 @@ int main(void) {
     F(mcubes_batch_item, ncall) F(mcubes_batch_item, params)
     printf("mcubes_batch_info size %zu\n", sizeof(mcubes_batch_info));
     F(mcubes_batch_info, grids_len) F(mcubes_batch_info, last_iterations)
-    F(mcubes_batch_info, streams)
+    F(mcubes_batch_info, streams) F(mcubes_batch_info, precision)
     F(mcubes_batch_info, last_samples) F(mcubes_batch_info, last_ms)
     printf("mcubes_batch_class size %zu\n", sizeof(mcubes_batch_class));
     F(mcubes_batch_class, shares) F(mcubes_batch_class, samples) F(mcubes_batch_class, tuned_ms)
@@ -165,7 +165,7 @@ _GOOD = (3, 2, 1000, [1.0, 1.0, 0.5, 0.5])
     ([_GOOD, _GOOD, (1, 2, 1000, [0.0, 1.0, 0.5, 0.5])], {}, mc.MCUBES_E_INTEGRAND),
     ([(0, 2, 1000, [float("nan"), 1.0, 0.5, 0.5])], {}, mc.MCUBES_E_INTEGRAND),
     ([(3, 2, 2 * 2**32 + 4, [1.0, 1.0, 0.5, 0.5])], {}, mc.MCUBES_E_ARG),
-    ([_GOOD], dict(precision=mc.MCUBES_FP32), mc.MCUBES_E_ARG),
+    ([_GOOD], dict(precision=mc.MCUBES_BF16), mc.MCUBES_E_ARG),
     ([_GOOD], dict(nbins=501), mc.MCUBES_E_ARG),
     ([_GOOD], dict(block_size=96), mc.MCUBES_E_ARG),
     ([_GOOD], dict(skip=-2), mc.MCUBES_E_ARG),

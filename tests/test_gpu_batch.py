@@ -28,7 +28,8 @@ import pytest
 
 import oracle
 import workloads
-from parity_util import EPS, LIBM_FAMILIES, host_threads, random_grid, var_tolerance
+from parity_util import (EPS, LIBM_FAMILIES, gpu_iteration, gpu_refine, host_threads,
+                         random_grid, var_tolerance)
 
 pytestmark = pytest.mark.gpu
 
@@ -173,6 +174,40 @@ def test_batch_lockstep_matches_oracle(mc):
             tol = var_tolerance(pr.family, rV, rB, m, p)
             assert abs(gV - rV) <= tol * abs(rV) + 1e-300, f"{tag}: var {gV!r} vs {rV!r}"
             ref_grid = oracle.refine(grids[i], rB)
+            assert np.allclose(np.array(new[i]), ref_grid, rtol=1e-12, atol=1e-15), tag
+            grids[i] = ref_grid
+
+
+def test_fp32_batch_matches_the_single_fp32_path(mc):
+    """The FP32 form of the batch (every integrand mapped and evaluated in
+    FP32, as mcubes_integrate with MCUBES_FP32) against the single-integrand
+    FP32 path with stream id = the item's index: the same samples through the
+    same FP32 arithmetic, so I_t, var_t and the bins agree up to the order of
+    the sums (1e-12; the RMS weight for the oscillatory family), and the
+    refined grids with them.  Two lock-step iterations from random grids; the
+    single FP32 path is itself pinned to the FP64 oracle by its own tests."""
+    probs = workloads.batch_problems(**SMALL)
+    nb = 500
+    opt = mc.mcubes_default_options(nbins=nb, precision=mc.MCUBES_FP32)
+    b = mc.Batch(_items(probs), seed=77, options=opt)
+    assert b.info()["precision"] == mc.MCUBES_FP32
+    rng = np.random.default_rng(32)
+    grids = [random_grid(rng, p.dim, nb) for p in probs]
+    for t in range(2):
+        _say(f"fp32 batch lock-step t={t}")
+        est, new = b.step(t, grids)
+        for i, (pr, (gI, gV)) in enumerate(zip(probs, est)):
+            plan = mc.mcubes_plan_create(pr.family, pr.params, pr.dim, pr.ncall, 77,
+                                         mc.mcubes_default_options(nbins=nb,
+                                                                   precision=mc.MCUBES_FP32,
+                                                                   stream_id=i))
+            sI, sV, sB = gpu_iteration(plan, t, grids[i])
+            g, m, p, n = oracle.plan(pr.dim, pr.ncall)
+            tag = f"t={t} item {i} ({pr.name})"
+            scale = max(abs(sI), math.sqrt(float(sB[0].sum()) / n)) if pr.family == 0 else abs(sI)
+            assert abs(gI - sI) <= 1e-12 * scale + 1e-300, f"{tag}: I {gI!r} vs {sI!r}"
+            assert abs(gV - sV) <= 1e-12 * abs(sV) + 1e-300, f"{tag}: var {gV!r} vs {sV!r}"
+            ref_grid = gpu_refine(plan, grids[i], sB)
             assert np.allclose(np.array(new[i]), ref_grid, rtol=1e-12, atol=1e-15), tag
             grids[i] = ref_grid
 
