@@ -86,19 +86,29 @@ def host_cpu():
     return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
 
 
+def _code_only(text):
+    """C/C++ source without its comments and blank lines (the part that
+    decides what the compiler builds)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.split("\n") if line.strip())
+
+
 def source_digest():
-    """SHA-256 over the sources that define the single-integrand V-Sample
-    kernel and its launch (identifies the kernel build that a stored counter
-    profile belongs to): the kernel template, its per-family instantiations,
-    the shared declarations and the host code that sizes the launch."""
+    """SHA-256 over the code (comments dropped) of the sources that define the
+    single-integrand V-Sample kernel and its launch (identifies the kernel
+    build that a stored counter profile belongs to): the kernel template, its
+    per-family instantiations, the shared declarations and the host code that
+    sizes the launch."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2302_05730_amd", "csrc")
     h = hashlib.sha256()
     for name in sorted(os.listdir(csrc)):
         if (name in ("vsample_impl.h", "mcubes_internal.h", "mcubes_api.hip")
                 or (name.startswith("vsample_f") and name.endswith(".hip"))):
-            with open(os.path.join(csrc, name), "rb") as fh:
-                h.update(name.encode() + b"\0" + fh.read())
+            with open(os.path.join(csrc, name), encoding="utf-8") as fh:
+                h.update(name.encode() + b"\0" + _code_only(fh.read()).encode())
     return h.hexdigest()
 
 

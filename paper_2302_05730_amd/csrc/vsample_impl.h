@@ -13,10 +13,11 @@
 // which needs no division in the loop.  The results depend only on the cube
 // id, never on the launch geometry.
 //
-// Per block, the grid of all axes is staged once into LDS as (edge, width)
-// pairs (one 16-byte LDS read per axis and sample), and the bin contributions go into an
-// LDS-private FP64 histogram (ds_add_f64), flushed at the end with one
-// global FP64 atomic per non-empty bin.  Per-thread sums of the cube sums and
+// A sample reads the bin's left edge and width on every axis, from tables
+// split between LDS (staged once per block) and the global grid row through
+// the vector L1 cache (see VsLds and table_from_l1), and adds its bin
+// contributions to an LDS-private FP64 histogram (ds_add_f64), flushed at
+// the end with one global FP64 atomic per non-empty bin.  Per-thread sums of the cube sums and
 // cube variances are reduced across the wave with shuffles, across the
 // block in LDS, and written as one partial per block; a separate kernel adds
 // the partials in a fixed order.

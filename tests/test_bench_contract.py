@@ -32,6 +32,16 @@ def test_stored_profiles_follow_the_kernel_sources(monkeypatch):
     assert bench.stored_valu_busy() is None
 
 
+def test_digest_sees_code_not_comments():
+    """The digest that ties a stored profile to the kernel sources ignores
+    comments and blank lines, and nothing else."""
+    code = "int f(int a) {\n    return a + 1;  // one more\n}\n"
+    assert bench._code_only(code) == bench._code_only(
+        "/* helper */\nint f(int a) {\n\n    return a + 1;\n}\n// end\n")
+    assert bench._code_only(code) != bench._code_only(code.replace("a + 1", "a + 2"))
+    assert bench._code_only("x = 1; /* a\n b */ y = 2;") == "x = 1;  y = 2;"
+
+
 def test_fp64_work_per_sample():
     # 9 d + 7 + F_f: 8-D Gaussian 72 + 7 + (32 + exp) = 112, oscillatory
     # 72 + 7 + (16 + 2 + cos) = 98, corner peak 72 + 7 + (16 + 1 + 8 + 1) = 105
