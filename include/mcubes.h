@@ -630,9 +630,11 @@ int mcubes_flow_weight_tail(mcubes_flow *flow, double *shape, int64_t *tail_coun
  * combined result of the iterations that decide it (flow, or plain on
  * fallback).  Synchronous; allocates its buffers.
  * The flow's weights have a long tail where it is thinner than f (regions
- * of f that training has barely sampled): on the 6-D correlated mixture
- * the defaults leave the estimate within a few 1e-4, more often low than
- * high, with an error estimate that is often a few times too small. */
+ * of f that training has barely sampled).  On the 6-D correlated mixture at
+ * 2^26 samples per iteration the defaults give a median error of about
+ * 1e-5 with 42 of 46 seeds within two stated errors; a run that happens to
+ * draw none of the rare large weights comes out low by 3-4 of its stated
+ * errors (2 of those 46). */
 typedef struct {
     int32_t warmup_iters;  /* default 8 */
     int32_t precision;     /* proposal iterations: MCUBES_BF16 (default) or MCUBES_FP32 */
