@@ -278,7 +278,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 //   FP64 form: bin sums of every axis, and the edges E_i and widths W_i of the
 //   staged axes (with bin sums, axes 0, 4, 8, the others reading (E_i, E_i+1)
 //   from the global grid through the vector L1 cache; without bin sums, and
-//   for d = 1, every axis).
+//   for d = 1, every axis).  With bin sums (d >= 2) a staged axis keeps
+//   (E_i, W_i) side by side in a row of twice the width, read as one 16-byte
+//   pair at twice the bin offset (the E and W regions together hold these
+//   rows); otherwise E and W are separate rows.
 //   FP32 form: bin sums, and (E_i, W_i) as a pair of floats for every axis.
 template <int D, bool BINS, bool F32>
 struct VsLds {
@@ -370,6 +373,14 @@ __device__ __forceinline__ double draw(const VsArgs &A, uint32_t iteration, cons
                     const double2 e = *reinterpret_cast<const double2 *>(row[j] + o8[j]);
                     e0[q] = e.x;
                     e1[q] = e.y;
+                } else if constexpr (BINS && D >= 2) {
+                    // (E_i, W_i) side by side: one 16-byte LDS read at twice the
+                    // bin offset
+                    const int l = staged_axis<D, BINS>(j);
+                    const double2 ew = *reinterpret_cast<const double2 *>(
+                        lds + L::kE + 2 * l * L::kRow + (o8[j] << 1));
+                    e0[q] = ew.x;
+                    e1[q] = ew.y;
                 } else {
                     const int l = staged_axis<D, BINS>(j);
                     e0[q] = *reinterpret_cast<const double *>(lds + L::kE + l * L::kRow + o8[j]);
@@ -506,8 +517,13 @@ __device__ __forceinline__ void vs_block(const VsArgs &A, const double *__restri
                 make_float2((float)e0, (float)(e1 - e0));
         } else if (!table_from_l1<D, BINS>(j)) {
             const int l = staged_axis<D, BINS>(j);
-            *reinterpret_cast<double *>(lds + L::kE + l * L::kRow + 8 * i) = e0;
-            *reinterpret_cast<double *>(lds + L::kW + l * L::kRow + 8 * i) = e1 - e0;
+            if constexpr (BINS && D >= 2) {
+                *reinterpret_cast<double2 *>(lds + L::kE + 2 * l * L::kRow + 16 * i) =
+                    make_double2(e0, e1 - e0);
+            } else {
+                *reinterpret_cast<double *>(lds + L::kE + l * L::kRow + 8 * i) = e0;
+                *reinterpret_cast<double *>(lds + L::kW + l * L::kRow + 8 * i) = e1 - e0;
+            }
         }
         if constexpr (BINS) *reinterpret_cast<double *>(lds + L::kH + j * L::kRow + 8 * i) = 0.0;
     }
