@@ -28,6 +28,7 @@
 // to the plain definition.
 #pragma once
 
+#include "cos_reduced.h"
 #include "mcubes_internal.h"
 
 namespace mcubes {
@@ -79,7 +80,9 @@ struct Family<MCUBES_OSCILLATORY, D> {  // cos(2 pi u_0 + sum a_i x_i)
     static __device__ __forceinline__ void axis(Acc &a, double ca, double, double x) {
         a.s = __fma_rn(ca, x, a.s);
     }
-    static __device__ __forceinline__ double end(const Acc &a, const VsArgs &) { return cos(a.s); }
+    static __device__ __forceinline__ double end(const Acc &a, const VsArgs &) {
+        return cos_reduced(a.s);
+    }
 };
 
 template <int D>
