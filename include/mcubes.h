@@ -630,11 +630,10 @@ int mcubes_flow_weight_tail(mcubes_flow *flow, double *shape, int64_t *tail_coun
  * combined result of the iterations that decide it (flow, or plain on
  * fallback).  Synchronous; allocates its buffers.
  * The flow's weights have a long tail where it is thinner than f (regions
- * of f that training has barely sampled).  On the 6-D correlated mixture at
- * 2^26 samples per iteration the defaults give a median error of about
- * 1e-5 with 42 of 46 seeds within two stated errors; a run that happens to
- * draw none of the rare large weights comes out low by 3-4 of its stated
- * errors (2 of those 46). */
+ * of f that training has barely sampled); the tail rounds exist to lighten
+ * it.  On the 6-D correlated mixture the defaults gave, at 2^26 samples per
+ * iteration, a median error of 2.1e-5 with 17 of 20 seeds within two stated
+ * errors and all 20 within three; at 2^22, 24 of 24 runs within two. */
 typedef struct {
     int32_t warmup_iters;  /* default 8 */
     int32_t precision;     /* proposal iterations: MCUBES_BF16 (default) or MCUBES_FP32 */
@@ -647,7 +646,7 @@ typedef struct {
     int64_t batch;         /* default 65536 */
     double lr;             /* default 4e-3 */
     double round_lr;       /* default 2e-3 */
-    double tail_power;     /* default 1.5 */
+    double tail_power;     /* default 1.75 */
     double tail_lr;        /* default 8e-4 */
     int32_t train_precision; /* training products: MCUBES_BF16 (default) or MCUBES_FP32 */
     int32_t anchor_rounds; /* default 2: how many of the first `rounds` also train on

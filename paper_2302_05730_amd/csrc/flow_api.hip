@@ -492,7 +492,7 @@ void mcubes_default_flow_options(mcubes_flow_options *o) {
     o->batch = 65536;
     o->lr = 4e-3;
     o->round_lr = 2e-3;
-    o->tail_power = 1.5;
+    o->tail_power = 1.75;
     o->tail_lr = 8e-4;
     o->train_precision = MCUBES_BF16;
     o->anchor_rounds = 2;

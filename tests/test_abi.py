@@ -231,6 +231,6 @@ def test_default_flow_options():
     assert (fo.warmup_iters, fo.train_items, fo.epochs, fo.rounds, fo.round_samples,
             fo.round_epochs, fo.tail_rounds, fo.batch) == (8, 1 << 20, 10, 4, 1 << 25, 2, 4,
                                                            65536)
-    assert (fo.lr, fo.round_lr, fo.tail_power, fo.tail_lr) == (4e-3, 2e-3, 1.5, 8e-4)
+    assert (fo.lr, fo.round_lr, fo.tail_power, fo.tail_lr) == (4e-3, 2e-3, 1.75, 8e-4)
     assert fo.precision == mc.MCUBES_BF16 and fo.train_precision == mc.MCUBES_BF16
     assert fo.anchor_rounds == 2 and fo.min_iters == 4
