@@ -530,7 +530,7 @@ def test_flow_pipeline_beats_plain_mcubes_on_the_mixture(mc):
     the BF16 matrix cores and in FP32, land at least ten times closer, with
     a per-iteration variance typically ten thousand times below the plain
     method's.  Whether the error bars cover the integral is a statement
-    over seeds (test_flow_pipeline_error_bars_cover_the_integral)."""
+    over seeds (tests/test_zy_flow_coverage.py)."""
     pr = workloads.mixture_6d(ncall=1 << 22)
     for prec in (mc.MCUBES_BF16, mc.MCUBES_FP32):
         fl = mc.Flow(workloads.flow_init(7))
@@ -549,37 +549,6 @@ def test_flow_pipeline_beats_plain_mcubes_on_the_mixture(mc):
         # typically 1e4 times lower; one of the rare weights of 1e4 adds
         # (1e4 / 2^22)^2 ~ 6e-6 to a single iteration's variance
         assert rep["first_flow_var"] < rep["last_plain_var"] / 10
-
-
-def test_flow_pipeline_error_bars_cover_the_integral(mc):
-    """Coverage over seeds, the error model of m-Cubes (the error is the
-    standard deviation of the estimate): eight pipelines with the default
-    recipe on the mixture at 2^22 samples per iteration, run to a relative
-    error of 1e-3 (at least four flow iterations).  A correct error bar
-    covers the integral within 2 sigma about 95% of the time and within
-    3 sigma almost always; asked here: at least 7 of 8 within 2 sigma, all
-    8 within 3 sigma, and every estimate within 2e-3.  Runs the pipeline
-    refuses to call converged (heavy weight tail with disagreeing
-    iterations) still count: their error bars must cover too."""
-    pr = workloads.mixture_6d(ncall=1 << 22)
-    pulls, devs = [], []
-    for seed in range(101, 109):
-        fl = mc.Flow(workloads.flow_init(7))
-        res, rep = fl.integrate(pr.family, pr.params, pr.ncall, 50, 1e-3, seed,
-                                mc.mcubes_default_options(nbins=500))
-        dev = res["estimate"] - 1.0
-        pull = dev / res["error"]
-        _say(f"seed {seed}: {res['estimate']:.6f} +- {res['error']:.2e} (pull {pull:+.2f}), "
-             f"{res['iterations']} flow iterations, chi2/dof {res['chi2_dof']:.2f}, "
-             f"tail {rep['tail_shape']:.3f}, converged {res['converged']}, "
-             f"used {rep['used_flow']}")
-        assert rep["used_flow"] == 1 and res["iterations"] >= 4
-        pulls.append(pull)
-        devs.append(abs(dev))
-    pulls = np.abs(np.array(pulls))
-    assert np.sum(pulls <= 2.0) >= 7, pulls
-    assert np.all(pulls <= 3.0), pulls
-    assert max(devs) <= 2e-3, devs
 
 
 def test_pipeline_falls_back_to_plain_when_the_flow_loses(mc):
