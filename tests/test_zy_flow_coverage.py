@@ -28,17 +28,27 @@ def _say(*a):
 
 def test_flow_pipeline_error_bars_cover_the_integral(mc):
     """Coverage over seeds, the error model of m-Cubes (the error is the
-    standard deviation of the estimate): eight pipelines with the default
+    standard deviation of the estimate): sixteen pipelines with the default
     recipe on the mixture at 2^22 samples per iteration, run to a relative
-    error of 1e-3 (at least four flow iterations).  A correct error bar
-    covers the integral within 2 sigma about 95% of the time and within
-    3 sigma almost always; asked here: at least 7 of 8 within 2 sigma, all
-    8 within 3 sigma, and every estimate within 2e-3.  Runs the pipeline
-    refuses to call converged (heavy weight tail with disagreeing
+    error of 1e-3 (at least four flow iterations).  The same seed trains a
+    different flow on every run (the FP64 histogram atomics of the warm-up
+    add in hardware order), so the sixteen pulls are independent draws and
+    the criterion is a statistical one, set by the binomial distribution:
+      * asked: at least 12 of 16 within 2 sigma, at most one beyond 3 sigma,
+        and every estimate within 2e-3 of the integral;
+      * an exactly Gaussian error (95.4% within 2 sigma, 99.73% within 3)
+        fails this with probability 0.14%; the measured coverage of the
+        default recipe at this size (about 90% and 99%: the weights' heavy
+        tail leaves the median run slightly low) fails it with about 3%;
+        error bars 2 times too small fail it with 86%, 1.5 times too small
+        with 29%.
+    (Eight seeds with 7 of 8 within 2 sigma and all within 3 fail an exactly
+    Gaussian error 6.9% of the time, and this recipe 25%.)  Runs the
+    pipeline refuses to call converged (heavy weight tail with disagreeing
     iterations) still count: their error bars must cover too."""
     pr = workloads.mixture_6d(ncall=1 << 22)
     pulls, devs = [], []
-    for seed in range(101, 109):
+    for seed in range(101, 117):
         fl = mc.Flow(workloads.flow_init(7))
         res, rep = fl.integrate(pr.family, pr.params, pr.ncall, 50, 1e-3, seed,
                                 mc.mcubes_default_options(nbins=500))
@@ -52,6 +62,6 @@ def test_flow_pipeline_error_bars_cover_the_integral(mc):
         pulls.append(pull)
         devs.append(abs(dev))
     pulls = np.abs(np.array(pulls))
-    assert np.sum(pulls <= 2.0) >= 7, pulls
-    assert np.all(pulls <= 3.0), pulls
+    assert np.sum(pulls <= 2.0) >= 12, pulls
+    assert np.sum(pulls > 3.0) <= 1, pulls
     assert max(devs) <= 2e-3, devs
