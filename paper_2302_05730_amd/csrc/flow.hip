@@ -417,19 +417,7 @@ __global__ void wgrad_sum_kernel(const float *__restrict__ part, int slices,
                                  float *__restrict__ grad) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= PARAMS) return;
-    // slice order; sixteen loads in flight before their adds (about one wave
-    // per SIMD here, so the loads, not the adds, set the time)
-    float a = 0.0f;
-    int k = 0;
-    for (; k + 16 <= slices; k += 16) {
-        float v[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) v[q] = part[(int64_t)(k + q) * PARAMS + i];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) a += v[q];
-    }
-    for (; k < slices; ++k) a += part[(int64_t)k * PARAMS + i];
-    grad[i] = a;
+    grad[i] = slice_sum(part, slices, i);
 }
 
 // one workgroup per minibatch: the sum of its weights (fixed order)
@@ -526,12 +514,7 @@ __global__ void adam_kernel(float *__restrict__ theta, float *__restrict__ m,
                             float lr, float beta1, float beta2, float eps, float c1, float c2) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    const float g = grad[i];
-    const float mi = beta1 * m[i] + (1.0f - beta1) * g;
-    const float vi = beta2 * v[i] + (1.0f - beta2) * g * g;
-    m[i] = mi;
-    v[i] = vi;
-    theta[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    adam_update(theta, m, v, i, grad[i], lr, beta1, beta2, eps, c1, c2);
 }
 
 // The flow as the map of an m-Cubes iteration: cube c's sample k draws u

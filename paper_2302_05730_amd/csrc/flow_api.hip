@@ -18,6 +18,7 @@ struct mcubes_flow {
     void *d_frags = nullptr;           // BF16 weight fragments for the matrix-core path
     void *d_bfrags = nullptr;          // BF16 fragments of the backward products
     float *d_fbias = nullptr;          // biases in accumulator order
+    int *d_inv = nullptr;              // where each parameter sits in the three packed forms
     bool packed = false;               // fragments up to date with d_theta
     double *d_aux = nullptr;           // [0] sum of weights, [1] loss
     double *d_part = nullptr;          // per-block partials of the flow-mapped iteration
@@ -71,6 +72,7 @@ void release(mcubes_flow *F) {
     (void)hipFree(F->d_frags);
     (void)hipFree(F->d_bfrags);
     (void)hipFree(F->d_fbias);
+    (void)hipFree(F->d_inv);
     (void)hipFree(F->d_aux);
     (void)hipFree(F->d_part);
     (void)hipFree(F->d_whist);
@@ -120,10 +122,12 @@ int ensure_scratch(mcubes_flow *F, int64_t n) {
     return MCUBES_OK;
 }
 
-// One step's forward/backward pass and weight gradients (loss += its value).
-// wsum: the sum of the n weights on the device, or NULL to form it first.
-hipError_t train_step(mcubes_flow *F, int precision, const double *d_x, const double *d_w,
-                      int64_t n, const double *wsum, double *d_loss, hipStream_t s) {
+// One step's forward/backward pass (loss += its value).  wsum: the sum of
+// the n weights on the device, or NULL to form it first.  BF16: `pack`
+// repacks the fragments from theta first; without it they must already hold
+// theta (as the fused gradient and Adam launch leaves them).
+hipError_t train_pass(mcubes_flow *F, int precision, const double *d_x, const double *d_w,
+                      int64_t n, const double *wsum, double *d_loss, bool pack, hipStream_t s) {
     hipError_t e = hipSuccess;
     if (!wsum) {
         e = launch_flow_wsum(d_w, n, F->d_aux, s);
@@ -131,11 +135,16 @@ hipError_t train_step(mcubes_flow *F, int precision, const double *d_x, const do
     }
     if (e != hipSuccess) return e;
     if (precision == MCUBES_BF16)
-        e = launch_flow_train_bf16(F->d_theta, F->d_frags, F->d_bfrags, F->d_fbias, d_x, d_w, n,
-                                   wsum, F->d_scratch, d_loss, F->cus, s);
-    else
-        e = launch_flow_train_fp32(F->d_theta, F->d_thetaT, d_x, d_w, n, wsum, F->d_scratch,
-                                   d_loss, s);
+        return launch_flow_train_bf16(F->d_theta, F->d_frags, F->d_bfrags, F->d_fbias, d_x, d_w,
+                                      n, wsum, F->d_scratch, d_loss, F->cus, pack, s);
+    return launch_flow_train_fp32(F->d_theta, F->d_thetaT, d_x, d_w, n, wsum, F->d_scratch, d_loss,
+                                  s);
+}
+
+// The pass and the weight gradients (in F->d_grad).
+hipError_t train_step(mcubes_flow *F, int precision, const double *d_x, const double *d_w,
+                      int64_t n, const double *wsum, double *d_loss, hipStream_t s) {
+    const hipError_t e = train_pass(F, precision, d_x, d_w, n, wsum, d_loss, true, s);
     if (e != hipSuccess) return e;
     return precision == MCUBES_BF16 ? launch_flow_wgrad_bf16(F->d_scratch, n, F->d_grad, s)
                                     : launch_flow_wgrad(F->d_scratch, n, F->d_grad, s);
@@ -196,6 +205,11 @@ int mcubes_flow_create(const double *theta, mcubes_flow **out) {
     if (e == hipSuccess) e = hipMalloc(&F->d_bfrags, (size_t)flow_bf16_bwd_frag_bytes());
     if (e == hipSuccess)
         e = hipMalloc((void **)&F->d_fbias, (size_t)flow_bf16_bias_floats() * sizeof(float));
+    const size_t ib = (size_t)flow_bf16_inverse_map_ints() * sizeof(int);
+    if (e == hipSuccess) e = hipMalloc((void **)&F->d_inv, ib);
+    if (e == hipSuccess) e = hipMemset(F->d_inv, 0xff, ib);  // -1: no slot
+    if (e == hipSuccess) e = launch_flow_inverse_map(F->d_inv, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e == hipSuccess) e = hipMalloc((void **)&F->d_aux, 2 * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&F->d_part, 2 * kVsBlocks * sizeof(double));
     if (e == hipSuccess)
@@ -316,19 +330,31 @@ int mcubes_flow_train(mcubes_flow *F, int precision, const double *d_x, const do
     }
     hipError_t ew = launch_flow_batch_wsums(d_w, n, batch, F->d_wsums, s);
     if (ew != hipSuccess) return hip_fail(ew, "minibatch weight sums");
+    bool first = true;
     for (int ep = 0; ep < epochs; ++ep) {
         hipError_t e = hipMemsetAsync(d_loss, 0, sizeof(double), s);
         int nbatch = 0;
         for (int64_t b0 = 0; b0 < n && e == hipSuccess; b0 += batch) {
             const int64_t nb = n - b0 < batch ? n - b0 : batch;
-            e = train_step(F, precision, d_x + b0 * flow::D, d_w + b0, nb, F->d_wsums + b0 / batch,
-                           d_loss, s);
-            if (e == hipSuccess) {
-                F->step += 1;
-                const double c1 = 1.0 - pow(0.9, (double)F->step);
-                const double c2 = 1.0 - pow(0.999, (double)F->step);
-                e = launch_flow_adam(F->d_theta, F->d_m, F->d_v, F->d_grad, (float)lr, 0.9f,
-                                     0.999f, 1e-8f, (float)c1, (float)c2, s);
+            // BF16: the step's last launch updates the fragments with theta,
+            // so only the call's first pass packs them
+            e = train_pass(F, precision, d_x + b0 * flow::D, d_w + b0, nb, F->d_wsums + b0 / batch,
+                           d_loss, first, s);
+            first = false;
+            if (e != hipSuccess) break;
+            F->step += 1;
+            const double c1 = 1.0 - pow(0.9, (double)F->step);
+            const double c2 = 1.0 - pow(0.999, (double)F->step);
+            if (precision == MCUBES_BF16) {
+                e = launch_flow_wgrad_adam_bf16(F->d_scratch, nb, F->d_theta, F->d_m, F->d_v,
+                                                F->d_grad, (float)lr, 0.9f, 0.999f, 1e-8f,
+                                                (float)c1, (float)c2, F->d_inv, F->d_frags,
+                                                F->d_bfrags, F->d_fbias, s);
+            } else {
+                e = launch_flow_wgrad(F->d_scratch, nb, F->d_grad, s);
+                if (e == hipSuccess)
+                    e = launch_flow_adam(F->d_theta, F->d_m, F->d_v, F->d_grad, (float)lr, 0.9f,
+                                         0.999f, 1e-8f, (float)c1, (float)c2, s);
             }
             ++nbatch;
         }

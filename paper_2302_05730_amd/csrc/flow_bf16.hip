@@ -86,42 +86,56 @@ __device__ __forceinline__ void blob8(float u, int k0, float e[8]) {
     }
 }
 
-// One thread per (layer, fragment, lane): the 8 BF16 weights lane `lane`
-// feeds to the matrix core, and the biases in accumulator order.
+// Where the parameters sit in the packed forms (indices into theta over all
+// layers; -1 for padding).  Bias entry gid (< L BIAS) of the accumulator-
+// order bias array:
+__device__ __forceinline__ int bias_param(int gid) {
+    const int l = gid / BIAS, q = gid % BIAS;
+    int off, n, t;
+    if (q < BOFF_2) {
+        off = OFF_B1; n = HID; t = q / 32;
+    } else if (q < BOFF_3) {
+        off = OFF_B2; n = HID; t = (q - BOFF_2) / 32;
+    } else {
+        off = OFF_B3; n = OUT; t = (q - BOFF_3) / 32;
+    }
+    const int w = q % 32, h = w / 16, r = w % 16;
+    const int f = acc_feature(t, r, h);
+    return f < n ? l * LP + off + f : -1;
+}
+
+// element e of forward fragment slot gid = (layer, fragment, lane): the 8
+// BF16 weights lane `lane` feeds to the matrix core
+__device__ __forceinline__ int fwd_param(int gid, int e) {
+    const int lane = gid % 64, fr = (gid / 64) % FRAGS, l = gid / (64 * FRAGS);
+    const int row = lane % 32, h = lane / 32;
+    if (fr < OFF_G2) {  // first product: natural K order over the 96 one-blob inputs
+        const int t = fr / G1K, ks = fr % G1K;
+        return l * LP + OFF_W1 + (16 * ks + 8 * h + e) * HID + 32 * t + row;
+    }
+    // second and third: K order of the previous accumulator registers
+    const bool third = fr >= OFF_G3;
+    const int q = fr - (third ? OFF_G3 : OFF_G2);
+    const int t = q / 4, ks = q % 4;
+    const int o = 32 * t + row;
+    const int k = acc_feature(ks / 2, 8 * (ks % 2) + e, h);
+    if (third) return o < OUT ? l * LP + OFF_W3 + k * OUT + o : -1;
+    return l * LP + OFF_W2 + k * HID + o;
+}
+
+// One thread per (layer, fragment, lane): its 8 BF16 weights, and the biases
+// in accumulator order.
 __device__ __forceinline__ void pack_fwd(int gid, const float *__restrict__ theta,
                                          bf16x8 *__restrict__ frags, float *__restrict__ bias) {
     if (gid < L * BIAS) {
-        const int l = gid / BIAS, q = gid % BIAS;
-        const float *P = theta + l * LP;
-        int off, n, t;
-        if (q < BOFF_2) {
-            off = OFF_B1; n = HID; t = q / 32;
-        } else if (q < BOFF_3) {
-            off = OFF_B2; n = HID; t = (q - BOFF_2) / 32;
-        } else {
-            off = OFF_B3; n = OUT; t = (q - BOFF_3) / 32;
-        }
-        const int w = q % 32, h = w / 16, r = w % 16;
-        const int f = acc_feature(t, r, h);
-        bias[gid] = f < n ? P[off + f] : 0.0f;
+        const int p = bias_param(gid);
+        bias[gid] = p >= 0 ? theta[p] : 0.0f;
     }
     if (gid >= L * FRAGS * 64) return;
-    const int lane = gid % 64, fr = (gid / 64) % FRAGS, l = gid / (64 * FRAGS);
-    const float *P = theta + l * LP;
-    const int row = lane % 32, h = lane / 32;
     float v[8];
-    if (fr < OFF_G2) {  // first product: natural K order over the 96 one-blob inputs
-        const int t = fr / G1K, ks = fr % G1K;
-        for (int e = 0; e < 8; ++e) v[e] = P[OFF_W1 + (16 * ks + 8 * h + e) * HID + 32 * t + row];
-    } else {  // second and third: K order of the previous accumulator registers
-        const bool third = fr >= OFF_G3;
-        const int q = fr - (third ? OFF_G3 : OFF_G2);
-        const int t = q / 4, ks = q % 4;
-        const int o = 32 * t + row;
-        for (int e = 0; e < 8; ++e) {
-            const int k = acc_feature(ks / 2, 8 * (ks % 2) + e, h);
-            v[e] = third ? (o < OUT ? P[OFF_W3 + k * OUT + o] : 0.0f) : P[OFF_W2 + k * HID + o];
-        }
+    for (int e = 0; e < 8; ++e) {
+        const int p = fwd_param(gid, e);
+        v[e] = p >= 0 ? theta[p] : 0.0f;
     }
     frags[gid] = pack8(v);
 }
@@ -391,29 +405,81 @@ constexpr int B3T = 2, B3K = 7, B2T = 2, B2K = 4, B1T = 3, B1K = 4;
 constexpr int OFF_B3F = 0, OFF_B2F = OFF_B3F + B3T * B3K, OFF_B1F = OFF_B2F + B2T * B2K;
 constexpr int BFRAGS = OFF_B1F + B1T * B1K;  // 34
 
+// element e of backward fragment slot gid = (layer, fragment, lane)
+__device__ __forceinline__ int bwd_param(int gid, int e) {
+    const int lane = gid % 64, fr = (gid / 64) % BFRAGS, l = gid / (64 * BFRAGS);
+    const int row = lane % 32, h = lane / 32;
+    if (fr < OFF_B2F) {
+        const int t = fr / B3K, ks = fr % B3K, i = 32 * t + row;
+        const int k = 16 * ks + 8 * h + e;
+        return k < OUT ? l * LP + OFF_W3 + i * OUT + k : -1;
+    }
+    if (fr < OFF_B1F) {
+        const int q = fr - OFF_B2F, t = q / B2K, ks = q % B2K, i = 32 * t + row;
+        return l * LP + OFF_W2 + i * HID + acc_feature(ks / 2, 8 * (ks % 2) + e, h);
+    }
+    const int q = fr - OFF_B1F, t = q / B1K, ks = q % B1K, r = 32 * t + row;
+    return l * LP + OFF_W1 + r * HID + acc_feature(ks / 2, 8 * (ks % 2) + e, h);
+}
+
 __device__ __forceinline__ void pack_bwd(int gid, const float *__restrict__ theta,
                                          bf16x8 *__restrict__ frags) {
     if (gid >= L * BFRAGS * 64) return;
-    const int lane = gid % 64, fr = (gid / 64) % BFRAGS, l = gid / (64 * BFRAGS);
-    const float *P = theta + l * LP;
-    const int row = lane % 32, h = lane / 32;
     float v[8];
-    if (fr < OFF_B2F) {
-        const int t = fr / B3K, ks = fr % B3K, i = 32 * t + row;
-        for (int e = 0; e < 8; ++e) {
-            const int k = 16 * ks + 8 * h + e;
-            v[e] = k < OUT ? P[OFF_W3 + i * OUT + k] : 0.0f;
-        }
-    } else if (fr < OFF_B1F) {
-        const int q = fr - OFF_B2F, t = q / B2K, ks = q % B2K, i = 32 * t + row;
-        for (int e = 0; e < 8; ++e)
-            v[e] = P[OFF_W2 + i * HID + acc_feature(ks / 2, 8 * (ks % 2) + e, h)];
-    } else {
-        const int q = fr - OFF_B1F, t = q / B1K, ks = q % B1K, r = 32 * t + row;
-        for (int e = 0; e < 8; ++e)
-            v[e] = P[OFF_W1 + r * HID + acc_feature(ks / 2, 8 * (ks % 2) + e, h)];
+    for (int e = 0; e < 8; ++e) {
+        const int p = bwd_param(gid, e);
+        v[e] = p >= 0 ? theta[p] : 0.0f;
     }
     frags[gid] = pack8(v);
+}
+
+// The inverse of the three maps: inv[3 p], inv[3 p + 1], inv[3 p + 2] = the
+// BF16 element of the forward fragments, of the backward fragments and the
+// bias entry that hold parameter p (-1 where none; the caller fills inv with
+// -1 first).  Every weight sits in exactly one forward and one backward
+// element, every bias in one bias entry, so the three are well defined.
+__global__ void inverse_map_kernel(int *__restrict__ inv) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nf = L * FRAGS * 64, nb = L * BFRAGS * 64;
+    if (gid < nf) {
+        for (int e = 0; e < 8; ++e) {
+            const int p = fwd_param(gid, e);
+            if (p >= 0) inv[3 * p] = 8 * gid + e;
+        }
+    } else if (gid < nf + nb) {
+        const int g = gid - nf;
+        for (int e = 0; e < 8; ++e) {
+            const int p = bwd_param(g, e);
+            if (p >= 0) inv[3 * p + 1] = 8 * g + e;
+        }
+    }
+    if (gid < L * BIAS) {
+        const int p = bias_param(gid);
+        if (p >= 0) inv[3 * p + 2] = gid;
+    }
+}
+
+// The end of a BF16 training step in one launch: the gradient's slice sum
+// (as wgrad_sum_kernel), the Adam step (as adam_kernel), and the new
+// parameter written through the inverse map into both fragment sets and the
+// bias array, the values pack_train_kernel would write from the new theta.
+// The next step's training pass then starts without repacking.
+__global__ void sum_adam_pack_kernel(const float *__restrict__ part, int slices,
+                                     float *__restrict__ theta, float *__restrict__ m,
+                                     float *__restrict__ v, float *__restrict__ grad, float lr,
+                                     float beta1, float beta2, float eps, float c1, float c2,
+                                     const int *__restrict__ inv, uint16_t *__restrict__ frags,
+                                     uint16_t *__restrict__ bfrags, float *__restrict__ bias) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= PARAMS) return;
+    const float g = slice_sum(part, slices, i);
+    grad[i] = g;
+    const float t = adam_update(theta, m, v, i, g, lr, beta1, beta2, eps, c1, c2);
+    const int pf = inv[3 * i], pb = inv[3 * i + 1], pz = inv[3 * i + 2];
+    const uint16_t bits = bf16_bits(t);
+    if (pf >= 0) frags[pf] = bits;
+    if (pb >= 0) bfrags[pb] = bits;
+    if (pz >= 0) bias[pz] = t;
 }
 
 // forward and backward fragments (and biases) in one launch: threads
@@ -1018,11 +1084,14 @@ int64_t flow_bf16_train_extra_floats(int64_t n) { return (int64_t)L * BF_EXTRA *
 
 hipError_t launch_flow_train_bf16(const float *theta, void *frags, void *bfrags, float *bias,
                                   const double *x, const double *w, int64_t n, const double *wsum,
-                                  float *scratch, double *loss, int cus, hipStream_t s) {
-    // the forward part covers the bias entries too (L BIAS < L FRAGS 64)
-    const int nf = L * FRAGS * 64, nb = L * BFRAGS * 64;
-    hipLaunchKernelGGL(pack_train_kernel, dim3((nf + nb + 255) / 256), dim3(256), 0, s, theta,
-                       (bf16x8 *)frags, bias, (bf16x8 *)bfrags, nf);
+                                  float *scratch, double *loss, int cus, bool pack,
+                                  hipStream_t s) {
+    if (pack) {
+        // the forward part covers the bias entries too (L BIAS < L FRAGS 64)
+        const int nf = L * FRAGS * 64, nb = L * BFRAGS * 64;
+        hipLaunchKernelGGL(pack_train_kernel, dim3((nf + nb + 255) / 256), dim3(256), 0, s, theta,
+                           (bf16x8 *)frags, bias, (bf16x8 *)bfrags, nf);
+    }
     // one workgroup of TR_WAVES waves per TR_WAVES x 64 samples, at most one
     // per CU (a wave fills a SIMD's registers)
     int64_t blocks = (n + TR_WAVES * 64 - 1) / (TR_WAVES * 64);
@@ -1035,21 +1104,60 @@ hipError_t launch_flow_train_bf16(const float *theta, void *frags, void *bfrags,
     return hipGetLastError();
 }
 
-hipError_t launch_flow_wgrad_bf16(const float *scratch_in, int64_t n, float *grad,
-                                  hipStream_t s) {
-    float *scratch = const_cast<float *>(scratch_in);
-    // slices of at least 512 samples (a multiple of 16), at most kWgradSlices
+namespace {
+
+// slices of at least 512 samples (a multiple of 16), at most kWgradSlices;
+// returns their number and their length in *ks
+int wgrad_bf16_slices(int64_t n, int64_t *ks) {
     int64_t slices = (n + 511) / 512;
     if (slices > kWgradSlices) slices = kWgradSlices;
-    int64_t ks = (n + slices - 1) / slices;
-    ks = (ks + 15) / 16 * 16;
-    slices = (n + ks - 1) / ks;
+    int64_t k = (n + slices - 1) / slices;
+    k = (k + 15) / 16 * 16;
+    *ks = k;
+    return (int)((n + k - 1) / k);
+}
+
+// the per-slice partial sums only; returns the slice count in *slices
+hipError_t launch_wgrad_bf16_parts(const float *scratch_in, int64_t n, int *slices,
+                                   hipStream_t s) {
+    float *scratch = const_cast<float *>(scratch_in);
+    int64_t ks = 0;
+    *slices = wgrad_bf16_slices(n, &ks);
     float *part = scratch + (int64_t)L * FS * n;
-    hipLaunchKernelGGL(wgrad_bf16_kernel, dim3(L * WB_TILES, (unsigned)slices), dim3(64), 0, s,
+    hipLaunchKernelGGL(wgrad_bf16_kernel, dim3(L * WB_TILES, (unsigned)*slices), dim3(64), 0, s,
                        scratch, n, ks, part);
-    const hipError_t e = hipGetLastError();
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_flow_wgrad_bf16(const float *scratch, int64_t n, float *grad,
+                                  hipStream_t s) {
+    int slices = 0;
+    const hipError_t e = launch_wgrad_bf16_parts(scratch, n, &slices, s);
     if (e != hipSuccess) return e;
-    return launch_flow_wgrad_sum(part, (int)slices, grad, s);
+    return launch_flow_wgrad_sum(scratch + (int64_t)L * FS * n, slices, grad, s);
+}
+
+int64_t flow_bf16_inverse_map_ints() { return 3 * (int64_t)PARAMS; }
+
+hipError_t launch_flow_inverse_map(int *inv, hipStream_t s) {
+    const int threads = L * (FRAGS + BFRAGS) * 64;
+    hipLaunchKernelGGL(inverse_map_kernel, dim3((threads + 255) / 256), dim3(256), 0, s, inv);
+    return hipGetLastError();
+}
+
+hipError_t launch_flow_wgrad_adam_bf16(const float *scratch, int64_t n, float *theta, float *m,
+                                       float *v, float *grad, float lr, float beta1, float beta2,
+                                       float eps, float c1, float c2, const int *inv,
+                                       void *frags, void *bfrags, float *bias, hipStream_t s) {
+    int slices = 0;
+    const hipError_t e = launch_wgrad_bf16_parts(scratch, n, &slices, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sum_adam_pack_kernel, dim3((PARAMS + 255) / 256), dim3(256), 0, s,
+                       scratch + (int64_t)L * FS * n, slices, theta, m, v, grad, lr, beta1, beta2,
+                       eps, c1, c2, inv, (uint16_t *)frags, (uint16_t *)bfrags, bias);
+    return hipGetLastError();
 }
 
 template <int F>

@@ -46,6 +46,38 @@ constexpr int FS_D2 = FS_DOUT + OUT, FS_D1 = FS_D2 + HID, FS = FS_D1 + HID;
 // partial sums follow the fields in the scratch buffer)
 constexpr int kWgradSlices = 128;
 
+// Gradient of parameter i: the slices' partial sums part[slice][i] added in
+// slice order (sixteen loads in flight before their adds: with about one
+// wave per SIMD the loads, not the adds, set the time).
+__device__ __forceinline__ float slice_sum(const float *__restrict__ part, int slices, int i) {
+    float a = 0.0f;
+    int k = 0;
+    for (; k + 16 <= slices; k += 16) {
+        float v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = part[(int64_t)(k + q) * PARAMS + i];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) a += v[q];
+    }
+    for (; k < slices; ++k) a += part[(int64_t)k * PARAMS + i];
+    return a;
+}
+
+// One Adam step of parameter i with gradient g on the FP32 master copy;
+// c1 = 1 - beta1^t, c2 = 1 - beta2^t.  Returns the new parameter.
+__device__ __forceinline__ float adam_update(float *__restrict__ theta, float *__restrict__ m,
+                                             float *__restrict__ v, int i, float g, float lr,
+                                             float beta1, float beta2, float eps, float c1,
+                                             float c2) {
+    const float mi = beta1 * m[i] + (1.0f - beta1) * g;
+    const float vi = beta2 * v[i] + (1.0f - beta2) * g * g;
+    m[i] = mi;
+    v[i] = vi;
+    const float t = theta[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    theta[i] = t;
+    return t;
+}
+
 // Histogram of log2 of the flow-mapped weights (the tail diagnostic): bin
 // floor(8 log2 w) + 2048, clamped to [0, 4095]; weights that are not
 // positive (or not numbers) are not counted.  Kept per workgroup in LDS.

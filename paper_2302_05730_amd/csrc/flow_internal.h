@@ -31,19 +31,32 @@ hipError_t launch_pow_weights(double *w, int64_t n, double power, hipStream_t s)
 // backward pass of the weighted NLL (loss += its value, per-sample fields in
 // scratch; FP32 form: thetaT, flow_transposed_floats() floats, is rewritten
 // from theta; BF16 form: the forward and backward fragments are repacked
-// from theta); then the weight gradients from the scratch fields.
+// from theta when `pack`, else taken as they are); then the weight
+// gradients from the scratch fields.
 hipError_t launch_flow_wsum(const double *w, int64_t n, double *wsum, hipStream_t s);
 hipError_t launch_flow_train_fp32(const float *theta, float *thetaT, const double *x,
                                   const double *w, int64_t n, const double *wsum, float *scratch,
                                   double *loss, hipStream_t s);
 hipError_t launch_flow_train_bf16(const float *theta, void *frags, void *bfrags, float *bias,
                                   const double *x, const double *w, int64_t n, const double *wsum,
-                                  float *scratch, double *loss, int cus, hipStream_t s);
+                                  float *scratch, double *loss, int cus, bool pack,
+                                  hipStream_t s);
 hipError_t launch_flow_wgrad(const float *scratch, int64_t n, float *grad, hipStream_t s);
 // the same sums on the matrix cores (BF16 operands, FP32 accumulation)
 hipError_t launch_flow_wgrad_bf16(const float *scratch, int64_t n, float *grad, hipStream_t s);
 // grad[i] <- sum over the slices of part[slice][i], in slice order
 hipError_t launch_flow_wgrad_sum(const float *part, int slices, float *grad, hipStream_t s);
+// The BF16 weight gradients, then grad, the Adam step on theta (m, v) and the
+// new parameters written into frags, bfrags and bias through inv (the
+// inverse map, flow_bf16_inverse_map_ints() ints from launch_flow_inverse_map
+// over a buffer filled with -1): bit for bit launch_flow_wgrad_bf16,
+// launch_flow_adam and a repack, in two launches.
+int64_t flow_bf16_inverse_map_ints();
+hipError_t launch_flow_inverse_map(int *inv, hipStream_t s);
+hipError_t launch_flow_wgrad_adam_bf16(const float *scratch, int64_t n, float *theta, float *m,
+                                       float *v, float *grad, float lr, float beta1, float beta2,
+                                       float eps, float c1, float c2, const int *inv,
+                                       void *frags, void *bfrags, float *bias, hipStream_t s);
 int64_t flow_bf16_bwd_frag_bytes();
 int64_t flow_bf16_train_extra_floats(int64_t n);
 hipError_t launch_flow_adam(float *theta, float *m, float *v, const float *grad, float lr,

@@ -405,6 +405,38 @@ def test_training_reduces_the_loss(mc):
     assert sd1 < sd0 / 1.5 and ess1 > ess0
 
 
+@pytest.mark.parametrize("precision", ["bf16", "fp32"])
+def test_training_call_equals_its_steps(mc, precision):
+    """mcubes_flow_train ends each BF16 step with one launch that sums the
+    slices, takes the Adam step and writes the new parameters straight into
+    the packed fragments (no repack before the next step).  It must leave
+    exactly the parameters of the same minibatches taken one call at a time,
+    mcubes_flow_loss_grad (which repacks) then mcubes_flow_adam_step, bit for
+    bit, over two epochs with a ragged last minibatch."""
+    import torch
+    prec = mc.MCUBES_BF16 if precision == "bf16" else mc.MCUBES_FP32
+    n, batch, epochs, lr = 3 * 8192 + 1000, 8192, 2, 1e-3
+    rng = np.random.default_rng(11)
+    x = _dev(rng.uniform(0.02, 0.98, (n, 6)))
+    w = _dev(rng.uniform(0.1, 3.0, n))
+    theta0 = workloads.flow_random(5, out_scale=0.4)
+    whole = mc.Flow(theta0)
+    whole.train(x.view(-1), w, n, epochs, batch, lr, precision=prec)
+    steps = mc.Flow(theta0)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(epochs):
+        for b0 in range(0, n, batch):
+            nb = min(batch, n - b0)
+            steps.loss_grad(x.view(-1)[6 * b0:6 * (b0 + nb)], w[b0:b0 + nb], nb, None, loss,
+                            precision=prec)
+            steps.adam_step(lr)
+    torch.cuda.synchronize()
+    a = np.asarray(whole.params(), dtype=np.float64)
+    b = np.asarray(steps.params(), dtype=np.float64)
+    assert np.any(a != np.asarray(theta0, dtype=np.float32))
+    assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+
+
 def test_flow_combine_matches_oracle(mc):
     """The equal-weight combination of flow-mapped iterations, fed one
     iteration at a time through the C-ABI, against the oracle on every
