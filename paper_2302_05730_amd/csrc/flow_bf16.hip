@@ -590,9 +590,24 @@ __device__ __forceinline__ uint32_t *relu_bits(float *ext_l, int64_t n64, int64_
 constexpr int TR_WAVES = 4;
 constexpr int TR_SLOT = G3T * G3K + BFRAGS;  // 50 fragments >= FRAGS
 
-__device__ __forceinline__ void stage_frags(bf16x8 *dst, const bf16x8 *__restrict__ src,
-                                            int frags) {
-    for (int i = threadIdx.x; i < frags * 64; i += TR_WAVES * 64) dst[i] = src[i];
+// Copies FR fragments (FR x 64 lanes of 16 bytes) from src to dst, the
+// workgroup's threads striding over them.  Every load is issued before the
+// first LDS write, so the copy waits one memory round trip, not one per
+// stride.
+template <int FR>
+__device__ __forceinline__ void stage_frags(bf16x8 *dst, const bf16x8 *__restrict__ src) {
+    constexpr int N = FR * 64, T = TR_WAVES * 64, PER = (N + T - 1) / T;
+    bf16x8 v[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int i = threadIdx.x + k * T;
+        if (i < N) v[k] = src[i];
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int i = threadIdx.x + k * T;
+        if (i < N) dst[i] = v[k];
+    }
 }
 
 // The BF16 fields leave the pass through a per-wave LDS tile T[f][c] (nf
@@ -672,7 +687,7 @@ __global__ __launch_bounds__(TR_WAVES * 64) void train_bf16_kernel(
                 for (int j = 0; j < D; ++j) sc[(FS_U + j) * n + s] = u[j];
             }
             __syncthreads();  // every wave is done with the previous fragments
-            stage_frags(slot, frags + (size_t)l * FRAGS * 64, FRAGS);
+            stage_frags<FRAGS>(slot, frags + (size_t)l * FRAGS * 64);
             __syncthreads();
             const bf16x8 *Fr = slot + lane;
             const float *Bs = bias + l * BIAS + h * 16;
@@ -773,8 +788,8 @@ __global__ __launch_bounds__(TR_WAVES * 64) void train_bf16_kernel(
                 gprev[j] = g[j];
             }
             __syncthreads();  // every wave is done with the previous fragments
-            stage_frags(slot, frags + ((size_t)l * FRAGS + OFF_G3) * 64, G3T * G3K);
-            stage_frags(slot + G3T * G3K * 64, bfrags + (size_t)l * BFRAGS * 64, BFRAGS);
+            stage_frags<G3T * G3K>(slot, frags + ((size_t)l * FRAGS + OFF_G3) * 64);
+            stage_frags<BFRAGS>(slot + G3T * G3K * 64, bfrags + (size_t)l * BFRAGS * 64);
             __syncthreads();
             // the spline parameters again, from the stored operands
             f32x16 own[2][G3T];
