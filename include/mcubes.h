@@ -632,9 +632,10 @@ int mcubes_flow_weight_tail(mcubes_flow *flow, double *shape, int64_t *tail_coun
  * The flow's weights have a long tail where it is thinner than f (regions
  * of f that training has barely sampled); the tail rounds exist to lighten
  * it.  On the 6-D correlated mixture the defaults gave, at 2^26 samples per
- * iteration, a median error of 1.7e-5 over 60 seeds, 53 of them within two
- * stated errors and 59 within three (the other at 3.3); at 2^22, 36 of 40
- * runs within two and all 40 within three. */
+ * iteration, a median error of 1.7e-5 over 120 seeds, 107 of them within
+ * two stated errors and 118 within three (of the other two, one at 3.3 and
+ * one at 8.0 that came back not converged, its weight-tail shape 0.52); at
+ * 2^22, 36 of 40 runs within two and all 40 within three. */
 typedef struct {
     int32_t warmup_iters;  /* default 8 */
     int32_t precision;     /* proposal iterations: MCUBES_BF16 (default) or MCUBES_FP32 */
