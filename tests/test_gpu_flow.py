@@ -435,6 +435,23 @@ def test_training_call_equals_its_steps(mc, precision):
     b = np.asarray(steps.params(), dtype=np.float64)
     assert np.any(a != np.asarray(theta0, dtype=np.float32))
     assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+    # other calls in between (BF16 sampling packs the forward fragments
+    # itself), then one more epoch each way
+    z = _dev(rng.uniform(0.0, 1.0, (4096, 6)))
+    xs = torch.empty(4096 * 6, dtype=torch.float64, device="cuda")
+    lq = torch.empty(4096, dtype=torch.float64, device="cuda")
+    for fl in (whole, steps):
+        fl.sample(z.view(-1), 4096, xs, lq, precision=mc.MCUBES_BF16)
+    whole.train(x.view(-1), w, n, 1, batch, lr, precision=prec)
+    for b0 in range(0, n, batch):
+        nb = min(batch, n - b0)
+        steps.loss_grad(x.view(-1)[6 * b0:6 * (b0 + nb)], w[b0:b0 + nb], nb, None, loss,
+                        precision=prec)
+        steps.adam_step(lr)
+    torch.cuda.synchronize()
+    a = np.asarray(whole.params(), dtype=np.float64)
+    b = np.asarray(steps.params(), dtype=np.float64)
+    assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
 
 
 def test_flow_combine_matches_oracle(mc):
