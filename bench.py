@@ -459,6 +459,13 @@ def main():
     import paper_2302_05730_amd as mc
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy_mib:
+        n = args.calibrate_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.only_batch:
         print(json.dumps({"batched": bench_batch(mc, args.batch_n or 512, args.batch_iters,
                                                  full=False)}), flush=True)
@@ -467,13 +474,6 @@ def main():
         print(json.dumps({"learned_proposal": bench_flow(mc, args.flow_ncall or (1 << 26))}),
               flush=True)
         return
-    if args.calibrate_copy_mib:
-        n = args.calibrate_copy_mib * (1 << 20) // 8
-        src = torch.ones(n, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
     problems = workloads.large_8d_set(ncall=args.ncall)
     opts = mc.mcubes_default_options(nbins=500, block_size=args.block, blocks=args.blocks)
     plans = [mc.mcubes_plan_create(pr.family, pr.params, pr.dim, pr.ncall, pr.seed, opts)
